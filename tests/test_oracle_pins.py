@@ -1,0 +1,567 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test checks one part of the oracle against something the paper or the
+mathematics fixes: published generator outputs, exact rational arithmetic,
+closed forms, dense linear algebra (numpy/scipy), brute-force characterisations
+and hand-traced cases of Algorithms 2 and 3.  No GPU is used.
+"""
+
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import graphgen as gg
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dense_A(g):
+    A = np.zeros((g.n, g.n))
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    A[rows, g.col] = g.w
+    return A
+
+
+def dense_L(g, d=None):
+    A = dense_A(g)
+    return np.diag(A.sum(1) if d is None else d) - A
+
+
+def sparse_A(g):
+    return sp.csr_matrix((g.w, g.col, g.row_ptr), shape=(g.n, g.n))
+
+
+SMALL_GRAPHS = [
+    lambda: gg.grid2d(9, 7),
+    lambda: gg.grid3d(4, 5, 3, weights="loguniform", seed=11),
+    lambda: gg.gnp(120, 0.05, seed=3),
+    lambda: gg.rmat(8, 8, seed=5),
+    lambda: gg.chung_lu(600, seed=9, max_deg=80),
+    lambda: gg.star(12),
+    lambda: gg.path(17),
+    lambda: gg.cycle(10),
+]
+
+
+# ------------------------------------------------------------ generators
+
+def test_splitmix64_published_outputs():
+    lines = open(os.path.join(GOLDEN, "splitmix64_seed0.txt")).read().splitlines()
+    vals = [int(t, 16) for t in lines if t.startswith("0x")]
+    assert len(vals) == 5
+    assert [oracle.vertex_hash(i) for i in range(5)] == vals
+
+
+def test_hash_identity_mode_and_bijection_sample():
+    assert oracle.vertex_hash(7, 1) == 7
+    hs = {oracle.vertex_hash(i) for i in range(5000)}
+    assert len(hs) == 5000
+
+
+def test_test_vectors_uniform_on_53bit_grid():
+    xs = np.array([oracle.tv(3, 1, k, i) for k in range(4) for i in range(4000)])
+    assert np.all(xs >= -1.0) and np.all(xs < 1.0)
+    scaled = (xs + 1.0) * 2.0**52
+    assert np.all(scaled == np.floor(scaled))
+    assert abs(xs.mean()) < 0.02
+    assert abs(xs.var() - 1.0 / 3.0) < 0.01
+    # streams differ by level, vector index and seed
+    assert oracle.tv(3, 1, 0, 5) != oracle.tv(3, 2, 0, 5)
+    assert oracle.tv(3, 1, 0, 5) != oracle.tv(3, 1, 1, 5)
+    assert oracle.tv(3, 1, 0, 5) != oracle.tv(4, 1, 0, 5)
+
+
+# ------------------------------------------------------------ exact sums
+
+def _exact_term(v):
+    return round(Fraction(v) * 2**64)  # Fraction.__round__: nearest, ties to even
+
+
+def _edge_values(rng):
+    vals = list(rng.standard_normal(200) * 10.0 ** rng.integers(-22, 12, 200))
+    # exact ties at the 2^-64 grid: odd multiples of 2^-65
+    vals += [math.ldexp(2 * k + 1, -65) for k in range(-6, 6)]
+    vals += [math.ldexp(3, -66), -math.ldexp(3, -66), math.ldexp(1, -66), 5e-324, -5e-324, 0.0]
+    vals += [math.ldexp(1, 61), -math.ldexp(1, 61) + 1.0, 1e-20, 1.5e-19, 2.5e-19]
+    return vals
+
+
+def test_xs_term_is_nearest_integer_ties_to_even():
+    rng = np.random.default_rng(0)
+    for v in _edge_values(rng):
+        st, t = oracle.xs_term(float(v))
+        assert st == 0
+        if t >= 1 << 127:
+            t -= 1 << 128
+        assert t == _exact_term(float(v)), v
+
+
+def test_xs_term_range_guard():
+    assert oracle.xs_term(2.0**63)[0] == 8
+    assert oracle.xs_term(float("nan"))[0] == 8
+
+
+def test_xs_round_is_correctly_rounded():
+    rng = np.random.default_rng(1)
+    cases = [0, 1, -1, (1 << 53) + 1, (1 << 54) + 2, (1 << 54) + 6, -(1 << 100) - 3]
+    for _ in range(400):
+        bits = int(rng.integers(1, 126))
+        s = int(rng.integers(0, 2**62)) << max(0, bits - 62) | int(rng.integers(0, 2**20))
+        s &= (1 << 126) - 1
+        cases.append(s if rng.random() < 0.5 else -s)
+    # halfway cases: 53 significant bits then exactly one half ulp
+    for m in [(1 << 52) + 1, (1 << 52) + 2, (1 << 53) - 1]:
+        cases.append((2 * m + 1) << 10)
+    for s in cases:
+        assert oracle.xs_round(s) == float(Fraction(s, 2**64)), s
+
+
+def test_xsum_equals_fsum_for_grid_aligned_terms():
+    rng = np.random.default_rng(2)
+    for _ in range(50):
+        n = int(rng.integers(1, 300))
+        t = rng.standard_normal(n) * 10.0 ** rng.integers(-3, 9, n)
+        t = np.where(np.abs(t) < 2.0**-10, 2.0**-10, t)  # exponent >= -11: on the 2^-64 grid
+        st, s = oracle.xsum(t)
+        assert st == 0
+        assert s == math.fsum(t)
+
+
+def test_xsum_is_order_independent():
+    rng = np.random.default_rng(3)
+    t = rng.standard_normal(1000) * 10.0 ** rng.integers(-25, 10, 1000)
+    ref = oracle.xsum(t)[1]
+    for _ in range(5):
+        assert oracle.xsum(rng.permutation(t))[1] == ref
+    exact = sum(_exact_term(float(v)) for v in t)
+    assert ref == float(Fraction(exact, 2**64))
+
+
+# ------------------------------------------------------------ validation
+
+def test_validate_accepts_generated_graphs():
+    for mk in SMALL_GRAPHS:
+        assert oracle.validate(mk()) == 0
+
+
+def test_validate_rejects_bad_graphs():
+    g = gg.grid2d(4, 4)
+    bad = g.copy()
+    bad.w[3] *= 2.0  # asymmetric weight
+    assert oracle.validate(bad) == 2
+    bad = g.copy()
+    bad.w[0] = -1.0
+    assert oracle.validate(bad) == 2
+    bad = g.copy()
+    bad.w[0] = 0.0
+    assert oracle.validate(bad) == 2
+    bad = g.copy()
+    bad.col[0] = 0  # self loop in row 0
+    assert oracle.validate(bad) == 2
+    bad = g.copy()
+    bad.col[[1, 2]] = bad.col[[2, 1]]  # unsorted row
+    assert oracle.validate(bad) == 2
+    two = gg.from_edges(4, [0, 2], [1, 3])
+    assert oracle.validate(two) == 3
+    assert oracle.validate(gg.from_edges(1, [], [])) == 0
+
+
+# ------------------------------------------------------------ diagonal
+
+def test_diag_is_correctly_rounded_row_sum():
+    g = gg.grid3d(6, 5, 4, weights="loguniform", seed=4)  # weights >= 1e-3: on the 2^-64 grid
+    d = oracle.diag(g)
+    for i in range(g.n):
+        assert d[i] == math.fsum(g.w[g.row_ptr[i]:g.row_ptr[i + 1]])
+
+
+# ------------------------------------------------------ elimination select
+
+def test_elim_select_local_min_characterisation():
+    for mk in SMALL_GRAPHS:
+        g = mk()
+        deg = g.degrees()
+        cnt, z, F = oracle.elim_select(g)
+        h = np.array([oracle.vertex_hash(i) for i in range(g.n)], dtype=object)
+        for i in range(g.n):
+            nb = g.col[g.row_ptr[i]:g.row_ptr[i + 1]]
+            cands = [j for j in list(nb) + [i] if deg[j] <= 4]
+            expect_z = min(cands, key=lambda j: h[j]) if cands else -1
+            assert z[i] == expect_z
+            local_min = deg[i] <= 4 and all(h[i] < h[j] for j in nb if deg[j] <= 4)
+            assert F[i] == local_min
+        assert cnt == F.sum()
+        # F is an independent set
+        rows = np.repeat(np.arange(g.n), deg)
+        assert not np.any(F[rows] & F[g.col])
+
+
+def test_elim_chain_sequential_hashes_eliminate_one_vertex():
+    g = gg.path(40)
+    cnt, z, F = oracle.elim_select(g, hash_mode=1)
+    assert cnt == 1 and F[0]
+
+
+def test_elim_chain_alternating_hashes_eliminate_every_other_vertex():
+    n = 40
+    # chain position p carries id p//2 (low) when p is even, n//2 + p//2 (high) when odd
+    ids = np.array([p // 2 if p % 2 == 0 else n // 2 + p // 2 for p in range(n)])
+    g = gg.from_edges(n, ids[:-1], ids[1:])
+    cnt, z, F = oracle.elim_select(g, hash_mode=1)
+    assert cnt == n // 2
+    assert set(np.nonzero(F)[0]) == set(range(n // 2))
+
+
+def test_elim_high_degree_vertices_are_not_candidates():
+    g = gg.star(6)
+    cnt, z, F = oracle.elim_select(g)
+    assert not F[0] and F[1:].all() and cnt == 6
+    assert z[0] == min(range(1, 7), key=oracle.vertex_hash)
+
+
+# --------------------------------------------------- Schur complement level
+
+def test_schur_leaf_elimination_deletes_the_edge():
+    g = gg.from_edges(3, [0, 1], [1, 2], [2.0, 3.0])
+    F = np.array([True, False, False])
+    cidx, gc, cd = oracle.elim_build(g, F)
+    assert list(cidx) == [-1, 0, 1]
+    assert gc.nnz == 2 and np.all(gc.w == 3.0) and np.all(cd == 3.0)
+
+
+def test_schur_degree_two_vertex_gives_series_edge():
+    g = gg.path(3)
+    cidx, gc, cd = oracle.elim_build(g, np.array([False, True, False]))
+    assert list(gc.w) == [0.5, 0.5] and list(cd) == [0.5, 0.5]
+    g = gg.from_edges(3, [0, 1], [1, 2], [2.0, 6.0])
+    _, gc, _ = oracle.elim_build(g, np.array([False, True, False]))
+    assert np.allclose(gc.w, 2.0 * 6.0 / 8.0, rtol=0, atol=1e-15)
+
+
+def test_schur_matches_dense_block_formula_and_two_level_identity():
+    for mk in SMALL_GRAPHS:
+        g = mk()
+        cnt, z, F = oracle.elim_select(g)
+        if cnt == 0:
+            continue
+        cidx, gc, cd = oracle.elim_build(g, F)
+        L = dense_L(g)
+        Fi = np.nonzero(F)[0]
+        Ci = np.nonzero(~F)[0]
+        assert np.array_equal(cidx[Ci], np.arange(Ci.size))
+        LFF = L[np.ix_(Fi, Fi)]
+        assert np.allclose(LFF, np.diag(np.diag(LFF)))  # diagonal: F independent
+        LFC = L[np.ix_(Fi, Ci)]
+        schur = L[np.ix_(Ci, Ci)] - LFC.T @ np.diag(1.0 / np.diag(LFF)) @ LFC
+        Lc = dense_L(gc, cd)
+        scale = np.abs(schur).max()
+        assert np.abs(Lc - schur).max() <= 1e-13 * scale
+        # additive two-level form: x = P Lc^+ P^T b + [L_FF^-1 b_F; 0] solves L x = b
+        P = np.zeros((g.n, Ci.size))
+        P[Ci, np.arange(Ci.size)] = 1.0
+        P[np.ix_(Fi, np.arange(Ci.size))] = -np.diag(1.0 / np.diag(LFF)) @ LFC
+        rng = np.random.default_rng(0)
+        b = rng.standard_normal(g.n)
+        b -= b.mean()
+        x = P @ np.linalg.pinv(schur) @ P.T @ b
+        x[Fi] += b[Fi] / np.diag(LFF)
+        assert np.linalg.norm(L @ x - b) <= 1e-9 * np.linalg.norm(b)
+
+
+# ------------------------------------------------------------------- SoC
+
+def test_soc_test_vectors_follow_weighted_jacobi():
+    g = gg.chung_lu(400, seed=2, max_deg=50)
+    opts = oracle.default_opts()
+    X, S = oracle.soc(g, opts, level=3)
+    X0 = np.array([[oracle.tv(opts.seed, 3, k, i) for k in range(4)] for i in range(g.n)])
+    A = sparse_A(g)
+    d = np.asarray(A.sum(1)).ravel()
+    w = opts.tv_omega
+    Y = X0
+    for _ in range(opts.tv_sweeps):
+        Y = (1 - w) * Y + w * (A @ Y) / d[:, None]
+    assert np.abs(X - Y).max() <= 1e-14
+
+
+def test_soc_strength_invariants():
+    for mk in SMALL_GRAPHS:
+        g = mk()
+        X, S = oracle.soc(g)
+        assert np.all(S >= 0.0) and np.all(S <= 1.0 + 1e-15)
+        # symmetric, bit for bit
+        rows = np.repeat(np.arange(g.n), g.degrees())
+        key = rows * g.n + g.col
+        tkey = g.col.astype(np.int64) * g.n + rows
+        order = np.argsort(key)
+        pos = order[np.searchsorted(key[order], tkey)]
+        assert np.array_equal(S, S[pos])
+        assert S.max() == 1.0
+        # Cauchy-Schwarz bound on the affinity of each edge
+        nx = np.linalg.norm(X, axis=1)
+        cos2 = (np.einsum("ij,ij->i", X[rows], X[g.col]) / (nx[rows] * nx[g.col])) ** 2
+        assert np.all(S >= cos2 * (1 - 1e-12))  # S >= C because every row maximum is <= 1
+        M = np.zeros(g.n)
+        np.maximum.at(M, rows, cos2)
+        expect = cos2 / np.maximum(M[rows], M[g.col])
+        assert np.allclose(S, expect, rtol=1e-12, atol=1e-14)
+
+
+def test_soc_single_edge_has_strength_one():
+    g = gg.path(2)
+    _, S = oracle.soc(g)
+    assert list(S) == [1.0, 1.0]
+
+
+# ----------------------------------------------------------- aggregation
+
+def _uniform_S(g, value=1.0):
+    return np.full(g.nnz, value)
+
+
+def test_star_seed_threshold_is_at_least_eight():
+    o1 = oracle.default_opts(agg_iters=1)
+    for m, seed_after_one in [(7, False), (8, True), (9, True)]:
+        g = gg.star(m)
+        nc, agg, state, idx, votes = oracle.aggregate(g, _uniform_S(g), o1)
+        assert votes[0] == m
+        assert (state[0] == 2) == seed_after_one
+    o2 = oracle.default_opts(agg_iters=2)
+    assert oracle.aggregate(gg.star(8), _uniform_S(gg.star(8)), o2)[0] == 1
+    assert oracle.aggregate(gg.star(7), _uniform_S(gg.star(7)), o2)[0] == 8
+
+
+def test_filter_keeps_strength_equal_to_threshold():
+    g = gg.star(8)
+    o1 = oracle.default_opts(agg_iters=1)
+    _, _, state, _, votes = oracle.aggregate(g, _uniform_S(g, 0.5), o1)
+    assert votes[0] == 8 and state[0] == 2
+    _, _, state, _, votes = oracle.aggregate(g, _uniform_S(g, 0.4999), o1)
+    assert votes[0] == 0 and state[0] == 1
+
+
+def test_path_hand_trace():
+    # traced by hand in the design doc: seeds 1 and 3, aggregates {0,1,2} and {3,4}
+    g = gg.path(5)
+    nc, agg, state, idx, votes = oracle.aggregate(g, _uniform_S(g), oracle.default_opts())
+    assert nc == 2
+    assert list(agg) == [0, 0, 0, 1, 1]
+    assert list(state) == [0, 2, 0, 2, 0]
+    assert list(idx) == [1, 1, 1, 3, 3]
+    assert list(votes) == [4, 8, 5, 8, 3]
+
+
+def test_adjacent_roots_are_allowed():
+    # two stars K_{1,9} whose hubs 0 and 10 are joined
+    u = [0] * 9 + [10] * 9 + [0]
+    v = list(range(1, 10)) + list(range(11, 20)) + [10]
+    g = gg.from_edges(20, u, v)
+    nc, agg, state, idx, votes = oracle.aggregate(g, _uniform_S(g), oracle.default_opts())
+    assert nc == 2
+    assert state[0] == 2 and state[10] == 2
+    assert all(idx[1:10] == 0) and all(idx[11:20] == 10)
+
+
+def test_aggregation_invariants_on_random_graphs():
+    for mk in SMALL_GRAPHS:
+        g = mk()
+        _, S = oracle.soc(g)
+        nc, agg, state, idx, votes = oracle.aggregate(g, S)
+        roots = np.nonzero(idx == np.arange(g.n))[0]
+        assert nc == roots.size
+        assert np.array_equal(agg[roots], np.arange(nc))  # renumbered in increasing root id
+        assert np.all(idx[idx] == idx)  # every index names a root
+        assert np.array_equal(agg, agg[idx])
+        for i in np.nonzero(idx != np.arange(g.n))[0]:
+            assert idx[i] in g.col[g.row_ptr[i]:g.row_ptr[i + 1]]  # joined a neighbour
+            assert state[idx[i]] == 2 and state[i] == 0
+
+
+# -------------------------------------------------------------- Galerkin
+
+def test_galerkin_matches_dense_triple_product():
+    rng = np.random.default_rng(5)
+    for mk in SMALL_GRAPHS:
+        g = mk()
+        nc = max(2, g.n // 4)
+        agg = rng.integers(0, nc, g.n)
+        agg[:nc] = np.arange(nc)  # every aggregate non-empty
+        gc, cd = oracle.galerkin(g, agg, nc)
+        R = np.zeros((nc, g.n))
+        R[agg, np.arange(g.n)] = 1.0
+        ref = R @ dense_L(g) @ R.T
+        Lc = dense_L(gc, cd)
+        assert np.abs(Lc - ref).max() <= 1e-12 * np.abs(ref).max()
+        assert np.all(gc.w > 0)
+        assert abs(Lc.sum()) <= 1e-12 * np.abs(ref).max() * nc
+        rows = np.repeat(np.arange(g.n), g.degrees())
+        inter = agg[rows] != agg[g.col]
+        assert math.isclose(math.fsum(gc.w), math.fsum(g.w[inter]), rel_tol=1e-14)
+
+
+# --------------------------------------------------- hierarchy invariants
+
+def _check_laplacian_level(g, d):
+    assert oracle.validate(g) in (0,)
+    for i in range(g.n):
+        row = g.w[g.row_ptr[i]:g.row_ptr[i + 1]]
+        s = math.fsum(row)
+        assert abs(d[i] - s) <= 0.5 * math.ulp(d[i]) + 0.0
+
+
+@pytest.mark.parametrize("mk", [lambda: gg.grid2d(64, 64), lambda: gg.rmat(11, 16, seed=2),
+                                lambda: gg.chung_lu(5000, seed=6, max_deg=300),
+                                lambda: gg.grid3d(10, 10, 10, weights="loguniform", seed=4)])
+def test_every_level_is_a_connected_laplacian(mk):
+    g = mk()
+    h = oracle.Hierarchy(g)
+    levels = h.levels()
+    assert levels[-1].type == oracle.COARSEST
+    assert levels[-1].n + levels[-1].nnz <= 1000
+    for l, L in enumerate(levels):
+        gl, d = h.csr(l)
+        _check_laplacian_level(gl, d)
+        if l + 1 < len(levels):
+            assert levels[l + 1].n == L.nc
+            assert levels[l + 1].n < L.n
+        if L.type == oracle.ELIM:
+            assert l + 1 < len(levels) and levels[l + 1].type != oracle.ELIM
+
+
+def test_coarsest_pseudo_inverse():
+    g = gg.grid2d(20, 20)
+    h = oracle.Hierarchy(g)
+    gl, d = h.csr(h.num_levels - 1)
+    L = dense_L(gl, d)
+    P = h.coarsest_pinv()
+    ref = np.linalg.pinv(L)
+    assert np.abs(P - ref).max() <= 1e-9 * np.abs(ref).max()
+    assert np.abs(L @ P @ L - L).max() <= 1e-10 * np.abs(L).max()
+
+
+# ------------------------------------------------------------- eigenvalue
+
+def test_tridiag_max_matches_eigvalsh():
+    rng = np.random.default_rng(7)
+    for m in range(1, 12):
+        a = rng.standard_normal(m)
+        b = rng.standard_normal(max(m - 1, 0))
+        T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+        assert math.isclose(oracle.tridiag_max(a, b), np.linalg.eigvalsh(T).max(), rel_tol=1e-12,
+                            abs_tol=1e-12)
+
+
+def test_lanczos_on_even_cycle_finds_two():
+    g = gg.cycle(8)  # D^-1 L has eigenvalues 1 - cos(2 pi k / 8); the largest is 2
+    lm = oracle.lanczos_lmax(g, steps=10)
+    assert abs(lm - 2.0) < 1e-10
+
+
+def test_lanczos_estimate_on_bipartite_grid():
+    g = gg.grid2d(12, 12)  # bipartite: lambda_max(D^-1 L) = 2 exactly
+    lm = oracle.lanczos_lmax(g, steps=10)
+    assert 1.8 < lm <= 2.0 + 1e-12
+
+
+# -------------------------------------------------------------- smoother
+
+def test_chebyshev_damps_eigenvectors_by_the_chebyshev_ratio():
+    n = 16
+    g = gg.cycle(n)  # D = 2I; D^-1 L u_k = mu_k u_k, mu_k = 1 - cos(2 pi k / n)
+    opts = oracle.default_opts()
+    lmax = 2.0
+    lo, hi = opts.cheb_lo * lmax, opts.cheb_hi * lmax
+    theta, delta = (hi + lo) / 2, (hi - lo) / 2
+
+    def T2(t):
+        return 2 * t * t - 1
+
+    L = dense_L(g)
+    i = np.arange(n)
+    for k in range(n // 2 + 1):
+        u = np.cos(2 * np.pi * k * i / n)
+        mu = 1 - np.cos(2 * np.pi * k / n)
+        b = L @ u
+        x = oracle.cheb_apply(g, lmax, np.zeros(n), b, opts, x_is_zero=True)
+        factor = T2((theta - mu) / delta) / T2(theta / delta)
+        assert np.abs((u - x) - factor * u).max() <= 1e-13
+        # from a non-zero start the error obeys the same polynomial
+        x0 = 0.25 * u
+        x = oracle.cheb_apply(g, lmax, x0, b, opts)
+        assert np.abs((u - x) - factor * 0.75 * u).max() <= 1e-13
+
+
+# ----------------------------------------------------------------- solve
+
+SOLVE_GRAPHS = [
+    lambda: gg.grid2d(15, 15),
+    lambda: gg.gnp(200, 0.03, seed=4),
+    lambda: gg.star(40),
+    lambda: gg.path(60),
+    lambda: gg.chung_lu(300, seed=4, max_deg=40),
+    lambda: gg.grid3d(6, 6, 6, weights="loguniform", seed=8),
+]
+
+
+@pytest.mark.parametrize("cycle", [1, 2])
+@pytest.mark.parametrize("mk", SOLVE_GRAPHS)
+def test_solve_matches_dense_pseudo_inverse(mk, cycle):
+    g = mk()
+    h = oracle.Hierarchy(g, oracle.default_opts(cycle=cycle, coarsest_nnz=60))
+    rng = np.random.default_rng(1)
+    b = rng.standard_normal(g.n)
+    x, st, it, rel, work = h.solve(b, 1e-8, 300)
+    assert st == 0 and rel <= 1e-8
+    L = dense_L(g)
+    bp = b - b.mean()
+    ref = np.linalg.pinv(L) @ bp
+    ev = np.linalg.eigvalsh(L)
+    lam1 = ev[1]
+    # ||x - x*|| <= ||r|| / lambda_1 (both mean-zero)
+    bound = 1.5 * rel * np.linalg.norm(bp) / lam1 + 1e-12 * np.linalg.norm(ref)
+    assert np.linalg.norm(x - ref) <= bound
+    assert abs(x.mean()) < 1e-12 * (np.abs(x).max() + 1)
+    assert np.linalg.norm(bp - L @ x) <= 1e-8 * np.linalg.norm(bp) * 1.0001
+
+
+def test_solve_eigenvector_rhs_on_path():
+    n = 50
+    g = gg.path(n)
+    h = oracle.Hierarchy(g, oracle.default_opts(coarsest_nnz=20))
+    i = np.arange(n)
+    for k in (1, 7, 30):
+        u = np.cos(np.pi * k * (i + 0.5) / n)  # Laplacian eigenvector of the path
+        lam = 2 - 2 * np.cos(np.pi * k / n)
+        x, st, it, rel, work = h.solve(u, 1e-10, 200)
+        assert st == 0
+        assert np.linalg.norm(x - u / lam) <= 1e-8 * np.linalg.norm(u / lam) / (lam / 4.0)
+
+
+def test_elimination_level_with_exact_coarse_solve_is_exact():
+    g = gg.grid2d(10, 10)
+    h = oracle.Hierarchy(g, oracle.default_opts(max_levels=2, coarsest_nnz=100))
+    lv = h.levels()
+    assert [L.type for L in lv] == [oracle.ELIM, oracle.COARSEST]
+    rng = np.random.default_rng(2)
+    b = rng.standard_normal(g.n)
+    b -= b.mean()
+    x = h.cycle(b)
+    L = dense_L(g)
+    assert np.linalg.norm(L @ x - b) <= 1e-12 * np.linalg.norm(b)
+    x, st, it, rel, work = h.solve(b, 1e-8)
+    assert st == 0 and it == 1
+
+
+def test_wda_within_the_papers_range_on_the_2d_grid():
+    # context only: the paper's V-cycle WDA on its test set spans roughly 3 to 100
+    g = gg.grid2d(64, 64)
+    h = oracle.Hierarchy(g)
+    b = gg.rhs(g.n, 1, 1)[:, 0]
+    x, st, it, rel, work = h.solve(b)
+    wda = -work / math.log10(rel)
+    assert st == 0 and 3 < wda < 100
