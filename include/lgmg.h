@@ -1,0 +1,187 @@
+/*
+ * lgmg.h -- C ABI of liblgmg.so: unsmoothed-aggregation multigrid for graph
+ * Laplacians (Konolige & Brown, "A Parallel Solver for Graph Laplacians",
+ * PASC'18) on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Section 2.1): a connected, undirected graph with positive edge
+ * weights w_ij defines L = D - A with D_ii = sum_j w_ij.  L is symmetric
+ * positive semi-definite with null space span{1}; lg_solve returns the
+ * mean-zero x with L x = b - mean(b).
+ *
+ * Conventions for every entry point:
+ *  - Every function returns lg_status; no C++ exception crosses the boundary.
+ *    On failure lg_last_error() (per thread) describes the cause.
+ *  - Graph arrays are the CSR of the symmetric adjacency A: both directions
+ *    stored, column indices strictly increasing within a row, no diagonal
+ *    entries, weights > 0.  row_ptr is int64[n+1], col int32[nnz],
+ *    w float64[nnz].  nnz must be below 2^31.
+ *  - "device" pointers are HIP device allocations (e.g. torch tensors'
+ *    data_ptr on cuda:0), used on the caller's stream.  Host pointers are
+ *    ordinary memory.  The library never frees caller memory.
+ *  - Multi-vector layout: n x k row-major (entry (i, c) at [i*k + c]).
+ *  - hip_stream is a hipStream_t (NULL = the default stream).  Calls are
+ *    asynchronous with respect to the host only where stated; setup and
+ *    solve synchronise the stream before returning.
+ *  - A hierarchy may be used by one call at a time (solves on one hierarchy
+ *    share its workspace).
+ */
+#ifndef LGMG_H
+#define LGMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lg_status;
+enum {
+  LG_OK = 0,
+  LG_E_ARG = 1,           /* invalid argument or unsupported size */
+  LG_E_GRAPH = 2,         /* not a valid weighted undirected graph (asymmetric, w <= 0, loop, unsorted) */
+  LG_E_DISCONNECTED = 3,  /* graph not connected (Section 2.1 assumes connectivity) */
+  LG_E_NOMEM = 4,         /* device allocation failed */
+  LG_E_HIP = 5,           /* HIP runtime error */
+  LG_E_NOT_CONVERGED = 6, /* max_iter reached or breakdown; X and info are still filled */
+  LG_E_BUSY = 7,          /* reserved */
+  LG_E_RANGE = 8          /* total edge weight >= 2^62: outside the exact-sum range */
+};
+
+enum { LG_LEVEL_AGG = 0, LG_LEVEL_ELIM = 1, LG_LEVEL_COARSEST = 2 };
+enum { LG_CYCLE_V = 1, LG_CYCLE_K = 2 };
+enum { LG_FP64 = 0, LG_MIXED = 1 };
+
+typedef struct {
+  int64_t n;               /* vertices, >= 1 */
+  int64_t nnz;             /* stored adjacency entries (2 x undirected edges) */
+  const int64_t* row_ptr;  /* [n+1] */
+  const int32_t* col;      /* [nnz] */
+  const double* w;         /* [nnz] */
+  int32_t on_device;       /* 1: the three arrays are device pointers, 0: host pointers */
+} lg_graph;
+
+/* Method parameters; lg_default_opts fills the paper's values. */
+typedef struct {
+  int32_t elim_enable;      /* low-degree elimination before each aggregation (Section 3.4) */
+  int32_t elim_max_degree;  /* candidates: degree <= this (4, Section 3.4) */
+  double elim_min_fraction; /* apply only if more than this fraction is eliminated (0.05) */
+  int32_t agg_iters;        /* voting iterations (10, Section 3.5) */
+  double agg_filter_base;   /* iteration t keeps strengths >= base^t (0.5, Algorithm 3) */
+  int32_t seed_votes;       /* votes that make an Undecided vertex a Seed (8, Section 3.5) */
+  int32_t tv_sweeps;        /* Jacobi sweeps on the 4 test vectors (3, Section 3.5) */
+  double tv_omega;          /* their damping; the paper gives none (2/3) */
+  int32_t cheb_degree;      /* Chebyshev smoother degree (2, Section 4) */
+  double cheb_lo, cheb_hi;  /* interval as fractions of lambda_max (0.3, 1.1, Section 3.6) */
+  int32_t eig_iters;        /* Lanczos steps for lambda_max (10, Section 3.6) */
+  int64_t coarsest_nnz;     /* stop coarsening once n + nnz(A) <= this (1000, Section 4) */
+  int32_t max_levels;       /* cap on hierarchy depth (64) */
+  int32_t cycle;            /* LG_CYCLE_V (CG outside) or LG_CYCLE_K (FCG outside, Section 3.7) */
+  int32_t hash_mode;        /* elimination hash: 0 = mixed id, 1 = identity (testing) */
+  uint64_t seed;            /* seed of the counter-based generator for test and start vectors */
+  int32_t precision;        /* LG_FP64, or LG_MIXED: fp32 hierarchy values and cycle inside fp64 CG */
+  int32_t max_rhs;          /* largest k passed to lg_solve (1..32); sizes the solve workspace */
+  int32_t keep_setup_data;  /* 1: keep strengths, test vectors, votes and elimination choices for export */
+  int32_t validate;         /* 1: check symmetry, weights and connectivity on the device */
+} lg_setup_opts;
+
+typedef struct lg_hierarchy lg_hierarchy;
+
+typedef struct {
+  int32_t type;    /* LG_LEVEL_* */
+  int64_t n;       /* vertices on this level */
+  int64_t nnz;     /* stored off-diagonal entries */
+  int64_t nc;      /* vertices on the next level (0 for the coarsest) */
+  double lmax;     /* lambda_max estimate of D^-1 L (aggregation levels) */
+  int64_t n_hub;   /* rows split across workgroups by the row scheduler */
+} lg_level_stats;
+
+typedef struct {
+  int32_t iters;        /* CG / FCG iterations */
+  double rel_residual;  /* final true ||b - L x|| / ||b|| (b projected to mean zero) */
+  double work_units;    /* work in finest-level residual evaluations (Section 2.3.1) */
+  double wda;           /* work per digit of accuracy, -work / log10(rel_residual) */
+} lg_rhs_info;
+
+/* Fill o with the paper's parameters (Sections 3.4-3.6, 4). */
+lg_status lg_default_opts(lg_setup_opts* o);
+
+/* Build the multigrid hierarchy of L = D - A (Sections 3.4-3.6): per level an
+ * optional low-degree elimination (Algorithm 2 and the Schur complement), the
+ * affinity strength of connection, voting aggregation (Algorithm 3), the
+ * Galerkin operator R L P and a Lanczos lambda_max estimate; the last level
+ * gets a dense pseudo-inverse.  g's arrays are only read during the call.
+ * On success *out owns device memory until lg_free.  Errors: LG_E_ARG,
+ * LG_E_GRAPH, LG_E_DISCONNECTED, LG_E_RANGE, LG_E_NOMEM, LG_E_HIP. */
+lg_status lg_setup(const lg_graph* g, const lg_setup_opts* o, void* hip_stream,
+                   lg_hierarchy** out);
+
+/* Solve L X = B - mean(B) for k right-hand sides at once (Section 4: CG
+ * preconditioned by one V-cycle, or FCG with a K-cycle; relative tolerance
+ * rtol on the true residual).  B and X are device n x k row-major fp64; B is
+ * not modified; X receives mean-zero solutions.  info (host, k entries, may
+ * be NULL) receives per-column statistics.  1 <= k <= max_rhs of setup.
+ * Returns LG_E_NOT_CONVERGED (X and info filled) if a column misses rtol. */
+lg_status lg_solve(lg_hierarchy* h, const double* B, double* X, int32_t k, double rtol,
+                   int32_t max_iter, void* hip_stream, lg_rhs_info* info);
+
+/* One application of the preconditioner (Algorithm 1 from the finest level
+ * with zero initial guess; V- or K-cycle and precision as in setup):
+ * X = M B for device n x k fp64 arrays.  No projection.  Used to compare the
+ * cycle with a reference implementation. */
+lg_status lg_cycle(lg_hierarchy* h, const double* B, double* X, int32_t k, void* hip_stream);
+
+/* Y = L_l X on hierarchy level l for device n_l x k fp64 arrays (fp64
+ * values).  Asynchronous on hip_stream. */
+lg_status lg_spmv(lg_hierarchy* h, int32_t level, const double* X, double* Y, int32_t k,
+                  void* hip_stream);
+
+/* Level statistics into out[0 .. min(cap, levels)); *n_levels = depth. */
+lg_status lg_hierarchy_stats(const lg_hierarchy* h, lg_level_stats* out, int32_t cap,
+                             int32_t* n_levels);
+
+/* Copy level l's operator to host buffers sized from lg_hierarchy_stats:
+ * row_ptr int64[n+1], col int32[nnz], w float64[nnz], d float64[n] (any may
+ * be NULL).  map (int32[n], may be NULL) receives the aggregate of each vertex
+ * (aggregation level) or its coarse index, -1 if eliminated (elimination
+ * level).  Returns LG_E_ARG for a bad level. */
+lg_status lg_export_level(const lg_hierarchy* h, int32_t level, int64_t* row_ptr, int32_t* col,
+                          double* w, double* d, int32_t* map);
+
+/* Setup intermediates of level l, kept only when keep_setup_data was set
+ * (else LG_E_ARG); any pointer may be NULL.  Host buffers:
+ * X float64[n*4] (test vectors after smoothing), S float64[nnz] (strength per
+ * stored edge), state int32[n] (0 Decided, 1 Undecided, 2 Seed), idx int32[n]
+ * (root named by each vertex), votes int32[n], z int32[n] (elimination
+ * semiring product, -1 for none). */
+lg_status lg_export_setup_data(const lg_hierarchy* h, int32_t level, double* X, double* S,
+                               int32_t* state, int32_t* idx, int32_t* votes, int32_t* z);
+
+/* Dense pseudo-inverse of the coarsest level, host float64[nc*nc]. */
+lg_status lg_export_coarsest(const lg_hierarchy* h, double* Lplus);
+
+/* Device bytes held by the hierarchy, including the solve workspace. */
+size_t lg_hierarchy_bytes(const lg_hierarchy* h);
+
+/* Milliseconds the last lg_setup on h took (host wall clock). */
+double lg_setup_ms(const lg_hierarchy* h);
+
+/* Release every device allocation of h.  NULL is ignored. */
+void lg_free(lg_hierarchy* h);
+
+/* Kernel timing with HIP events for one kernel family (name as listed by
+ * lg_profile_names, e.g. "spmm"), recorded around each of its launches on the
+ * launch stream while enabled.  lg_profile_read returns the launch count, the
+ * summed event time and the summed algorithmic bytes of those launches, then
+ * resets the counters.  Disabled by default (family NULL). */
+lg_status lg_profile_enable(const char* family);
+lg_status lg_profile_read(int64_t* launches, double* total_ms, double* total_bytes);
+const char* lg_profile_names(void);
+
+const char* lg_status_str(lg_status s);
+const char* lg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

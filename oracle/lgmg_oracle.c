@@ -937,7 +937,7 @@ int lgo_setup(int64_t n, const int64_t* rp, const int32_t* col, const double* w,
   h->nlev = l + 1;
   olevel* last = &h->lev[l];
   last->type = LGO_COARSEST;
-  if (last->A.n > 8192) {
+  if (last->A.n > 2048) {
     st = LGO_E_ARG; /* coarsening stalled far above a dense-solvable size */
     goto fail;
   }

@@ -1,0 +1,102 @@
+// impl.h -- the device-resident hierarchy behind lg_hierarchy.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace lg {
+
+// Packed voting status (Algorithm 3): state in bits 30-31, index in bits 0-29.
+// State codes equal their rank in the argmax order: Seed > Undecided > Decided.
+constexpr int kDecided = 0, kUndecided = 1, kSeed = 2;
+constexpr int32_t kIdxMask = (1 << 30) - 1;
+
+struct Level {
+  int type = LG_LEVEL_COARSEST;
+  int64_t n = 0, nnz = 0, nc = 0;
+  // off-diagonal adjacency (CSR, int32 offsets) and the Laplacian diagonal
+  int32_t* rp = nullptr;
+  int32_t* col = nullptr;
+  double* w = nullptr;
+  double* d = nullptr;
+  double* dinv = nullptr;
+  float* wf = nullptr;  // mixed precision copies
+  float* df = nullptr;
+  float* dinvf = nullptr;
+  Sched sched;
+  // aggregation level: aggregate of each vertex and the member lists of R
+  int32_t* agg = nullptr;
+  int32_t* mptr = nullptr;
+  int32_t* mem = nullptr;
+  Sched msched;
+  // elimination level: coarse index (-1 = eliminated), fine vertex of each
+  // coarse vertex, and the F-part of P^T as CSR over coarse rows
+  int32_t* cidx = nullptr;
+  int32_t* cvert = nullptr;
+  int32_t* ptrp = nullptr;
+  int32_t* ptf = nullptr;
+  double* ptc = nullptr;
+  float* ptcf = nullptr;
+  Sched ptsched;
+  int64_t nF = 0, nnzP = 0;
+  double lmax = 0.0;
+  // setup data kept for export
+  double* X = nullptr;
+  double* S = nullptr;
+  int32_t* status = nullptr;
+  int32_t* votes = nullptr;
+  int32_t* z = nullptr;
+  // cycle workspace (precision type, n x K)
+  void* vb = nullptr;
+  void* vx = nullptr;
+  void* vx2 = nullptr;
+  void* vr = nullptr;
+  void* vp = nullptr;
+  // K-cycle workspace (levels whose coarse solve is FCG)
+  void* kr = nullptr;
+  void* kp1 = nullptr;
+  void* kq1 = nullptr;
+  void* kz = nullptr;
+  void* kx = nullptr;
+  double* kscal = nullptr;  // per-column scalars of the inner FCG
+};
+
+}  // namespace lg
+
+struct lg_hierarchy {
+  lg_setup_opts opts{};
+  int device = 0;
+  lg::Arena mem{(size_t)64 << 20};
+  std::vector<lg::Level> lev;
+  double* Lplus = nullptr;  // coarsest pseudo-inverse, fp64
+  int K = 1;                // padded right-hand-side capacity
+  // outer Krylov workspace, fp64, n0 x K
+  double *pb = nullptr, *px = nullptr, *pr = nullptr, *pz = nullptr, *pp = nullptr,
+         *pq = nullptr, *pt = nullptr;
+  void* cyc_in = nullptr;   // level-0 cycle input in the cycle precision (mixed)
+  double* scal = nullptr;   // device scalars, 32 x K
+  double* red = nullptr;    // reduction partials
+  double* host_scal = nullptr;  // pinned mirror of scal
+  double setup_ms = 0.0;
+  double* lmax_dev = nullptr;
+  ~lg_hierarchy() {
+    if (host_scal) (void)hipHostFree(host_scal);
+  }
+};
+
+namespace lg {
+constexpr int kRedBlocks = 240;  // fixed grid of the two-stage reductions
+// scalar slots (each K wide) of lg_hierarchy::scal
+enum {
+  S_BN = 0, S_RZ, S_PQ, S_ALPHA, S_BETA, S_RR, S_PR, S_ZQ, S_ACTIVE, S_MEAN, S_TMP, S_TR,
+  S_COUNT = 32
+};
+
+void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st);
+void alloc_solve_workspace(lg_hierarchy* h, hipStream_t st);
+lg_status solve_dispatch(lg_hierarchy* h, const double* B, double* X, int k, double rtol,
+                         int max_iter, hipStream_t st, lg_rhs_info* info);
+void cycle_dispatch(lg_hierarchy* h, const double* B, double* X, int k, hipStream_t st);
+void spmv_dispatch(lg_hierarchy* h, int level, const double* X, double* Y, int k, hipStream_t st);
+}  // namespace lg

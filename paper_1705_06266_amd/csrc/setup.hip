@@ -1,0 +1,1224 @@
+// setup.hip -- hierarchy construction on the device (Sections 3.4-3.6, 4).
+//
+// Decisions (which vertices are eliminated, which aggregates form) must not
+// depend on thread scheduling.  All sums that feed them or a stored level are
+// exact and order free (xs_term/xs_value in common.h); products, quotients
+// and the per-edge affinity use a fixed operand order, and the argmin/argmax
+// reductions use total orders.  Integer atomics only count.
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "impl.h"
+#include "ops.h"
+
+namespace lg {
+
+enum {
+  F_ROWPTR = 1, F_COL = 2, F_LOOP = 4, F_ORDER = 8, F_WEIGHT = 16, F_ASYM = 32, F_XSUM = 64
+};
+
+constexpr int kMaxLevelCap = 128;
+constexpr int64_t kDenseLimit = 2048;
+
+static inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)ceil_div(n, b); }
+
+// --------------------------------------------------------------- input
+__global__ void k_rowptr_to32(const int64_t* __restrict__ rp64, int32_t* __restrict__ rp,
+                              int64_t n, int64_t nnz, int* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i > n) return;
+  const int64_t v = rp64[i];
+  int f = 0;
+  if (v < 0 || v > nnz) f = F_ROWPTR;
+  if (i == 0 && v != 0) f = F_ROWPTR;
+  if (i == n && v != nnz) f = F_ROWPTR;
+  if (i < n && rp64[i + 1] < v) f = F_ROWPTR;
+  if (f) atomicOr(flags, f);
+  rp[i] = (int32_t)v;
+}
+
+struct NoAcc {
+  int v;
+};
+
+// Section 2.1: weights positive, undirected (w_ij = w_ji), no self-loops;
+// plus the CSR rules (columns in range, strictly increasing).
+struct ValidateOp {
+  using Acc = NoAcc;
+  const int32_t* __restrict__ rp;
+  const int32_t* __restrict__ col;
+  const double* __restrict__ w;
+  int64_t n;
+  int* flags;
+  __device__ Acc identity() const { return {0}; }
+  __device__ bool active(int64_t) const { return true; }
+  __device__ void accum(Acc& a, int64_t row, int e) const {
+    const int j = col[e];
+    int f = 0;
+    if (j < 0 || j >= n) {
+      f = F_COL;
+    } else {
+      if (j == row) f |= F_LOOP;
+      if (e > rp[row] && col[e - 1] >= j) f |= F_ORDER;
+      const double we = w[e];
+      if (!(we > 0.0) || !__builtin_isfinite(we)) f |= F_WEIGHT;
+      int lo = rp[j], hi = rp[j + 1] - 1, found = -1;
+      while (lo <= hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        const int c = col[mid];
+        if (c == row) {
+          found = mid;
+          break;
+        }
+        if (c < row) lo = mid + 1;
+        else hi = mid - 1;
+      }
+      if (found < 0 || w[found] != we) f |= F_ASYM;
+    }
+    a.v |= f;
+  }
+  __device__ void combine(Acc& a, const Acc& o) const { a.v |= o.v; }
+  __device__ void finish(int64_t, const Acc& a, int lane, int) const {
+    if (lane == 0 && a.v) atomicOr(flags, a.v);
+  }
+};
+
+// ------------------------------------------- connectivity (union-find)
+__device__ __forceinline__ int uf_load(int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ int uf_find(int* parent, int x) {
+  int cur = x;
+  int next = uf_load(&parent[cur]);
+  while (next != cur) {
+    const int nn = uf_load(&parent[next]);
+    if (nn != next) __hip_atomic_store(&parent[cur], nn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    cur = next;
+    next = nn;
+  }
+  return cur;
+}
+// Link the larger root under the smaller one; a failed CAS means another
+// thread linked that root first, so every retry follows progress.
+__device__ void uf_unite(int* parent, int a, int b) {
+  for (;;) {
+    a = uf_find(parent, a);
+    b = uf_find(parent, b);
+    if (a == b) return;
+    if (a > b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    if (atomicCAS(&parent[b], b, a) == b) return;
+  }
+}
+
+struct UniteOp {
+  using Acc = NoAcc;
+  const int32_t* __restrict__ col;
+  int* parent;
+  int64_t n;
+  __device__ Acc identity() const { return {0}; }
+  __device__ bool active(int64_t) const { return true; }
+  __device__ void accum(Acc&, int64_t row, int e) const {
+    const int j = col[e];
+    if (j > row && j < n) uf_unite(parent, (int)row, j);
+  }
+  __device__ void combine(Acc&, const Acc&) const {}
+  __device__ void finish(int64_t, const Acc&, int, int) const {}
+};
+
+__global__ void k_iota(int* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = (int)i;
+}
+
+__global__ void k_count_roots(int* parent, int64_t n, int* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool root = i < n && uf_find(parent, (int)i) == (int)i;
+  const uint64_t m = __ballot(root);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, __popcll(m));
+}
+
+// ------------------------------------------------------ exact row sums
+struct XAcc {
+  u128 s;
+  int bad;
+  int pad[3];
+};
+
+// out[row] = exact sum of val over the row; outinv[row] = 1 / out[row].
+struct RowXsumOp {
+  using Acc = XAcc;
+  const double* __restrict__ val;
+  double* __restrict__ out;
+  double* __restrict__ outinv;
+  int* flags;
+  __device__ Acc identity() const { return {0, 0, {0, 0, 0}}; }
+  __device__ bool active(int64_t) const { return true; }
+  __device__ void accum(Acc& a, int64_t, int e) const { a.s += xs_term(val[e], a.bad); }
+  __device__ void combine(Acc& a, const Acc& o) const {
+    a.s += o.s;
+    a.bad |= o.bad;
+  }
+  __device__ void finish(int64_t row, const Acc& a, int lane, int) const {
+    if (lane) return;
+    const double v = xs_value(a.s);
+    out[row] = v;
+    if (outinv) outinv[row] = v > 0.0 ? 1.0 / v : 0.0;
+    if (a.bad) atomicOr(flags, F_XSUM);
+  }
+};
+
+// Runs of equal (row, col) keys after sorting: one exact sum per run.
+struct RunXsumOp {
+  using Acc = XAcc;
+  const double* __restrict__ val;
+  const uint64_t* __restrict__ keys;
+  const int32_t* __restrict__ start;
+  int32_t* __restrict__ ocol;
+  double* __restrict__ ow;
+  int* flags;
+  __device__ Acc identity() const { return {0, 0, {0, 0, 0}}; }
+  __device__ bool active(int64_t) const { return true; }
+  __device__ void accum(Acc& a, int64_t, int e) const { a.s += xs_term(val[e], a.bad); }
+  __device__ void combine(Acc& a, const Acc& o) const {
+    a.s += o.s;
+    a.bad |= o.bad;
+  }
+  __device__ void finish(int64_t run, const Acc& a, int lane, int) const {
+    if (lane) return;
+    ow[run] = xs_value(a.s);
+    ocol[run] = (int32_t)(keys[start[run]] & 0xffffffffULL);
+    if (a.bad) atomicOr(flags, F_XSUM);
+  }
+};
+
+// --------------------------------------- Algorithm 2: elimination choice
+struct MinAcc {
+  uint64_t h;
+  int32_t id;
+  int32_t pad;
+};
+
+// z_i = candidate of least hash among i and its neighbours (-1 if none);
+// candidates have degree <= maxdeg.  flagC[i] = 1 unless z_i = i.
+struct ElimSelectOp {
+  using Acc = MinAcc;
+  const int32_t* __restrict__ rp;
+  const int32_t* __restrict__ col;
+  int maxdeg, hash_mode;
+  int32_t* __restrict__ z;
+  int32_t* __restrict__ keepC;
+  __device__ Acc identity() const { return {~0ULL, -1, 0}; }
+  __device__ bool active(int64_t) const { return true; }
+  __device__ void accum(Acc& a, int64_t, int e) const {
+    const int j = col[e];
+    if (rp[j + 1] - rp[j] > maxdeg) return;
+    const uint64_t h = vertex_hash(j, hash_mode);
+    if (h < a.h) {
+      a.h = h;
+      a.id = j;
+    }
+  }
+  __device__ void combine(Acc& a, const Acc& o) const {
+    if (o.h < a.h) a = o;
+  }
+  __device__ void finish(int64_t row, const Acc& acc, int lane, int) const {
+    if (lane) return;
+    Acc a = acc;
+    if (rp[row + 1] - rp[row] <= maxdeg) {
+      const uint64_t h = vertex_hash(row, hash_mode);
+      if (h < a.h) {
+        a.h = h;
+        a.id = (int32_t)row;
+      }
+    }
+    z[row] = a.id;
+    keepC[row] = (a.id == row) ? 0 : 1;
+  }
+};
+
+// ----------------------------------------------------- per-entry helpers
+struct RowIdxOp {
+  using Acc = NoAcc;
+  int32_t* __restrict__ rowidx;
+  __device__ Acc identity() const { return {0}; }
+  __device__ bool active(int64_t) const { return true; }
+  __device__ void accum(Acc&, int64_t row, int e) const { rowidx[e] = (int32_t)row; }
+  __device__ void combine(Acc&, const Acc&) const {}
+  __device__ void finish(int64_t, const Acc&, int, int) const {}
+};
+
+__global__ void k_cidx(const int32_t* __restrict__ keepC, const int64_t* __restrict__ pos,
+                       int64_t n, int32_t* __restrict__ cidx, int32_t* __restrict__ cvert) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  if (keepC[i]) {
+    cidx[i] = (int32_t)pos[i];
+    cvert[pos[i]] = (int32_t)i;
+  } else {
+    cidx[i] = -1;
+  }
+}
+
+// Entries contributed to the Schur complement by stored entry e = (a, b):
+// 1 if b stays, deg(b) - 1 fill entries if b is eliminated, 0 if a is.
+__global__ void k_elim_count(const int32_t* __restrict__ rowidx, const int32_t* __restrict__ col,
+                             const int32_t* __restrict__ rp, const int32_t* __restrict__ cidx,
+                             int64_t nnz, int32_t* __restrict__ cnt, int32_t* __restrict__ ptflag) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= nnz) return;
+  const int a = rowidx[e], b = col[e];
+  int c = 0, f = 0;
+  if (cidx[a] >= 0) {
+    if (cidx[b] >= 0) {
+      c = 1;
+    } else {
+      c = rp[b + 1] - rp[b] - 1;
+      f = 1;
+    }
+  }
+  cnt[e] = c;
+  ptflag[e] = f;
+}
+
+// Schur complement entries (Section 3.4): (a', b') <- w_ab, and for an
+// eliminated neighbour f of a, (a', c') <- (w_fa * w_fc) / d_f for each other
+// neighbour c of f.
+__global__ void k_elim_emit(const int32_t* __restrict__ rowidx, const int32_t* __restrict__ rp,
+                            const int32_t* __restrict__ col, const double* __restrict__ w,
+                            const double* __restrict__ d, const int32_t* __restrict__ cidx,
+                            const int64_t* __restrict__ off, int64_t nnz,
+                            uint64_t* __restrict__ keys, double* __restrict__ vals) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= nnz) return;
+  const int a = rowidx[e];
+  const int ca = cidx[a];
+  if (ca < 0) return;
+  const int b = col[e];
+  int64_t pos = off[e];
+  const uint64_t hi = (uint64_t)ca << 32;
+  if (cidx[b] >= 0) {
+    keys[pos] = hi | (uint32_t)cidx[b];
+    vals[pos] = w[e];
+    return;
+  }
+  const double w_fa = w[e];
+  const double d_f = d[b];
+  for (int e2 = rp[b]; e2 < rp[b + 1]; e2++) {
+    const int c = col[e2];
+    if (c == a) continue;
+    keys[pos] = hi | (uint32_t)cidx[c];
+    vals[pos] = (w_fa * w[e2]) / d_f;
+    pos++;
+  }
+}
+
+// F-part of P^T: coarse row of a lists (f, w_af / d_f) for eliminated neighbours f.
+__global__ void k_pt_emit(const int32_t* __restrict__ rowidx, const int32_t* __restrict__ col,
+                          const double* __restrict__ w, const double* __restrict__ d,
+                          const int32_t* __restrict__ ptflag, const int64_t* __restrict__ off,
+                          int64_t nnz, int32_t* __restrict__ ptf, double* __restrict__ ptc) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= nnz || !ptflag[e]) return;
+  const int f = col[e];
+  ptf[off[e]] = f;
+  ptc[off[e]] = w[e] / d[f];
+}
+
+__global__ void k_pt_rowptr(const int32_t* __restrict__ rp, const int32_t* __restrict__ cidx,
+                            const int64_t* __restrict__ off, int64_t n, int64_t total,
+                            int64_t nc, int32_t* __restrict__ ptrp) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n && cidx[i] >= 0) ptrp[cidx[i]] = (int32_t)off[rp[i]];
+  if (i == 0) ptrp[nc] = (int32_t)total;
+}
+
+// ------------------------------------ Section 3.5: strength of connection
+__global__ void k_tv_init(double* __restrict__ X, int64_t n, uint64_t key, int level) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int k = 0; k < 4; k++) X[i * 4 + k] = counter_uniform(key, level, k, i);
+}
+
+struct X4Acc {
+  u128 s[4];
+  int bad;
+  int pad[3];
+};
+
+// One weighted-Jacobi sweep on L y = 0 for the four test vectors:
+// Y_i = (1 - omega) X_i + omega * (exact sum_j w_ij X_j) / d_i.
+struct JacobiOp {
+  using Acc = X4Acc;
+  const int32_t* __restrict__ col;
+  const double* __restrict__ w;
+  const double* __restrict__ d;
+  const double* __restrict__ X;
+  double* __restrict__ Y;
+  double keep, omega;
+  int* flags;
+  __device__ Acc identity() const {
+    Acc a;
+#pragma unroll
+    for (int k = 0; k < 4; k++) a.s[k] = 0;
+    a.bad = 0;
+    return a;
+  }
+  __device__ bool active(int64_t) const { return true; }
+  __device__ void accum(Acc& a, int64_t, int e) const {
+    const double we = w[e];
+    const double* xj = X + (int64_t)col[e] * 4;
+#pragma unroll
+    for (int k = 0; k < 4; k++) a.s[k] += xs_term(we * xj[k], a.bad);
+  }
+  __device__ void combine(Acc& a, const Acc& o) const {
+#pragma unroll
+    for (int k = 0; k < 4; k++) a.s[k] += o.s[k];
+    a.bad |= o.bad;
+  }
+  __device__ void finish(int64_t row, const Acc& a, int lane, int G) const {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      if (k % G != lane) continue;
+      const double t = xs_value(a.s[k]) / d[row];
+      Y[row * 4 + k] = keep * X[row * 4 + k] + omega * t;
+    }
+    if (lane == 0 && a.bad) atomicOr(flags, F_XSUM);
+  }
+};
+
+__device__ __forceinline__ double sq4(const double* x) {
+  return x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3];
+}
+
+// Affinity C_ij = (x_i . x_j)^2 / (|x_i|^2 |x_j|^2) per stored edge, written to S.
+struct AffinityOp {
+  using Acc = NoAcc;
+  const int32_t* __restrict__ col;
+  const double* __restrict__ X;
+  double* __restrict__ S;
+  __device__ Acc identity() const { return {0}; }
+  __device__ bool active(int64_t) const { return true; }
+  __device__ void accum(Acc&, int64_t row, int e) const {
+    const double* xi = X + row * 4;
+    const double* xj = X + (int64_t)col[e] * 4;
+    const double p = xi[0] * xj[0] + xi[1] * xj[1] + xi[2] * xj[2] + xi[3] * xj[3];
+    const double den = sq4(xi) * sq4(xj);
+    S[e] = den > 0.0 ? (p * p) / den : 0.0;
+  }
+  __device__ void combine(Acc&, const Acc&) const {}
+  __device__ void finish(int64_t, const Acc&, int, int) const {}
+};
+
+// Row maximum of non-negative doubles (exact, order free).
+struct RowMaxOp {
+  using Acc = VecAcc<double, 1>;
+  const double* __restrict__ val;
+  double* __restrict__ out;
+  __device__ Acc identity() const { return {{0.0}}; }
+  __device__ bool active(int64_t) const { return true; }
+  __device__ void accum(Acc& a, int64_t, int e) const {
+    const double v = val[e];
+    if (v > a.v[0]) a.v[0] = v;
+  }
+  __device__ void combine(Acc& a, const Acc& o) const {
+    if (o.v[0] > a.v[0]) a.v[0] = o.v[0];
+  }
+  __device__ void finish(int64_t row, const Acc& a, int lane, int) const {
+    if (lane == 0) out[row] = a.v[0];
+  }
+};
+
+// S_ij = C_ij / max(M_i, M_j), 0 when that maximum is 0.
+struct NormalizeOp {
+  using Acc = NoAcc;
+  const int32_t* __restrict__ col;
+  const double* __restrict__ M;
+  double* __restrict__ S;
+  __device__ Acc identity() const { return {0}; }
+  __device__ bool active(int64_t) const { return true; }
+  __device__ void accum(Acc&, int64_t row, int e) const {
+    const double mi = M[row], mj = M[col[e]];
+    const double mx = mi > mj ? mi : mj;
+    S[e] = mx > 0.0 ? S[e] / mx : 0.0;
+  }
+  __device__ void combine(Acc&, const Acc&) const {}
+  __device__ void finish(int64_t, const Acc&, int, int) const {}
+};
+
+// ------------------------------------------ Algorithm 3: voting aggregation
+struct VoteAcc {
+  double s;
+  int32_t st;  // packed status of the best neighbour, -1 = none
+  int32_t pad;
+};
+
+__device__ __forceinline__ bool vote_better(const VoteAcc& x, const VoteAcc& y) {
+  if (x.st < 0) return false;
+  if (y.st < 0) return true;
+  const int rx = x.st >> 30, ry = y.st >> 30;
+  if (rx != ry) return rx > ry;
+  if (x.s != y.s) return x.s > y.s;
+  return (x.st & kIdxMask) < (y.st & kIdxMask);
+}
+
+// d_i = S_filt (+)agg.(x)agg status for Undecided i; a Seed neighbour is
+// joined, an Undecided neighbour gets a vote.  Reads `status`, writes `next`.
+struct VoteOp {
+  using Acc = VoteAcc;
+  const int32_t* __restrict__ col;
+  const double* __restrict__ S;
+  const int32_t* __restrict__ status;
+  int32_t* __restrict__ next;
+  int32_t* __restrict__ votes;
+  double tau;
+  __device__ Acc identity() const { return {-1.0, -1, 0}; }
+  __device__ bool active(int64_t row) const { return (status[row] >> 30) == kUndecided; }
+  __device__ void accum(Acc& a, int64_t, int e) const {
+    const double s = S[e];
+    if (!(s >= tau)) return;
+    const VoteAcc c{s, status[col[e]], 0};
+    if (vote_better(c, a)) a = c;
+  }
+  __device__ void combine(Acc& a, const Acc& o) const {
+    if (vote_better(o, a)) a = o;
+  }
+  __device__ void finish(int64_t row, const Acc& a, int lane, int) const {
+    if (lane) return;
+    const int32_t st = status[row];
+    int32_t out = st;
+    if ((st >> 30) == kUndecided && a.st >= 0) {
+      const int r = a.st >> 30;
+      if (r == kSeed) out = (kDecided << 30) | (a.st & kIdxMask);
+      else if (r == kUndecided) atomicAdd(&votes[a.st & kIdxMask], 1);
+    }
+    next[row] = out;
+  }
+};
+
+__global__ void k_status_init(int32_t* __restrict__ status, int32_t* __restrict__ votes,
+                              int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  status[i] = (kUndecided << 30) | (int32_t)i;
+  votes[i] = 0;
+}
+
+__global__ void k_promote(int32_t* __restrict__ next, const int32_t* __restrict__ votes,
+                          int64_t n, int seed_votes) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  if (next[i] == ((kUndecided << 30) | (int32_t)i) && votes[i] >= seed_votes)
+    next[i] = (kSeed << 30) | (int32_t)i;
+}
+
+__global__ void k_root_flags(const int32_t* __restrict__ status, int64_t n,
+                             int32_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) flag[i] = (status[i] & kIdxMask) == i;
+}
+
+__global__ void k_agg_from_roots(const int32_t* __restrict__ status,
+                                 const int64_t* __restrict__ rank, int64_t n,
+                                 int32_t* __restrict__ agg) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) agg[i] = (int32_t)rank[status[i] & kIdxMask];
+}
+
+// --------------------------------------------------- Galerkin assembly
+__global__ void k_gal_flags(const int32_t* __restrict__ rowidx, const int32_t* __restrict__ col,
+                            const int32_t* __restrict__ agg, int64_t nnz,
+                            int32_t* __restrict__ flag) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < nnz) flag[e] = agg[rowidx[e]] != agg[col[e]];
+}
+
+__global__ void k_gal_emit(const int32_t* __restrict__ rowidx, const int32_t* __restrict__ col,
+                           const double* __restrict__ w, const int32_t* __restrict__ agg,
+                           const int32_t* __restrict__ flag, const int64_t* __restrict__ off,
+                           int64_t nnz, uint64_t* __restrict__ keys, double* __restrict__ vals) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= nnz || !flag[e]) return;
+  keys[off[e]] = ((uint64_t)agg[rowidx[e]] << 32) | (uint32_t)agg[col[e]];
+  vals[off[e]] = w[e];
+}
+
+__global__ void k_run_heads(const uint64_t* __restrict__ keys, int64_t m,
+                            int32_t* __restrict__ head) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < m) head[e] = (e == 0 || keys[e] != keys[e - 1]);
+}
+
+__global__ void k_run_starts(const int32_t* __restrict__ head, const int64_t* __restrict__ ridx,
+                             int64_t m, int64_t R, int32_t* __restrict__ start) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < m && head[e]) start[ridx[e]] = (int32_t)e;
+  if (e == 0) start[R] = (int32_t)m;
+}
+
+// Row pointer of a matrix whose entries are sorted by row = key >> shift:
+// ptr[r] = index of the first entry with row >= r.
+__global__ void k_rowptr_sorted(const uint64_t* __restrict__ keys, const int32_t* __restrict__ at,
+                                int64_t m, int shift, int64_t nrows, int32_t* __restrict__ ptr) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= m) return;
+  const int64_t r = (int64_t)(keys[at ? at[e] : e] >> shift);
+  const int64_t rprev = e == 0 ? -1 : (int64_t)(keys[at ? at[e - 1] : e - 1] >> shift);
+  for (int64_t q = rprev + 1; q <= r; q++) ptr[q] = (int32_t)e;
+  if (e == m - 1)
+    for (int64_t q = r + 1; q <= nrows; q++) ptr[q] = (int32_t)m;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_u64_to_i32(const uint64_t* __restrict__ in, int64_t n, int32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] = (int32_t)in[i];
+}
+
+__global__ void k_members_keys(const int32_t* __restrict__ agg, int64_t n,
+                               uint64_t* __restrict__ keys, uint64_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = (uint64_t)agg[i];
+  vals[i] = (uint64_t)i;
+}
+
+// -------------------------------------------- reductions (deterministic)
+enum { RED_SUM = 0, RED_DOT = 1, RED_DDOT = 2 };
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_red1(const double* __restrict__ a,
+                                                 const double* __restrict__ b,
+                                                 const double* __restrict__ d, int64_t n,
+                                                 double* __restrict__ partial) {
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    if (MODE == RED_SUM) s += a[i];
+    else if (MODE == RED_DOT) s += a[i] * b[i];
+    else s += d[i] * a[i] * a[i];
+  }
+  __shared__ double sm[kBlock];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int m = kBlock / 2; m > 0; m >>= 1) {
+    if ((int)threadIdx.x < m) sm[threadIdx.x] += sm[threadIdx.x + m];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
+}
+
+__global__ void k_red2(const double* __restrict__ partial, int nb, double* __restrict__ out) {
+  __shared__ double sm[kBlock];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kBlock) s += partial[i];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int m = kBlock / 2; m > 0; m >>= 1) {
+    if ((int)threadIdx.x < m) sm[threadIdx.x] += sm[threadIdx.x + m];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sm[0];
+}
+
+template <int MODE>
+static void reduce_dev(const double* a, const double* b, const double* d, int64_t n,
+                       double* partial, double* out, hipStream_t st) {
+  const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ceil_div(n, kBlock)));
+  hipLaunchKernelGGL((k_red1<MODE>), dim3(nb), dim3(kBlock), 0, st, a, b, d, n, partial);
+  hipLaunchKernelGGL(k_red2, dim3(1), dim3(kBlock), 0, st, partial, nb, out);
+}
+
+// ---------------------------------------------- Lanczos (Section 3.6)
+enum { LZ_AL = 0, LZ_BE = 64, LZ_B2 = 128, LZ_SCALE = 129, LZ_M = 130, LZ_STOP = 131,
+       LZ_SUM = 132, LZ_SIZE = 136 };
+
+__global__ void k_lz_start(double* __restrict__ q, double* __restrict__ qp, int64_t n,
+                           uint64_t key, int level) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  q[i] = counter_uniform(key, level, kLanczosStream, i);
+  qp[i] = 0.0;
+}
+
+__global__ void k_lz_center(double* __restrict__ q, int64_t n, const double* __restrict__ lz) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) q[i] -= lz[LZ_SUM] / (double)n;
+}
+
+__global__ void k_lz_scale(double* __restrict__ q, int64_t n, const double* __restrict__ lz) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) q[i] /= sqrt(lz[LZ_B2]);
+}
+
+__global__ void k_lz_init_scalars(double* lz) {
+  for (int i = threadIdx.x; i < LZ_SIZE; i += blockDim.x) lz[i] = 0.0;
+}
+
+// u <- D^-1 u - alpha_j q - beta_{j-1} q_prev
+__global__ void k_lz_update(double* __restrict__ u, const double* __restrict__ q,
+                            const double* __restrict__ qp, const double* __restrict__ d, int64_t n,
+                            const double* __restrict__ lz, int j) {
+  if (lz[LZ_STOP] != 0.0) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double a = lz[LZ_AL + j];
+  const double bp = j > 0 ? lz[LZ_BE + j - 1] : 0.0;
+  u[i] = u[i] / d[i] - a * q[i] - bp * qp[i];
+}
+
+__global__ void k_lz_beta(double* lz, int j, int steps) {
+  if (lz[LZ_STOP] != 0.0) return;
+  const double a = lz[LZ_AL + j];
+  const double bp = j > 0 ? lz[LZ_BE + j - 1] : 0.0;
+  const double b = sqrt(lz[LZ_B2]);
+  double scale = lz[LZ_SCALE];
+  if (fabs(a) + bp > scale) scale = fabs(a) + bp;
+  lz[LZ_SCALE] = scale;
+  lz[LZ_M] = (double)(j + 1);
+  if (j == steps - 1 || b <= 1e-12 * scale) lz[LZ_STOP] = 1.0;
+  else lz[LZ_BE + j] = b;
+}
+
+__global__ void k_lz_next(double* __restrict__ u, double* __restrict__ q, double* __restrict__ qp,
+                          int64_t n, const double* __restrict__ lz, int j) {
+  if (lz[LZ_STOP] != 0.0) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double b = lz[LZ_BE + j];
+  qp[i] = q[i];
+  q[i] = u[i] / b;
+}
+
+__device__ int sturm_below(const double* a, const double* b, int m, double x) {
+  int c = 0;
+  double q = 1.0;
+  for (int i = 0; i < m; i++) {
+    q = (a[i] - x) - (i > 0 ? (b[i - 1] * b[i - 1]) / q : 0.0);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0.0) c++;
+  }
+  return c;
+}
+
+// Largest eigenvalue of the Lanczos tridiagonal by Sturm-count bisection.
+__global__ void k_lz_eig(const double* __restrict__ lz, double* __restrict__ out) {
+  const int m = (int)lz[LZ_M];
+  const double* a = lz + LZ_AL;
+  const double* b = lz + LZ_BE;
+  if (m <= 0) {
+    *out = 0.0;
+    return;
+  }
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < m; i++) {
+    const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i < m - 1 ? fabs(b[i]) : 0.0);
+    lo = fmin(lo, a[i] - r);
+    hi = fmax(hi, a[i] + r);
+  }
+  hi += 1e-12 * fabs(hi) + 1e-300;
+  lo -= 1e-12 * fabs(lo) + 1e-300;
+  for (int it = 0; it < 400; it++) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_below(a, b, m, mid) == m) hi = mid;
+    else lo = mid;
+  }
+  *out = 0.5 * (lo + hi);
+}
+
+// --------------------------------------------- coarsest pseudo-inverse
+__global__ void k_dense_lap(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            const double* __restrict__ w, const double* __restrict__ d, int64_t n,
+                            double* __restrict__ M) {
+  const int64_t i = blockIdx.x;
+  const double inv_n = 1.0 / (double)n;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) M[i * n + j] = inv_n + (i == j ? d[i] : 0.0);
+  __syncthreads();
+  for (int e = rp[i] + threadIdx.x; e < rp[i + 1]; e += blockDim.x) M[i * n + col[e]] -= w[e];
+}
+
+// In-place Gauss-Jordan inversion of the SPD matrix L + 11^T/n (no pivoting),
+// one workgroup, for the small coarsest level.
+__global__ __launch_bounds__(1024) void k_gauss_jordan(double* __restrict__ M, int n,
+                                                       double* __restrict__ colbuf) {
+  for (int k = 0; k < n; k++) {
+    __syncthreads();
+    const double inv = 1.0 / M[(int64_t)k * n + k];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) colbuf[i] = M[(int64_t)i * n + k];
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+      M[(int64_t)k * n + j] = (j == k ? 1.0 : M[(int64_t)k * n + j]) * inv;
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += blockDim.x) {
+      const int i = (int)(t / n), j = (int)(t % n);
+      if (i == k) continue;
+      const double mkj = M[(int64_t)k * n + j];
+      M[t] = (j == k ? 0.0 : M[t]) - colbuf[i] * mkj;
+    }
+  }
+}
+
+__global__ void k_sub_inv_n(double* __restrict__ M, int64_t nn, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t < nn) M[t] -= 1.0 / (double)n;
+}
+
+__global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
+__global__ void k_copy_f64(const double* __restrict__ in, double* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] = in[i];
+}
+
+// ===================================================================== host
+namespace {
+
+struct Ctx {
+  lg_hierarchy* h;
+  hipStream_t st;
+  Arena tmp{(size_t)256 << 20};
+  int* flags = nullptr;  // device error flags
+  uint64_t key = 0;
+};
+
+void check_flags(Ctx& c) {
+  int f = 0;
+  LG_HIP(hipMemcpyAsync(&f, c.flags, sizeof(int), hipMemcpyDeviceToHost, c.st));
+  LG_HIP(hipStreamSynchronize(c.st));
+  if (f & F_ROWPTR) fail(LG_E_GRAPH, "row pointers are not a valid CSR offset array");
+  if (f & F_COL) fail(LG_E_GRAPH, "column index out of range");
+  if (f & F_LOOP) fail(LG_E_GRAPH, "self-loop (diagonal entry) in the adjacency");
+  if (f & F_ORDER) fail(LG_E_GRAPH, "row columns not strictly increasing (unsorted or duplicate)");
+  if (f & F_WEIGHT) fail(LG_E_GRAPH, "edge weight not finite and positive");
+  if (f & F_ASYM) fail(LG_E_GRAPH, "adjacency not symmetric");
+  if (f & F_XSUM) fail(LG_E_RANGE, "sum outside the exact-sum range (total weight too large)");
+}
+
+// Row sums and reciprocals of a level's adjacency.
+void level_diag(Ctx& c, Level& L) {
+  L.d = c.h->mem.get<double>(L.n);
+  L.dinv = c.h->mem.get<double>(L.n);
+  run_rows(L.sched, L.rp, RowXsumOp{L.w, L.d, L.dinv, c.flags}, c.st);
+}
+
+// Sorted (row << 32 | col, value) pairs -> CSR of `out` with exact sums of
+// equal keys (rows 0..nrows-1), then its schedule and diagonal.
+void assemble(Ctx& c, uint64_t* keys, double* vals, int64_t m, int64_t nrows, Level& out) {
+  Arena& tmp = c.tmp;
+  lg_hierarchy* h = c.h;
+  out.n = nrows;
+  out.rp = h->mem.get<int32_t>(nrows + 1);
+  if (m == 0) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblk(nrows + 1)), dim3(kBlock), 0, c.st, out.rp,
+                       nrows + 1, 0);
+    out.nnz = 0;
+    out.col = h->mem.get<int32_t>(1);
+    out.w = h->mem.get<double>(1);
+  } else {
+    int32_t* head = tmp.get<int32_t>(m);
+    int64_t* ridx = tmp.get<int64_t>(m + 1);
+    hipLaunchKernelGGL(k_run_heads, dim3(nblk(m)), dim3(kBlock), 0, c.st, keys, m, head);
+    const int64_t R = scan_i32_to_i64(head, ridx, m, tmp, c.st, true);
+    int32_t* start = tmp.get<int32_t>(R + 1);
+    hipLaunchKernelGGL(k_run_starts, dim3(nblk(m)), dim3(kBlock), 0, c.st, head, ridx, m, R, start);
+    out.nnz = R;
+    out.col = h->mem.get<int32_t>(R);
+    out.w = h->mem.get<double>(R);
+    Sched rs;
+    build_sched(rs, start, R, m, tmp, tmp, c.st);
+    {
+      ProfScope ps("galerkin_reduce", c.st, (double)m * 16.0 + (double)R * 12.0);
+      run_rows(rs, start, RunXsumOp{vals, keys, start, out.col, out.w, c.flags}, c.st);
+    }
+    hipLaunchKernelGGL(k_rowptr_sorted, dim3(nblk(R)), dim3(kBlock), 0, c.st, keys, start, R, 32,
+                       nrows, out.rp);
+    LG_LAUNCH_CHECK();
+  }
+  build_sched(out.sched, out.rp, out.n, out.nnz, h->mem, tmp, c.st);
+  level_diag(c, out);
+}
+
+void row_index(Ctx& c, const Level& L, int32_t* rowidx) {
+  run_rows(L.sched, L.rp, RowIdxOp{rowidx}, c.st);
+}
+
+// Algorithm 2 on level l; returns |F| and leaves keepC / pos (scan) in tmp.
+struct ElimChoice {
+  int64_t nf = 0, nc = 0;
+  int32_t* keepC = nullptr;
+  int64_t* pos = nullptr;
+  int32_t* z = nullptr;
+};
+
+ElimChoice elim_select(Ctx& c, Level& L) {
+  const lg_setup_opts& o = c.h->opts;
+  ElimChoice ch;
+  ch.keepC = c.tmp.get<int32_t>(L.n);
+  ch.pos = c.tmp.get<int64_t>(L.n + 1);
+  ch.z = o.keep_setup_data ? c.h->mem.get<int32_t>(L.n) : c.tmp.get<int32_t>(L.n);
+  {
+    ProfScope ps("elim_select", c.st, 4.0 * (L.n + 1) + 4.0 * L.nnz + 8.0 * L.n);
+    run_rows(L.sched, L.rp, ElimSelectOp{L.rp, L.col, o.elim_max_degree, o.hash_mode, ch.z, ch.keepC},
+             c.st);
+  }
+  ch.nc = scan_i32_to_i64(ch.keepC, ch.pos, L.n, c.tmp, c.st, true);
+  ch.nf = L.n - ch.nc;
+  return ch;
+}
+
+// Elimination level (Section 3.4): Schur complement onto C and the transfer data.
+void build_elim(Ctx& c, Level& L, const ElimChoice& ch, Level& out) {
+  lg_hierarchy* h = c.h;
+  Arena& tmp = c.tmp;
+  const int64_t n = L.n, nnz = L.nnz, nc = ch.nc;
+  L.type = LG_LEVEL_ELIM;
+  L.nc = nc;
+  L.nF = ch.nf;
+  if (h->opts.keep_setup_data) L.z = ch.z;
+  L.cidx = h->mem.get<int32_t>(n);
+  L.cvert = h->mem.get<int32_t>(nc);
+  hipLaunchKernelGGL(k_cidx, dim3(nblk(n)), dim3(kBlock), 0, c.st, ch.keepC, ch.pos, n, L.cidx,
+                     L.cvert);
+  int32_t* rowidx = tmp.get<int32_t>(nnz);
+  row_index(c, L, rowidx);
+  int32_t* cnt = tmp.get<int32_t>(nnz);
+  int32_t* ptflag = tmp.get<int32_t>(nnz);
+  hipLaunchKernelGGL(k_elim_count, dim3(nblk(nnz)), dim3(kBlock), 0, c.st, rowidx, L.col, L.rp,
+                     L.cidx, nnz, cnt, ptflag);
+  int64_t* off = tmp.get<int64_t>(nnz + 1);
+  const int64_t m = scan_i32_to_i64(cnt, off, nnz, tmp, c.st, true);
+  uint64_t* keys = tmp.get<uint64_t>(m);
+  double* vals = tmp.get<double>(m);
+  hipLaunchKernelGGL(k_elim_emit, dim3(nblk(nnz)), dim3(kBlock), 0, c.st, rowidx, L.rp, L.col, L.w,
+                     L.d, L.cidx, off, nnz, keys, vals);
+  LG_LAUNCH_CHECK();
+  const int b = bits_for(nc > 0 ? nc - 1 : 0);
+  radix_sort_pairs(keys, (uint64_t*)vals, m, digit_shifts(b, b), tmp, c.st);
+  // transfer data: F-part of P^T
+  int64_t* off2 = tmp.get<int64_t>(nnz + 1);
+  const int64_t npt = scan_i32_to_i64(ptflag, off2, nnz, tmp, c.st, true);
+  L.ptrp = h->mem.get<int32_t>(nc + 1);
+  L.ptf = h->mem.get<int32_t>(npt);
+  L.ptc = h->mem.get<double>(npt);
+  hipLaunchKernelGGL(k_pt_emit, dim3(nblk(nnz)), dim3(kBlock), 0, c.st, rowidx, L.col, L.w, L.d,
+                     ptflag, off2, nnz, L.ptf, L.ptc);
+  hipLaunchKernelGGL(k_pt_rowptr, dim3(nblk(n)), dim3(kBlock), 0, c.st, L.rp, L.cidx, off2, n, npt,
+                     nc, L.ptrp);
+  LG_LAUNCH_CHECK();
+  build_sched(L.ptsched, L.ptrp, nc, npt, h->mem, tmp, c.st);
+  L.nnzP = nc + npt;  // each eliminated vertex's entries appear once in P^T
+  assemble(c, keys, vals, m, nc, out);
+}
+
+// Section 3.5: four smoothed test vectors and the normalised affinity S.
+void strength(Ctx& c, Level& L, int level, double* S, double* X) {
+  const lg_setup_opts& o = c.h->opts;
+  Arena& tmp = c.tmp;
+  double* Y = tmp.get<double>(4 * L.n);
+  hipLaunchKernelGGL(k_tv_init, dim3(nblk(L.n)), dim3(kBlock), 0, c.st, X, L.n, c.key, level);
+  const double omega = o.tv_omega, keep = 1.0 - o.tv_omega;
+  double* src = X;
+  double* dst = Y;
+  for (int s = 0; s < o.tv_sweeps; s++) {
+    ProfScope ps("jacobi_xsum", c.st, 4.0 * (L.n + 1) + 12.0 * L.nnz + 8.0 * L.n + 64.0 * L.n);
+    run_rows(L.sched, L.rp, JacobiOp{L.col, L.w, L.d, src, dst, keep, omega, c.flags}, c.st);
+    std::swap(src, dst);
+  }
+  if (src != X)
+    hipLaunchKernelGGL(k_copy_f64, dim3(nblk(4 * L.n)), dim3(kBlock), 0, c.st, src, X, 4 * L.n);
+  double* M = tmp.get<double>(L.n);
+  {
+    ProfScope ps("affinity", c.st, 4.0 * (L.n + 1) + 12.0 * L.nnz + 32.0 * L.n);
+    run_rows(L.sched, L.rp, AffinityOp{L.col, X, S}, c.st);
+    run_rows(L.sched, L.rp, RowMaxOp{S, M}, c.st);
+    run_rows(L.sched, L.rp, NormalizeOp{L.col, M, S}, c.st);
+  }
+  LG_LAUNCH_CHECK();
+}
+
+// Algorithm 3; returns the number of aggregates and fills L.agg.
+int64_t aggregate(Ctx& c, Level& L, const double* S, int32_t** status_out, int32_t** votes_out) {
+  const lg_setup_opts& o = c.h->opts;
+  Arena& tmp = c.tmp;
+  const int64_t n = L.n;
+  const bool keep = o.keep_setup_data != 0;
+  int32_t* status = tmp.get<int32_t>(n);
+  int32_t* next = tmp.get<int32_t>(n);
+  int32_t* votes = keep ? c.h->mem.get<int32_t>(n) : tmp.get<int32_t>(n);
+  hipLaunchKernelGGL(k_status_init, dim3(nblk(n)), dim3(kBlock), 0, c.st, status, votes, n);
+  double tau = 1.0;
+  for (int it = 1; it <= o.agg_iters; it++) {
+    tau *= o.agg_filter_base;
+    {
+      ProfScope ps("vote", c.st, 4.0 * (n + 1) + 12.0 * L.nnz + 8.0 * n);
+      run_rows(L.sched, L.rp, VoteOp{L.col, S, status, next, votes, tau}, c.st);
+    }
+    hipLaunchKernelGGL(k_promote, dim3(nblk(n)), dim3(kBlock), 0, c.st, next, votes, n,
+                       o.seed_votes);
+    std::swap(status, next);
+  }
+  LG_LAUNCH_CHECK();
+  int32_t* flag = tmp.get<int32_t>(n);
+  int64_t* rank = tmp.get<int64_t>(n + 1);
+  hipLaunchKernelGGL(k_root_flags, dim3(nblk(n)), dim3(kBlock), 0, c.st, status, n, flag);
+  const int64_t nc = scan_i32_to_i64(flag, rank, n, tmp, c.st, true);
+  L.agg = c.h->mem.get<int32_t>(n);
+  hipLaunchKernelGGL(k_agg_from_roots, dim3(nblk(n)), dim3(kBlock), 0, c.st, status, rank, n, L.agg);
+  if (keep) {
+    int32_t* st_keep = c.h->mem.get<int32_t>(n);
+    LG_HIP(hipMemcpyAsync(st_keep, status, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.st));
+    *status_out = st_keep;
+    *votes_out = votes;
+  }
+  LG_LAUNCH_CHECK();
+  return nc;
+}
+
+// Members of each aggregate (CSR of R, increasing vertex id) and the
+// Galerkin product R L P as the exact inter-aggregate weight sums.
+void galerkin(Ctx& c, Level& L, int64_t nc, Level& out) {
+  lg_hierarchy* h = c.h;
+  Arena& tmp = c.tmp;
+  const int64_t n = L.n, nnz = L.nnz;
+  const int b = bits_for(nc > 0 ? nc - 1 : 0);
+  {
+    uint64_t* mk = tmp.get<uint64_t>(n);
+    uint64_t* mv = tmp.get<uint64_t>(n);
+    hipLaunchKernelGGL(k_members_keys, dim3(nblk(n)), dim3(kBlock), 0, c.st, L.agg, n, mk, mv);
+    radix_sort_pairs(mk, mv, n, digit_shifts(b, 0), tmp, c.st);
+    L.mem = h->mem.get<int32_t>(n);
+    L.mptr = h->mem.get<int32_t>(nc + 1);
+    hipLaunchKernelGGL(k_u64_to_i32, dim3(nblk(n)), dim3(kBlock), 0, c.st, mv, n, L.mem);
+    hipLaunchKernelGGL(k_rowptr_sorted, dim3(nblk(n)), dim3(kBlock), 0, c.st, mk,
+                       (const int32_t*)nullptr, n, 0, nc, L.mptr);
+    LG_LAUNCH_CHECK();
+    build_sched(L.msched, L.mptr, nc, n, h->mem, tmp, c.st);
+  }
+  int32_t* rowidx = tmp.get<int32_t>(nnz);
+  row_index(c, L, rowidx);
+  int32_t* flag = tmp.get<int32_t>(nnz);
+  hipLaunchKernelGGL(k_gal_flags, dim3(nblk(nnz)), dim3(kBlock), 0, c.st, rowidx, L.col, L.agg,
+                     nnz, flag);
+  int64_t* off = tmp.get<int64_t>(nnz + 1);
+  const int64_t m = scan_i32_to_i64(flag, off, nnz, tmp, c.st, true);
+  uint64_t* keys = tmp.get<uint64_t>(m);
+  double* vals = tmp.get<double>(m);
+  hipLaunchKernelGGL(k_gal_emit, dim3(nblk(nnz)), dim3(kBlock), 0, c.st, rowidx, L.col, L.w, L.agg,
+                     flag, off, nnz, keys, vals);
+  LG_LAUNCH_CHECK();
+  radix_sort_pairs(keys, (uint64_t*)vals, m, digit_shifts(b, b), tmp, c.st);
+  assemble(c, keys, vals, m, nc, out);
+}
+
+// lambda_max(D^-1 L) by eig_iters Lanczos steps in the D inner product.
+void lanczos(Ctx& c, Level& L, int level, double* out) {
+  const lg_setup_opts& o = c.h->opts;
+  Arena& tmp = c.tmp;
+  const int64_t n = L.n;
+  double* q = tmp.get<double>(n);
+  double* qp = tmp.get<double>(n);
+  double* u = tmp.get<double>(n);
+  double* lz = tmp.get<double>(LZ_SIZE);
+  double* part = tmp.get<double>(kRedBlocks);
+  const int steps = std::min(o.eig_iters, 64);
+  hipLaunchKernelGGL(k_lz_init_scalars, dim3(1), dim3(64), 0, c.st, lz);
+  if (n < 2 || steps < 1) {
+    hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(1), 0, c.st, lz, out);
+    return;
+  }
+  hipLaunchKernelGGL(k_lz_start, dim3(nblk(n)), dim3(kBlock), 0, c.st, q, qp, n, c.key, level);
+  reduce_dev<RED_SUM>(q, nullptr, nullptr, n, part, lz + LZ_SUM, c.st);
+  hipLaunchKernelGGL(k_lz_center, dim3(nblk(n)), dim3(kBlock), 0, c.st, q, n, lz);
+  reduce_dev<RED_DDOT>(q, nullptr, L.d, n, part, lz + LZ_B2, c.st);
+  hipLaunchKernelGGL(k_lz_scale, dim3(nblk(n)), dim3(kBlock), 0, c.st, q, n, lz);
+  for (int j = 0; j < steps; j++) {
+    LapOp<double, 1, LAP_SPMV> op{L.col, L.w, L.d, L.dinv, q, u, nullptr, nullptr, 0.0, 0.0};
+    run_rows(L.sched, L.rp, op, c.st);
+    reduce_dev<RED_DOT>(q, u, nullptr, n, part, lz + LZ_AL + j, c.st);
+    hipLaunchKernelGGL(k_lz_update, dim3(nblk(n)), dim3(kBlock), 0, c.st, u, q, qp, L.d, n, lz, j);
+    reduce_dev<RED_DDOT>(u, nullptr, L.d, n, part, lz + LZ_B2, c.st);
+    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(1), 0, c.st, lz, j, steps);
+    hipLaunchKernelGGL(k_lz_next, dim3(nblk(n)), dim3(kBlock), 0, c.st, u, q, qp, n, lz, j);
+  }
+  hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(1), 0, c.st, lz, out);
+  LG_LAUNCH_CHECK();
+}
+
+void coarsest(Ctx& c, Level& L) {
+  lg_hierarchy* h = c.h;
+  const int64_t n = L.n;
+  if (n > kDenseLimit)
+    fail(LG_E_ARG, "coarsening stalled: coarsest level has " + std::to_string(n) +
+                       " vertices (dense solve limit " + std::to_string(kDenseLimit) + ")");
+  h->Lplus = h->mem.get<double>(n * n);
+  hipLaunchKernelGGL(k_dense_lap, dim3((unsigned)n), dim3(kBlock), 0, c.st, L.rp, L.col, L.w, L.d,
+                     n, h->Lplus);
+  double* colbuf = c.tmp.get<double>(n);
+  hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, c.st, h->Lplus, (int)n, colbuf);
+  hipLaunchKernelGGL(k_sub_inv_n, dim3(nblk(n * n)), dim3(kBlock), 0, c.st, h->Lplus, n * n, n);
+  LG_LAUNCH_CHECK();
+}
+
+void make_f32(Ctx& c, Level& L) {
+  lg_hierarchy* h = c.h;
+  L.wf = h->mem.get<float>(L.nnz);
+  L.df = h->mem.get<float>(L.n);
+  L.dinvf = h->mem.get<float>(L.n);
+  if (L.nnz) hipLaunchKernelGGL(k_to_f32, dim3(nblk(L.nnz)), dim3(kBlock), 0, c.st, L.w, L.wf, L.nnz);
+  hipLaunchKernelGGL(k_to_f32, dim3(nblk(L.n)), dim3(kBlock), 0, c.st, L.d, L.df, L.n);
+  hipLaunchKernelGGL(k_to_f32, dim3(nblk(L.n)), dim3(kBlock), 0, c.st, L.dinv, L.dinvf, L.n);
+  if (L.type == LG_LEVEL_ELIM) {
+    const int64_t npt = L.nnzP - L.nc;
+    L.ptcf = h->mem.get<float>(npt);
+    if (npt)
+      hipLaunchKernelGGL(k_to_f32, dim3(nblk(npt)), dim3(kBlock), 0, c.st, L.ptc, L.ptcf, npt);
+  }
+  LG_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
+  const lg_setup_opts& o = h->opts;
+  Ctx c;
+  c.h = h;
+  c.st = st;
+  c.key = seed_key(o.seed);
+  c.flags = h->mem.get<int>(4);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, st, (int32_t*)c.flags, (int64_t)4, 0);
+  const int64_t n = g->n, nnz = g->nnz;
+  h->lev.emplace_back();
+  Level* L0 = &h->lev.back();
+  L0->n = n;
+  L0->nnz = nnz;
+  L0->rp = h->mem.get<int32_t>(n + 1);
+  L0->col = h->mem.get<int32_t>(nnz);
+  L0->w = h->mem.get<double>(nnz);
+  {
+    Arena::Mark m = c.tmp.mark();
+    int64_t* rp64 = c.tmp.get<int64_t>(n + 1);
+    const hipMemcpyKind kind = g->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    LG_HIP(hipMemcpyAsync(rp64, g->row_ptr, sizeof(int64_t) * (n + 1), kind, st));
+    if (nnz) {
+      LG_HIP(hipMemcpyAsync(L0->col, g->col, sizeof(int32_t) * nnz, kind, st));
+      LG_HIP(hipMemcpyAsync(L0->w, g->w, sizeof(double) * nnz, kind, st));
+    }
+    hipLaunchKernelGGL(k_rowptr_to32, dim3(nblk(n + 1)), dim3(kBlock), 0, st, rp64, L0->rp, n, nnz,
+                       c.flags);
+    LG_LAUNCH_CHECK();
+    check_flags(c);  // row pointers must be sane before any row pass
+    c.tmp.rewind(m);
+  }
+  build_sched(L0->sched, L0->rp, n, nnz, h->mem, c.tmp, st);
+  if (o.validate) {
+    run_rows(L0->sched, L0->rp, ValidateOp{L0->rp, L0->col, L0->w, n, c.flags}, st);
+    check_flags(c);
+  }
+  level_diag(c, *L0);
+  check_flags(c);
+  {
+    // total weight guard of the exact sums, and connectivity (Section 2.1)
+    Arena::Mark m = c.tmp.mark();
+    double* part = c.tmp.get<double>(kRedBlocks);
+    double* tot = c.tmp.get<double>(1);
+    reduce_dev<RED_SUM>(L0->d, nullptr, nullptr, n, part, tot, st);
+    double total = 0.0;
+    LG_HIP(hipMemcpyAsync(&total, tot, sizeof(double), hipMemcpyDeviceToHost, st));
+    LG_HIP(hipStreamSynchronize(st));
+    if (!(total < 0x1p62)) fail(LG_E_RANGE, "total edge weight must be below 2^62");
+    if (o.validate) {
+      int* parent = c.tmp.get<int>(n);
+      int* cnt = c.tmp.get<int>(2);
+      hipLaunchKernelGGL(k_iota, dim3(nblk(n)), dim3(kBlock), 0, st, parent, n);
+      hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, st, (int32_t*)cnt, (int64_t)2, 0);
+      run_rows(L0->sched, L0->rp, UniteOp{L0->col, parent, n}, st);
+      hipLaunchKernelGGL(k_count_roots, dim3(nblk(n)), dim3(kBlock), 0, st, parent, n, cnt);
+      LG_LAUNCH_CHECK();
+      int roots = 0;
+      LG_HIP(hipMemcpyAsync(&roots, cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+      LG_HIP(hipStreamSynchronize(st));
+      if (roots != 1)
+        fail(LG_E_DISCONNECTED, "graph has " + std::to_string(roots) + " connected components");
+    }
+    c.tmp.rewind(m);
+  }
+
+  h->lmax_dev = h->mem.get<double>(kMaxLevelCap);
+  int l = 0;
+  for (;;) {
+    Level* L = &h->lev[l];
+    const bool stop_here = (L->n + L->nnz <= o.coarsest_nnz) || (l + 1 >= o.max_levels) ||
+                           (l + 2 >= kMaxLevelCap);
+    if (stop_here) break;
+    Arena::Mark lm = c.tmp.mark();
+    if (o.elim_enable) {
+      ElimChoice ch = elim_select(c, *L);
+      if ((double)ch.nf > o.elim_min_fraction * (double)L->n) {
+        h->lev.emplace_back();
+        L = &h->lev[l];
+        build_elim(c, *L, ch, h->lev[l + 1]);
+        check_flags(c);
+        c.tmp.rewind(lm);
+        l++;
+        L = &h->lev[l];
+        if ((L->n + L->nnz <= o.coarsest_nnz) || (l + 1 >= o.max_levels) ||
+            (l + 2 >= kMaxLevelCap))
+          break;
+      }
+      c.tmp.rewind(lm);
+    }
+    // aggregation level
+    double* X = o.keep_setup_data ? h->mem.get<double>(4 * L->n) : c.tmp.get<double>(4 * L->n);
+    double* S = o.keep_setup_data ? h->mem.get<double>(L->nnz) : c.tmp.get<double>(L->nnz);
+    strength(c, *L, l, S, X);
+    check_flags(c);
+    int32_t *status = nullptr, *votes = nullptr;
+    const int64_t nc = aggregate(c, *L, S, &status, &votes);
+    if (o.keep_setup_data) {
+      L->X = X;
+      L->S = S;
+      L->status = status;
+      L->votes = votes;
+    }
+    if (nc >= L->n) {  // no progress: this level becomes the coarsest
+      L->agg = nullptr;
+      c.tmp.rewind(lm);
+      break;
+    }
+    h->lev.emplace_back();
+    L = &h->lev[l];
+    L->type = LG_LEVEL_AGG;
+    L->nc = nc;
+    galerkin(c, *L, nc, h->lev[l + 1]);
+    lanczos(c, *L, l, h->lmax_dev + l);
+    check_flags(c);
+    c.tmp.rewind(lm);
+    l++;
+  }
+  h->lev.resize(l + 1);
+  h->lev[l].type = LG_LEVEL_COARSEST;
+  h->lev[l].nc = 0;
+  coarsest(c, h->lev[l]);
+  if (o.precision == LG_MIXED)
+    for (int i = 0; i < l; i++) make_f32(c, h->lev[i]);
+  std::vector<double> lm(l + 1, 0.0);
+  LG_HIP(hipMemcpyAsync(lm.data(), h->lmax_dev, sizeof(double) * (l + 1), hipMemcpyDeviceToHost, st));
+  LG_HIP(hipStreamSynchronize(st));
+  for (int i = 0; i <= l; i++) h->lev[i].lmax = h->lev[i].type == LG_LEVEL_AGG ? lm[i] : 0.0;
+  check_flags(c);
+}
+
+}  // namespace lg

@@ -1,0 +1,811 @@
+// solve.hip -- the solve phase (Algorithm 1 as a preconditioner for CG, or
+// the K-cycle inside flexible CG; Sections 2.3.2, 3.6, 3.7, 4) for k
+// right-hand sides at once.  Multi-vectors are n x K row-major with K the
+// padded batch width (a power of two up to 32); every kernel streams the
+// level's CSR once for all K columns.
+//
+// Precision: T = double (FP64) or float (the mixed form: hierarchy values,
+// smoother and transfers in fp32; the outer Krylov method, its dot products
+// and residuals, and the coarsest dense solve stay in fp64).
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "impl.h"
+#include "ops.h"
+
+namespace lg {
+
+static inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)ceil_div(n, b); }
+
+// ------------------------------------------------------- vector kernels
+template <typename T, int K>
+__global__ void k_cheb_zero(const T* __restrict__ b, const T* __restrict__ dinv,
+                            T* __restrict__ p, T* __restrict__ x, int64_t n, T inv_theta) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n * K) return;
+  const T v = dinv[i / K] * b[i] * inv_theta;
+  p[i] = v;
+  x[i] = v;
+}
+
+template <typename T, int K>
+__global__ void k_agg_prolong(const T* __restrict__ x, const T* __restrict__ xc,
+                              const int32_t* __restrict__ agg, T* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n * K) return;
+  const int64_t row = i / K;
+  out[i] = x[i] + xc[(int64_t)agg[row] * K + (i - row * K)];
+}
+
+// x = P_elim x_c + [D_FF^-1 b_F; 0] (Section 3.4, additive two-level form)
+template <typename T, int K>
+__global__ void k_elim_prolong(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                               const T* __restrict__ w, const T* __restrict__ dinv,
+                               const int32_t* __restrict__ cidx, const T* __restrict__ xc,
+                               const T* __restrict__ b, T* __restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n * K) return;
+  const int64_t row = i / K;
+  const int c = (int)(i - row * K);
+  const int ci = cidx[row];
+  if (ci >= 0) {
+    x[i] = xc[(int64_t)ci * K + c];
+    return;
+  }
+  const T di = dinv[row];
+  T s = T(0);
+  for (int e = rp[row]; e < rp[row + 1]; e++) s += (w[e] * di) * xc[(int64_t)cidx[col[e]] * K + c];
+  x[i] = s + b[i] * di;
+}
+
+// b_c[I] = sum of r over the members of aggregate I (R r, Section 3.5)
+template <typename T, int K>
+struct GatherSumOp {
+  using Acc = VecAcc<T, K>;
+  const int32_t* __restrict__ idx;
+  const T* __restrict__ src;
+  T* __restrict__ out;
+  __device__ Acc identity() const {
+    Acc a;
+#pragma unroll
+    for (int c = 0; c < K; c++) a.v[c] = T(0);
+    return a;
+  }
+  __device__ bool active(int64_t) const { return true; }
+  __device__ void accum(Acc& a, int64_t, int e) const {
+    const T* s = src + (int64_t)idx[e] * K;
+#pragma unroll
+    for (int c = 0; c < K; c++) a.v[c] += s[c];
+  }
+  __device__ void combine(Acc& a, const Acc& o) const {
+#pragma unroll
+    for (int c = 0; c < K; c++) a.v[c] += o.v[c];
+  }
+  __device__ void finish(int64_t row, const Acc& a, int lane, int G) const {
+#pragma unroll
+    for (int c = 0; c < K; c++)
+      if (c % G == lane) out[row * K + c] = a.v[c];
+  }
+};
+
+// b_c[a'] = b[a] + sum over eliminated neighbours f of (w_af / d_f) b_f  (P_elim^T b)
+template <typename T, int K>
+struct PtOp {
+  using Acc = VecAcc<T, K>;
+  const int32_t* __restrict__ ptf;
+  const T* __restrict__ ptc;
+  const int32_t* __restrict__ cvert;
+  const T* __restrict__ b;
+  T* __restrict__ bc;
+  __device__ Acc identity() const {
+    Acc a;
+#pragma unroll
+    for (int c = 0; c < K; c++) a.v[c] = T(0);
+    return a;
+  }
+  __device__ bool active(int64_t) const { return true; }
+  __device__ void accum(Acc& a, int64_t, int e) const {
+    const T cf = ptc[e];
+    const T* s = b + (int64_t)ptf[e] * K;
+#pragma unroll
+    for (int c = 0; c < K; c++) a.v[c] += cf * s[c];
+  }
+  __device__ void combine(Acc& a, const Acc& o) const {
+#pragma unroll
+    for (int c = 0; c < K; c++) a.v[c] += o.v[c];
+  }
+  __device__ void finish(int64_t row, const Acc& a, int lane, int G) const {
+    const int64_t v = cvert[row];
+#pragma unroll
+    for (int c = 0; c < K; c++)
+      if (c % G == lane) bc[row * K + c] = b[v * K + c] + a.v[c];
+  }
+};
+
+// Coarsest level: x = L^+ b with the fp64 dense pseudo-inverse; one wavefront per row.
+template <typename T, int K>
+__global__ __launch_bounds__(kBlock) void k_coarse(const double* __restrict__ Lp,
+                                                   const T* __restrict__ b, T* __restrict__ x,
+                                                   int64_t n) {
+  const int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double acc[K];
+#pragma unroll
+  for (int c = 0; c < K; c++) acc[c] = 0.0;
+  for (int64_t j = lane; j < n; j += 64) {
+    const double l = Lp[row * n + j];
+#pragma unroll
+    for (int c = 0; c < K; c++) acc[c] += l * (double)b[j * K + c];
+  }
+#pragma unroll
+  for (int c = 0; c < K; c++) {
+    double v = acc[c];
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+    if (lane == (c & 63)) x[row * K + c] = (T)v;
+  }
+}
+
+template <typename TI, typename TO>
+__global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < m) out[i] = (TO)in[i];
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, int64_t m, T v) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < m) p[i] = v;
+}
+
+__global__ void k_pad_in(const double* __restrict__ B, int k, double* __restrict__ out, int K,
+                         int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n * K) return;
+  const int64_t row = i / K;
+  const int c = (int)(i - row * K);
+  out[i] = c < k ? B[row * k + c] : 0.0;
+}
+
+__global__ void k_pad_out(const double* __restrict__ in, int K, double* __restrict__ X, int k,
+                          int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n * k) return;
+  const int64_t row = i / k;
+  const int c = (int)(i - row * k);
+  X[i] = in[row * K + c];
+}
+
+// Two-stage deterministic column dot products: ND products (a_d . b_d) per
+// column, or column sums where b_d is null.  Fixed grid and reduction order.
+template <typename T, int K, int ND>
+__global__ __launch_bounds__(kBlock) void k_dots(const T* __restrict__ a0, const T* __restrict__ b0,
+                                                 const T* __restrict__ a1, const T* __restrict__ b1,
+                                                 int64_t m, double* __restrict__ partial) {
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * kBlock) {
+    s0 += b0 ? (double)a0[i] * (double)b0[i] : (double)a0[i];
+    if (ND > 1) s1 += (double)a1[i] * (double)b1[i];
+  }
+  __shared__ double sm[ND][kBlock];
+  sm[0][threadIdx.x] = s0;
+  if (ND > 1) sm[ND - 1][threadIdx.x] = s1;
+  __syncthreads();
+  if ((int)threadIdx.x < K) {
+    for (int d = 0; d < ND; d++) {
+      double t = 0.0;
+      for (int q = threadIdx.x; q < kBlock; q += K) t += sm[d][q];
+      partial[((int64_t)blockIdx.x * ND + d) * K + threadIdx.x] = t;
+    }
+  }
+}
+
+template <int K, int ND>
+__global__ void k_dots_final(const double* __restrict__ partial, int nb, double* __restrict__ out0,
+                             double* __restrict__ out1) {
+  const int t = threadIdx.x;
+  if (t >= ND * K) return;
+  const int d = t / K, c = t % K;
+  double s = 0.0;
+  for (int b = 0; b < nb; b++) s += partial[((int64_t)b * ND + d) * K + c];
+  (d == 0 ? out0 : out1)[c] = s;
+}
+
+template <int K>
+__global__ void k_sub_mean(double* __restrict__ v, const double* __restrict__ sums, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n * K) return;
+  v[i] -= sums[i % K] / (double)n;
+}
+
+// alpha = num / (p . q) for active columns; a non-positive p . q is a breakdown.
+template <int K>
+__global__ void k_alpha(double* __restrict__ scal, int flexible) {
+  const int c = threadIdx.x;
+  if (c >= K) return;
+  const double act = scal[S_ACTIVE * K + c];
+  const double pq = scal[S_PQ * K + c];
+  const double num = flexible ? scal[S_PR * K + c] : scal[S_RZ * K + c];
+  double a = 0.0;
+  if (act > 0.0) {
+    if (pq > 0.0) a = num / pq;
+    else {
+      scal[S_ACTIVE * K + c] = 0.0;
+      scal[S_TR * K + c] = 1.0;  // breakdown
+    }
+  }
+  scal[S_ALPHA * K + c] = a;
+}
+
+template <int K>
+__global__ void k_beta(double* __restrict__ scal, int flexible) {
+  const int c = threadIdx.x;
+  if (c >= K) return;
+  const double act = scal[S_ACTIVE * K + c];
+  double b = 0.0;
+  if (act > 0.0) {
+    if (flexible) {
+      const double pq = scal[S_PQ * K + c];
+      b = pq > 0.0 ? -scal[S_ZQ * K + c] / pq : 0.0;
+    } else {
+      const double rz = scal[S_RZ * K + c];
+      const double rz2 = scal[S_TMP * K + c];
+      b = rz != 0.0 ? rz2 / rz : 0.0;
+      scal[S_RZ * K + c] = rz2;
+    }
+  }
+  scal[S_BETA * K + c] = b;
+}
+
+template <int K>
+__global__ void k_update_xr(double* __restrict__ x, double* __restrict__ r,
+                            const double* __restrict__ p, const double* __restrict__ q,
+                            const double* __restrict__ scal, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n * K) return;
+  const double a = scal[S_ALPHA * K + (i % K)];
+  x[i] += a * p[i];
+  r[i] -= a * q[i];
+}
+
+template <int K>
+__global__ void k_xpby(double* __restrict__ p, const double* __restrict__ z,
+                       const double* __restrict__ scal, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n * K) return;
+  p[i] = z[i] + scal[S_BETA * K + (i % K)] * p[i];
+}
+
+// p = z only in restarted columns (flag[c] = 1)
+template <int K>
+__global__ void k_restart_p(double* __restrict__ p, const double* __restrict__ z,
+                            const double* __restrict__ flag, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n * K) return;
+  if (flag[i % K] > 0.0) p[i] = z[i];
+}
+
+// ---- inner FCG(2) scalars of the K-cycle: [d1 a1 alpha1 zq d2 a2] x K
+template <int K>
+__global__ void k_fcg_alpha1(double* __restrict__ ks) {
+  const int c = threadIdx.x;
+  if (c >= K) return;
+  const double d1 = ks[0 * K + c], a1 = ks[1 * K + c];
+  ks[2 * K + c] = d1 > 0.0 ? a1 / d1 : 0.0;
+}
+
+template <typename T, int K>
+__global__ void k_fcg_step1(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p1,
+                            const T* __restrict__ q1, const double* __restrict__ ks, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n * K) return;
+  const T a = (T)ks[2 * K + (i % K)];
+  x[i] = a * p1[i];
+  r[i] -= a * q1[i];
+}
+
+template <typename T, int K>
+__global__ void k_fcg_p2(T* __restrict__ z, const T* __restrict__ p1,
+                         const double* __restrict__ ks, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n * K) return;
+  const int c = (int)(i % K);
+  const double d1 = ks[0 * K + c];
+  const T g = (T)(d1 > 0.0 ? ks[3 * K + c] / d1 : 0.0);
+  z[i] -= g * p1[i];
+}
+
+template <typename T, int K>
+__global__ void k_fcg_final(T* __restrict__ x, const T* __restrict__ p2,
+                            const double* __restrict__ ks, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n * K) return;
+  const int c = (int)(i % K);
+  const double d2 = ks[4 * K + c];
+  const T a = (T)(d2 > 0.0 ? ks[5 * K + c] / d2 : 0.0);
+  x[i] += a * p2[i];
+}
+
+// ================================================================ host
+template <typename T>
+struct Vals {
+  const T *w, *d, *dinv, *ptc;
+};
+template <typename T>
+inline Vals<T> vals_of(const Level& L);
+template <>
+inline Vals<double> vals_of<double>(const Level& L) {
+  return {L.w, L.d, L.dinv, L.ptc};
+}
+template <>
+inline Vals<float> vals_of<float>(const Level& L) {
+  return {L.wf, L.df, L.dinvf, L.ptcf};
+}
+
+inline double spmm_bytes(const Level& L, int K, int s, int vecs) {
+  return 4.0 * (L.n + 1) + (double)L.nnz * (4 + s) + (double)L.n * s + (double)vecs * K * L.n * s;
+}
+
+template <typename T, int K>
+struct Engine {
+  lg_hierarchy* h;
+  hipStream_t st;
+
+  template <int MODE>
+  void lap(const Level& L, const T* x, T* y, const T* b, T* p, T c1, T c2, const char* fam,
+           int vecs) {
+    Vals<T> v = vals_of<T>(L);
+    LapOp<T, K, MODE> op{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2};
+    ProfScope ps(fam, st, spmm_bytes(L, K, (int)sizeof(T), vecs) + (MODE >= LAP_CHEB ? 8.0 * L.n : 0));
+    run_rows(L.sched, L.rp, op, st);
+  }
+
+  template <int ND>
+  void dots(const T* a0, const T* b0, const T* a1, const T* b1, int64_t n, double* out0,
+            double* out1) {
+    const int64_t m = n * K;
+    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ceil_div(m, kBlock)));
+    hipLaunchKernelGGL((k_dots<T, K, ND>), dim3(nb), dim3(kBlock), 0, st, a0, b0, a1, b1, m, h->red);
+    hipLaunchKernelGGL((k_dots_final<K, ND>), dim3(1), dim3(64), 0, st, (const double*)h->red, nb,
+                       out0, out1);
+  }
+
+  // Algorithm 1 from level l with zero initial guess; returns the buffer holding x.
+  T* level(int l, const T* b) {
+    Level& L = h->lev[l];
+    const int64_t n = L.n;
+    T* x = (T*)L.vx;
+    if (L.type == LG_LEVEL_COARSEST) {
+      ProfScope ps("coarse", st, 8.0 * n * n + 2.0 * K * n * sizeof(T));
+      hipLaunchKernelGGL((k_coarse<T, K>), dim3(nblk(n, kBlock / 64)), dim3(kBlock), 0, st, h->Lplus,
+                         b, x, n);
+      return x;
+    }
+    Level& C = h->lev[l + 1];
+    Vals<T> v = vals_of<T>(L);
+    if (L.type == LG_LEVEL_ELIM) {
+      T* bc = (T*)C.vb;
+      {
+        ProfScope ps("restrict", st, 0.0);
+        run_rows(L.ptsched, L.ptrp, PtOp<T, K>{L.ptf, v.ptc, L.cvert, b, bc}, st);
+      }
+      const T* xc = level(l + 1, bc);  // elimination interpolates exactly: no Krylov step here
+      ProfScope ps("prolong", st, 0.0);
+      hipLaunchKernelGGL((k_elim_prolong<T, K>), dim3(nblk(n * K)), dim3(kBlock), 0, st, L.rp, L.col,
+                         v.w, v.dinv, L.cidx, xc, b, x, n);
+      return x;
+    }
+    // aggregation level
+    T* x2 = (T*)L.vx2;
+    T* r = (T*)L.vr;
+    T* p = (T*)L.vp;
+    const lg_setup_opts& o = h->opts;
+    const int deg = o.cheb_degree;
+    const double lo = o.cheb_lo * L.lmax, hi = o.cheb_hi * L.lmax;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+    const double sigma = theta / delta;
+    const bool smooth = deg >= 1 && L.lmax > 0.0;
+    T* cur = x;
+    T* nxt = x2;
+    if (smooth) {
+      hipLaunchKernelGGL((k_cheb_zero<T, K>), dim3(nblk(n * K)), dim3(kBlock), 0, st, b, v.dinv, p,
+                         cur, n, (T)(1.0 / theta));
+      double rho = 1.0 / sigma;
+      for (int s = 1; s < deg; s++) {
+        const double rho1 = 1.0 / (2.0 * sigma - rho);
+        lap<LAP_CHEB>(L, cur, nxt, b, p, (T)(rho1 * rho), (T)(2.0 * rho1 / delta), "cheb", 5);
+        std::swap(cur, nxt);
+        rho = rho1;
+      }
+    } else {
+      hipLaunchKernelGGL((k_fill<T>), dim3(nblk(n * K)), dim3(kBlock), 0, st, cur, n * K, T(0));
+    }
+    lap<LAP_RESID>(L, cur, r, b, nullptr, T(0), T(0), "resid", 3);
+    T* bc = (T*)C.vb;
+    {
+      ProfScope ps("restrict", st, 4.0 * (L.nc + 1) + 4.0 * n + 2.0 * K * n * sizeof(T));
+      run_rows(L.msched, L.mptr, GatherSumOp<T, K>{L.mem, r, bc}, st);
+    }
+    const T* xc = (o.cycle == LG_CYCLE_K && C.type != LG_LEVEL_COARSEST) ? fcg2(l + 1, bc)
+                                                                          : level(l + 1, bc);
+    {
+      ProfScope ps("prolong", st, 4.0 * n + 3.0 * K * n * sizeof(T));
+      hipLaunchKernelGGL((k_agg_prolong<T, K>), dim3(nblk(n * K)), dim3(kBlock), 0, st, cur, xc,
+                         L.agg, nxt, n);
+      std::swap(cur, nxt);
+    }
+    if (smooth) {
+      lap<LAP_CHEB_FIRST>(L, cur, nxt, b, p, T(0), (T)(1.0 / theta), "cheb", 4);
+      std::swap(cur, nxt);
+      double rho = 1.0 / sigma;
+      for (int s = 1; s < deg; s++) {
+        const double rho1 = 1.0 / (2.0 * sigma - rho);
+        lap<LAP_CHEB>(L, cur, nxt, b, p, (T)(rho1 * rho), (T)(2.0 * rho1 / delta), "cheb", 5);
+        std::swap(cur, nxt);
+        rho = rho1;
+      }
+    }
+    return cur;
+  }
+
+  // Two flexible-CG iterations on L_l x = b preconditioned by the cycle from
+  // level l (the coarse solve of the K-cycle, Section 3.7).
+  T* fcg2(int l, const T* b) {
+    Level& C = h->lev[l];
+    const int64_t n = C.n;
+    T* r = (T*)C.kr;
+    T* p1 = (T*)C.kp1;
+    T* q1 = (T*)C.kq1;
+    T* q2 = (T*)C.kz;
+    T* x = (T*)C.kx;
+    double* ks = C.kscal;
+    const unsigned g = nblk(n * K);
+    LG_HIP(hipMemcpyAsync(r, b, sizeof(T) * n * K, hipMemcpyDeviceToDevice, st));
+    const T* z = level(l, r);
+    LG_HIP(hipMemcpyAsync(p1, z, sizeof(T) * n * K, hipMemcpyDeviceToDevice, st));
+    lap<LAP_SPMV>(C, p1, q1, nullptr, nullptr, T(0), T(0), "spmm_inner", 2);
+    dots<2>(p1, q1, p1, r, n, ks + 0 * K, ks + 1 * K);
+    hipLaunchKernelGGL((k_fcg_alpha1<K>), dim3(1), dim3(64), 0, st, ks);
+    hipLaunchKernelGGL((k_fcg_step1<T, K>), dim3(g), dim3(kBlock), 0, st, x, r, p1, q1,
+                       (const double*)ks, n);
+    T* z2 = level(l, r);
+    dots<1>(z2, q1, nullptr, nullptr, n, ks + 3 * K, nullptr);
+    hipLaunchKernelGGL((k_fcg_p2<T, K>), dim3(g), dim3(kBlock), 0, st, z2, p1, (const double*)ks, n);
+    lap<LAP_SPMV>(C, z2, q2, nullptr, nullptr, T(0), T(0), "spmm_inner", 2);
+    dots<2>(z2, q2, z2, r, n, ks + 4 * K, ks + 5 * K);
+    hipLaunchKernelGGL((k_fcg_final<T, K>), dim3(g), dim3(kBlock), 0, st, x, z2, (const double*)ks,
+                       n);
+    LG_LAUNCH_CHECK();
+    return x;
+  }
+
+  // z = M r (fp64 in and out) with M one cycle in precision T.
+  void precond(const double* r, double* z) {
+    const Level& L0 = h->lev[0];
+    const int64_t m = L0.n * K;
+    const T* in;
+    if (sizeof(T) == sizeof(double)) {
+      in = (const T*)r;
+    } else {
+      hipLaunchKernelGGL((k_convert<double, T>), dim3(nblk(m)), dim3(kBlock), 0, st, r,
+                         (T*)h->cyc_in, m);
+      in = (const T*)h->cyc_in;
+    }
+    const T* res = level(0, in);
+    hipLaunchKernelGGL((k_convert<T, double>), dim3(nblk(m)), dim3(kBlock), 0, st, res, z, m);
+    LG_LAUNCH_CHECK();
+  }
+};
+
+// fp64 Laplacian product on level l for K columns (outer Krylov method)
+template <int K>
+void lap64(lg_hierarchy* h, int l, const double* x, double* y, const double* b, hipStream_t st,
+           const char* fam) {
+  const Level& L = h->lev[l];
+  ProfScope ps(fam, st, spmm_bytes(L, K, 8, b ? 3 : 2));
+  if (b) {
+    LapOp<double, K, LAP_RESID> op{L.col, L.w, L.d, L.dinv, x, y, b, nullptr, 0.0, 0.0};
+    run_rows(L.sched, L.rp, op, st);
+  } else {
+    LapOp<double, K, LAP_SPMV> op{L.col, L.w, L.d, L.dinv, x, y, nullptr, nullptr, 0.0, 0.0};
+    run_rows(L.sched, L.rp, op, st);
+  }
+}
+
+// Work of one cycle in finest-residual units, following the same recursion
+// as Engine::level / fcg2 (Section 2.3.1: operator nonzeros per application).
+static double cycle_work(const lg_hierarchy* h, int l) {
+  const Level& L = h->lev[l];
+  const double unit = (double)(h->lev[0].n + h->lev[0].nnz);
+  const double nnzL = (double)(L.n + L.nnz);
+  if (L.type == LG_LEVEL_COARSEST) return (double)L.n * (double)L.n / unit;
+  if (L.type == LG_LEVEL_ELIM)
+    return (2.0 * L.nnzP + (double)L.nF) / unit + cycle_work(h, l + 1);
+  const int deg = h->opts.cheb_degree;
+  double w = ((2.0 * deg) * nnzL + 2.0 * L.n) / unit;
+  const Level& C = h->lev[l + 1];
+  if (h->opts.cycle == LG_CYCLE_K && C.type != LG_LEVEL_COARSEST)
+    w += 2.0 * (C.n + C.nnz) / unit + 2.0 * cycle_work(h, l + 1);
+  else
+    w += cycle_work(h, l + 1);
+  return w;
+}
+
+template <typename T, int K>
+lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, int max_iter,
+              hipStream_t st, lg_rhs_info* info) {
+  Engine<T, K> eng{h, st};
+  const Level& L0 = h->lev[0];
+  const int64_t n = L0.n;
+  const int64_t m = n * K;
+  const unsigned g = nblk(m);
+  const bool flex = h->opts.cycle == LG_CYCLE_K;
+  double* sc = h->scal;
+  double* hs = h->host_scal;
+  auto sl = [&](int slot) { return sc + slot * K; };
+  auto read_scal = [&]() {
+    LG_HIP(hipMemcpyAsync(hs, sc, sizeof(double) * S_COUNT * K, hipMemcpyDeviceToHost, st));
+    LG_HIP(hipStreamSynchronize(st));
+  };
+  auto write_slot = [&](int slot, const std::vector<double>& v) {
+    for (int c = 0; c < K; c++) hs[slot * K + c] = v[c];
+    LG_HIP(hipMemcpyAsync(sc + slot * K, hs + slot * K, sizeof(double) * K, hipMemcpyHostToDevice,
+                          st));
+  };
+  auto project64 = [&](double* v) {
+    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ceil_div(m, kBlock)));
+    hipLaunchKernelGGL((k_dots<double, K, 1>), dim3(nb), dim3(kBlock), 0, st, v,
+                       (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, m,
+                       h->red);
+    hipLaunchKernelGGL((k_dots_final<K, 1>), dim3(1), dim3(64), 0, st, (const double*)h->red, nb,
+                       sl(S_MEAN), (double*)nullptr);
+    hipLaunchKernelGGL((k_sub_mean<K>), dim3(g), dim3(kBlock), 0, st, v, (const double*)sl(S_MEAN), n);
+  };
+  auto dot64 = [&](const double* a, const double* b, int slot) {
+    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ceil_div(m, kBlock)));
+    hipLaunchKernelGGL((k_dots<double, K, 1>), dim3(nb), dim3(kBlock), 0, st, a, b,
+                       (const double*)nullptr, (const double*)nullptr, m, h->red);
+    hipLaunchKernelGGL((k_dots_final<K, 1>), dim3(1), dim3(64), 0, st, (const double*)h->red, nb,
+                       sl(slot), (double*)nullptr);
+  };
+  auto dot64x2 = [&](const double* a0, const double* b0, const double* a1, const double* b1,
+                     int s0, int s1) {
+    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ceil_div(m, kBlock)));
+    hipLaunchKernelGGL((k_dots<double, K, 2>), dim3(nb), dim3(kBlock), 0, st, a0, b0, a1, b1, m,
+                       h->red);
+    hipLaunchKernelGGL((k_dots_final<K, 2>), dim3(1), dim3(64), 0, st, (const double*)h->red, nb,
+                       sl(s0), sl(s1));
+  };
+
+  const double cw = cycle_work(h, 0);
+  std::vector<double> bn(K, 0.0), relres(K, 0.0), work(K, 0.0), active(K, 0.0), zero(K, 0.0);
+  std::vector<int> iters(K, 0);
+  std::vector<int> converged(K, 0);
+
+  hipLaunchKernelGGL(k_fill<double>, dim3(nblk(S_COUNT * K)), dim3(kBlock), 0, st, sc,
+                     (int64_t)S_COUNT * K, 0.0);
+  hipLaunchKernelGGL(k_pad_in, dim3(g), dim3(kBlock), 0, st, B, k, h->pb, K, n);
+  project64(h->pb);
+  dot64(h->pb, h->pb, S_BN);
+  read_scal();
+  for (int c = 0; c < K; c++) {
+    bn[c] = std::sqrt(hs[S_BN * K + c]);
+    active[c] = (c < k && bn[c] > 0.0) ? 1.0 : 0.0;
+    converged[c] = active[c] == 0.0;
+  }
+  write_slot(S_ACTIVE, active);
+  hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(kBlock), 0, st, h->px, m, 0.0);
+  LG_HIP(hipMemcpyAsync(h->pr, h->pb, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+  auto any_active = [&]() {
+    for (int c = 0; c < K; c++)
+      if (active[c] > 0.0) return true;
+    return false;
+  };
+  if (any_active()) {
+    eng.precond(h->pr, h->pz);
+    project64(h->pz);
+    for (int c = 0; c < K; c++) work[c] += active[c] > 0.0 ? cw : 0.0;
+    LG_HIP(hipMemcpyAsync(h->pp, h->pz, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    dot64(h->pr, h->pz, S_RZ);
+  }
+  for (int it = 1; it <= max_iter && any_active(); it++) {
+    lap64<K>(h, 0, h->pp, h->pq, nullptr, st, "spmm");
+    if (flex) dot64x2(h->pp, h->pq, h->pp, h->pr, S_PQ, S_PR);
+    else dot64(h->pp, h->pq, S_PQ);
+    hipLaunchKernelGGL((k_alpha<K>), dim3(1), dim3(64), 0, st, sc, flex ? 1 : 0);
+    hipLaunchKernelGGL((k_update_xr<K>), dim3(g), dim3(kBlock), 0, st, h->px, h->pr,
+                       (const double*)h->pp, (const double*)h->pq, (const double*)sc, n);
+    dot64(h->pr, h->pr, S_RR);
+    read_scal();
+    std::vector<int> newly;
+    for (int c = 0; c < K; c++) {
+      if (active[c] == 0.0) continue;
+      iters[c] = it;
+      work[c] += 1.0;
+      if (hs[S_ACTIVE * K + c] == 0.0) {  // breakdown flagged on the device
+        active[c] = 0.0;
+        continue;
+      }
+      if (std::sqrt(hs[S_RR * K + c]) / bn[c] <= rtol) newly.push_back(c);
+    }
+    bool restart = false;
+    std::vector<double> rflag(K, 0.0);
+    if (!newly.empty()) {
+      lap64<K>(h, 0, h->px, h->pt, h->pb, st, "resid64");
+      dot64(h->pt, h->pt, S_TR);
+      read_scal();
+      for (int c : newly) {
+        work[c] += 1.0;
+        const double rel = std::sqrt(hs[S_TR * K + c]) / bn[c];
+        if (rel <= rtol) {
+          active[c] = 0.0;
+          converged[c] = 1;
+          relres[c] = rel;
+        } else {
+          restart = true;
+          rflag[c] = 1.0;
+        }
+      }
+      write_slot(S_ACTIVE, active);
+      write_slot(S_TR, zero);
+    }
+    if (!any_active()) break;
+    if (restart) {  // continue from the true residual with a fresh direction
+      LG_HIP(hipMemcpyAsync(h->pr, h->pt, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    }
+    eng.precond(h->pr, h->pz);
+    project64(h->pz);
+    for (int c = 0; c < K; c++) work[c] += active[c] > 0.0 ? cw : 0.0;
+    if (flex) {
+      dot64(h->pz, h->pq, S_ZQ);
+      hipLaunchKernelGGL((k_beta<K>), dim3(1), dim3(64), 0, st, sc, 1);
+      hipLaunchKernelGGL((k_xpby<K>), dim3(g), dim3(kBlock), 0, st, h->pp, (const double*)h->pz,
+                         (const double*)sc, n);
+    } else {
+      dot64(h->pr, h->pz, S_TMP);
+      hipLaunchKernelGGL((k_beta<K>), dim3(1), dim3(64), 0, st, sc, 0);
+      hipLaunchKernelGGL((k_xpby<K>), dim3(g), dim3(kBlock), 0, st, h->pp, (const double*)h->pz,
+                         (const double*)sc, n);
+    }
+    if (restart) {
+      write_slot(S_MEAN, rflag);  // S_MEAN is free here: restart flags
+      hipLaunchKernelGGL((k_restart_p<K>), dim3(g), dim3(kBlock), 0, st, h->pp,
+                         (const double*)h->pz, (const double*)sl(S_MEAN), n);
+    }
+    LG_LAUNCH_CHECK();
+  }
+  lg_status status = LG_OK;
+  bool need_true = false;
+  for (int c = 0; c < k; c++)
+    if (!converged[c]) need_true = true;
+  if (need_true) {
+    lap64<K>(h, 0, h->px, h->pt, h->pb, st, "resid64");
+    dot64(h->pt, h->pt, S_TR);
+    read_scal();
+    for (int c = 0; c < k; c++)
+      if (!converged[c]) {
+        relres[c] = bn[c] > 0.0 ? std::sqrt(hs[S_TR * K + c]) / bn[c] : 0.0;
+        status = LG_E_NOT_CONVERGED;
+      }
+  }
+  project64(h->px);
+  hipLaunchKernelGGL(k_pad_out, dim3(nblk(n * k)), dim3(kBlock), 0, st, (const double*)h->px, K, X,
+                     k, n);
+  LG_LAUNCH_CHECK();
+  LG_HIP(hipStreamSynchronize(st));
+  if (info) {
+    for (int c = 0; c < k; c++) {
+      info[c].iters = iters[c];
+      info[c].rel_residual = relres[c];
+      info[c].work_units = work[c];
+      info[c].wda = (relres[c] > 0.0 && relres[c] < 1.0) ? -work[c] / std::log10(relres[c]) : 0.0;
+    }
+  }
+  return status;
+}
+
+template <typename T, int K>
+void cycle_once(lg_hierarchy* h, const double* B, double* X, int k, hipStream_t st) {
+  Engine<T, K> eng{h, st};
+  const int64_t n = h->lev[0].n;
+  hipLaunchKernelGGL(k_pad_in, dim3(nblk(n * K)), dim3(kBlock), 0, st, B, k, h->pb, K, n);
+  eng.precond(h->pb, h->pz);
+  hipLaunchKernelGGL(k_pad_out, dim3(nblk(n * k)), dim3(kBlock), 0, st, (const double*)h->pz, K, X,
+                     k, n);
+  LG_LAUNCH_CHECK();
+}
+
+template <typename T>
+static lg_status solve_k(lg_hierarchy* h, const double* B, double* X, int k, double rtol,
+                         int max_iter, hipStream_t st, lg_rhs_info* info) {
+  switch (h->K) {
+    case 1: return pcg<T, 1>(h, B, X, k, rtol, max_iter, st, info);
+    case 2: return pcg<T, 2>(h, B, X, k, rtol, max_iter, st, info);
+    case 4: return pcg<T, 4>(h, B, X, k, rtol, max_iter, st, info);
+    case 8: return pcg<T, 8>(h, B, X, k, rtol, max_iter, st, info);
+    case 16: return pcg<T, 16>(h, B, X, k, rtol, max_iter, st, info);
+    default: return pcg<T, 32>(h, B, X, k, rtol, max_iter, st, info);
+  }
+}
+
+lg_status solve_dispatch(lg_hierarchy* h, const double* B, double* X, int k, double rtol,
+                         int max_iter, hipStream_t st, lg_rhs_info* info) {
+  if (h->opts.precision == LG_MIXED) return solve_k<float>(h, B, X, k, rtol, max_iter, st, info);
+  return solve_k<double>(h, B, X, k, rtol, max_iter, st, info);
+}
+
+template <typename T>
+static void cycle_k(lg_hierarchy* h, const double* B, double* X, int k, hipStream_t st) {
+  switch (h->K) {
+    case 1: return cycle_once<T, 1>(h, B, X, k, st);
+    case 2: return cycle_once<T, 2>(h, B, X, k, st);
+    case 4: return cycle_once<T, 4>(h, B, X, k, st);
+    case 8: return cycle_once<T, 8>(h, B, X, k, st);
+    case 16: return cycle_once<T, 16>(h, B, X, k, st);
+    default: return cycle_once<T, 32>(h, B, X, k, st);
+  }
+}
+
+void cycle_dispatch(lg_hierarchy* h, const double* B, double* X, int k, hipStream_t st) {
+  if (h->opts.precision == LG_MIXED) cycle_k<float>(h, B, X, k, st);
+  else cycle_k<double>(h, B, X, k, st);
+}
+
+void spmv_dispatch(lg_hierarchy* h, int level, const double* X, double* Y, int k, hipStream_t st) {
+  switch (k) {
+    case 1: lap64<1>(h, level, X, Y, nullptr, st, "spmm"); break;
+    case 2: lap64<2>(h, level, X, Y, nullptr, st, "spmm"); break;
+    case 4: lap64<4>(h, level, X, Y, nullptr, st, "spmm"); break;
+    case 8: lap64<8>(h, level, X, Y, nullptr, st, "spmm"); break;
+    case 16: lap64<16>(h, level, X, Y, nullptr, st, "spmm"); break;
+    case 32: lap64<32>(h, level, X, Y, nullptr, st, "spmm"); break;
+    default: fail(LG_E_ARG, "lg_spmv: k must be 1, 2, 4, 8, 16 or 32");
+  }
+  LG_LAUNCH_CHECK();
+}
+
+// ----------------------------------------------------------- workspace
+void alloc_solve_workspace(lg_hierarchy* h, hipStream_t st) {
+  const int K = h->K;
+  const size_t s = h->opts.precision == LG_MIXED ? sizeof(float) : sizeof(double);
+  const int nl = (int)h->lev.size();
+  for (int l = 0; l < nl; l++) {
+    Level& L = h->lev[l];
+    const size_t v = (size_t)L.n * K * s;
+    L.vb = h->mem.alloc(v);
+    L.vx = h->mem.alloc(v);
+    if (L.type == LG_LEVEL_AGG) {
+      L.vx2 = h->mem.alloc(v);
+      L.vr = h->mem.alloc(v);
+      L.vp = h->mem.alloc(v);
+    }
+    const bool fcg_target = h->opts.cycle == LG_CYCLE_K && l > 0 &&
+                            h->lev[l - 1].type == LG_LEVEL_AGG && L.type != LG_LEVEL_COARSEST;
+    if (fcg_target) {
+      L.kr = h->mem.alloc(v);
+      L.kp1 = h->mem.alloc(v);
+      L.kq1 = h->mem.alloc(v);
+      L.kz = h->mem.alloc(v);
+      L.kx = h->mem.alloc(v);
+      L.kscal = h->mem.get<double>(8 * K);
+    }
+  }
+  const int64_t m = h->lev[0].n * K;
+  h->pb = h->mem.get<double>(m);
+  h->px = h->mem.get<double>(m);
+  h->pr = h->mem.get<double>(m);
+  h->pz = h->mem.get<double>(m);
+  h->pp = h->mem.get<double>(m);
+  h->pq = h->mem.get<double>(m);
+  h->pt = h->mem.get<double>(m);
+  if (h->opts.precision == LG_MIXED) h->cyc_in = h->mem.alloc((size_t)m * s);
+  h->scal = h->mem.get<double>(S_COUNT * K);
+  h->red = h->mem.get<double>((int64_t)kRedBlocks * 2 * K);
+  LG_HIP(hipHostMalloc((void**)&h->host_scal, sizeof(double) * S_COUNT * K, hipHostMallocDefault));
+  (void)st;
+}
+
+}  // namespace lg

@@ -1,0 +1,77 @@
+"""The C-ABI library loads on a machine without a GPU and exports every
+symbol that include/lgmg.h declares; the ctypes mirrors of its structs have
+the C layout.  No compute call is made."""
+
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1705_06266_amd.lgmg as lg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lgmg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lg_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_is_built():
+    assert os.path.exists(lg.LIB_PATH), "run __graft_entry__.build() first"
+
+
+def test_every_declared_symbol_is_exported():
+    lib = lg.load()
+    names = declared_functions()
+    assert len(names) >= 17
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(lg.EXPORTS) == names
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "lgmg.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(lg_setup_opts),"
+        " offsetof(lg_setup_opts, seed), offsetof(lg_setup_opts, validate), sizeof(lg_graph),"
+        " sizeof(lg_level_stats), sizeof(lg_rhs_info)); return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [C.sizeof(lg.lg_setup_opts), lg.lg_setup_opts.seed.offset,
+            lg.lg_setup_opts.validate.offset, C.sizeof(lg.lg_graph), C.sizeof(lg.lg_level_stats),
+            C.sizeof(lg.lg_rhs_info)]
+    assert got == want
+
+
+def test_default_options_are_the_papers():
+    o = lg.lg_default_opts()
+    assert (o.elim_max_degree, o.agg_iters, o.seed_votes, o.tv_sweeps, o.cheb_degree,
+            o.eig_iters, o.coarsest_nnz) == (4, 10, 8, 3, 2, 10, 1000)
+    assert (o.elim_min_fraction, o.agg_filter_base, o.cheb_lo, o.cheb_hi) == (0.05, 0.5, 0.3, 1.1)
+
+
+def test_argument_errors_need_no_device():
+    lib = lg.load()
+    h = C.c_void_p()
+    assert lib.lg_setup(None, None, None, C.byref(h)) == lg.LG_E_ARG
+    assert "null graph" in lg.lg_last_error()
+    g = lg.lg_graph(0, 0, None, None, None, 0)
+    rp = (C.c_int64 * 1)(0)
+    g.row_ptr = C.cast(rp, C.c_void_p)
+    assert lib.lg_setup(C.byref(g), None, None, C.byref(h)) == lg.LG_E_ARG
+    o = lg.lg_default_opts(max_rhs=64)
+    g.n = 1
+    rp2 = (C.c_int64 * 2)(0, 0)
+    g.row_ptr = C.cast(rp2, C.c_void_p)
+    assert lib.lg_setup(C.byref(g), C.byref(o), None, C.byref(h)) == lg.LG_E_ARG
+    assert "max_rhs" in lg.lg_last_error()
+    assert lib.lg_solve(None, None, None, 1, 1e-8, 10, None, None) == lg.LG_E_ARG
+    assert lg.status_str(lg.LG_E_DISCONNECTED) == "graph not connected"
+    lib.lg_free(None)

@@ -1,0 +1,233 @@
+"""Parity of the HIP path with the CPU oracle on the same seeded inputs.
+
+Bar: decisions and hierarchy values bit for bit (elimination product z,
+strengths S, test vectors, voting status and votes, aggregates, every coarse
+operator); floating-point solve results within the tolerances stated next to
+each assertion.  All calls go through the C ABI.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+import paper_1705_06266_amd.lgmg as lg
+from gpu_util import (bits, check_laplacian_level, compare_hierarchies, dense_laplacian_norm,
+                      gpu_setup, laplacian_apply, oracle_opts, say, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "grid2d_64x64": lambda: gg.grid2d(64, 64),
+    "grid3d_12_loguniform": lambda: gg.grid3d(12, 12, 12, weights="loguniform", seed=4),
+    "rmat_s12": lambda: gg.rmat(12, 16, seed=2),
+    "chunglu_30k_hubs": lambda: gg.chung_lu(30000, seed=6, max_deg=9000),
+    "star_6000": lambda: gg.star(6000),
+    "path_333": lambda: gg.path(333),
+    "gnp_700": lambda: gg.gnp(700, 0.01, seed=3),
+    "cycle_64": lambda: gg.cycle(64),
+}
+
+
+@pytest.fixture(scope="module")
+def built():
+    import torch
+
+    assert torch.cuda.is_available()
+    lg.load()
+    return True
+
+
+def _pair(name, **opts):
+    g = CASES[name]()
+    say(f"[case] {name}: n={g.n} nnz={g.nnz} opts={opts}")
+    hg = gpu_setup(g, keep_setup_data=1, **opts)
+    ho = oracle.Hierarchy(g, oracle_opts(hg.opts))
+    return g, hg, ho
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hierarchy_bit_exact(built, name):
+    g, hg, ho = _pair(name)
+    sg = compare_hierarchies(hg, ho, setup_data=True)
+    say(f"  levels={[(s['type'], s['n'], s['nnz']) for s in sg]}")
+
+
+@pytest.mark.parametrize("name", ["grid2d_64x64", "chunglu_30k_hubs", "star_6000"])
+def test_hierarchy_bit_exact_host_arrays_and_identity_hash(built, name):
+    g = CASES[name]()
+    say(f"[case] {name} host arrays, identity hash")
+    hg = gpu_setup(g, device_arrays=False, keep_setup_data=1, hash_mode=1)
+    ho = oracle.Hierarchy(g, oracle_opts(hg.opts))
+    compare_hierarchies(hg, ho, setup_data=True)
+
+
+@pytest.mark.parametrize("name", ["grid2d_64x64", "rmat_s12", "chunglu_30k_hubs"])
+def test_spmv_every_level(built, name):
+    import torch
+
+    g, hg, ho = _pair(name)
+    rng = np.random.default_rng(0)
+    for l, s in enumerate(lg.lg_hierarchy_stats(hg)):
+        for k in (1, 4, 32):
+            X = rng.standard_normal((s["n"], k))
+            Y = torch.empty((s["n"], k), dtype=torch.float64, device="cuda:0")
+            lg.lg_spmv(hg, l, to_dev(X), Y)
+            torch.cuda.synchronize()
+            Yo = np.stack([ho.spmv(l, X[:, c]) for c in range(k)], axis=1)
+            scale = np.abs(Yo).max() + 1e-300
+            # fp64 sums in another order: |error| <= deg * eps * max|w x|
+            assert np.abs(Y.cpu().numpy() - Yo).max() <= 1e-12 * scale, (l, k)
+
+
+@pytest.mark.parametrize("cycle", [1, 2])
+@pytest.mark.parametrize("name", ["grid2d_64x64", "rmat_s12", "chunglu_30k_hubs", "star_6000",
+                                  "grid3d_12_loguniform"])
+def test_one_cycle_matches(built, name, cycle):
+    g, hg, ho = _pair(name, cycle=cycle)
+    b = gg.rhs(g.n, 3, 7)
+    X = lg.lg_cycle(hg, to_dev(b)).cpu().numpy()
+    for c in range(3):
+        xo = ho.cycle(b[:, c])
+        err = np.linalg.norm(X[:, c] - xo) / np.linalg.norm(xo)
+        say(f"  column {c}: relative difference {err:.2e}")
+        # same operations, fp64, other summation orders: differences at rounding level
+        assert err <= 1e-10
+
+
+@pytest.mark.parametrize("cycle", [1, 2])
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_fp64_matches(built, name, cycle):
+    g, hg, ho = _pair(name, cycle=cycle)
+    b = gg.rhs(g.n, 1, 11)[:, 0]
+    X, info, st = lg.lg_solve(hg, to_dev(b[:, None]), rtol=1e-8, max_iter=300)
+    xg = X.cpu().numpy()[:, 0]
+    xo, sto, ito, relo, worko = ho.solve(b, 1e-8, 300)
+    say(f"  gpu iters={info[0]['iters']} rel={info[0]['rel_residual']:.2e} "
+        f"wda={info[0]['wda']:.2f} | oracle iters={ito} rel={relo:.2e}")
+    assert st == 0 and sto == 0
+    bp = b - b.mean()
+    rel_true = np.linalg.norm(bp - laplacian_apply(g, xg)) / np.linalg.norm(bp)
+    assert rel_true <= 1e-8 * 1.001
+    assert abs(info[0]["rel_residual"] - rel_true) <= 1e-3 * rel_true + 1e-15
+    assert abs(info[0]["iters"] - ito) <= 1
+    # both solve L x = b to 1e-8; the iterates of two fp64 runs of one method differ
+    # at rounding level amplified by the iteration: allow 1e-6 in the energy norm
+    diff = dense_laplacian_norm(g, xg - xo) / max(dense_laplacian_norm(g, xo), 1e-300)
+    say(f"  energy-norm difference {diff:.2e}")
+    assert diff <= 1e-6
+    assert abs(xg.mean()) <= 1e-12 * np.abs(xg).max()
+    # identical cost model on both sides
+    assert math.isclose(info[0]["work_units"], worko, rel_tol=1e-9) or \
+        abs(info[0]["iters"] - ito) == 1
+
+
+@pytest.mark.parametrize("name", ["grid3d_12_loguniform", "chunglu_30k_hubs", "rmat_s12"])
+def test_batched_columns_equal_single_solves(built, name):
+    g = CASES[name]()
+    say(f"[case] {name} batch of 5 vs single")
+    hb = gpu_setup(g, max_rhs=5)
+    h1 = gpu_setup(g, max_rhs=1)
+    B = gg.rhs(g.n, 5, 21)
+    Xb, infob, _ = lg.lg_solve(hb, to_dev(B))
+    Xb = Xb.cpu().numpy()
+    for c in range(5):
+        x1, info1, _ = lg.lg_solve(h1, to_dev(B[:, c:c + 1]))
+        x1 = x1.cpu().numpy()[:, 0]
+        diff = dense_laplacian_norm(g, Xb[:, c] - x1) / dense_laplacian_norm(g, x1)
+        say(f"  column {c}: iters {infob[c]['iters']} vs {info1[0]['iters']}, diff {diff:.1e}")
+        assert infob[c]["rel_residual"] <= 1e-8 and info1[0]["rel_residual"] <= 1e-8
+        assert abs(infob[c]["iters"] - info1[0]["iters"]) <= 1
+        assert diff <= 1e-6
+
+
+@pytest.mark.parametrize("cycle", [1, 2])
+@pytest.mark.parametrize("name", ["grid2d_64x64", "grid3d_12_loguniform", "chunglu_30k_hubs",
+                                  "rmat_s12"])
+def test_mixed_precision_reaches_tolerance(built, name, cycle):
+    g = CASES[name]()
+    say(f"[case] {name} mixed precision, cycle {cycle}")
+    hm = gpu_setup(g, precision=lg.LG_MIXED, max_rhs=4, cycle=cycle)
+    ho = oracle.Hierarchy(g, oracle_opts(hm.opts))
+    B = gg.rhs(g.n, 4, 5)
+    X, info, st = lg.lg_solve(hm, to_dev(B), rtol=1e-8, max_iter=300)
+    assert st == 0
+    X = X.cpu().numpy()
+    for c in range(4):
+        xo, sto, ito, relo, _ = ho.solve(B[:, c], 1e-8, 300)
+        err = dense_laplacian_norm(g, X[:, c] - xo) / dense_laplacian_norm(g, xo)
+        say(f"  column {c}: mixed iters {info[c]['iters']} (fp64 oracle {ito}), "
+            f"rel {info[c]['rel_residual']:.1e}, energy error vs fp64 {err:.1e}")
+        assert info[c]["rel_residual"] <= 1e-8
+        # stated bound: both at 1e-8 relative residual -> energy-norm error <= 1e-5
+        assert err <= 1e-5
+
+
+def test_not_converged_status_fills_info(built):
+    g = CASES["grid2d_64x64"]()
+    h = gpu_setup(g)
+    X, info, st = lg.lg_solve(h, to_dev(gg.rhs(g.n, 1, 1)), rtol=1e-8, max_iter=1,
+                              allow_unconverged=True)
+    assert st == lg.LG_E_NOT_CONVERGED
+    assert info[0]["iters"] == 1 and 1e-8 < info[0]["rel_residual"] < 1.0
+
+
+def test_zero_and_constant_rhs(built):
+    g = CASES["gnp_700"]()
+    h = gpu_setup(g, max_rhs=2)
+    B = np.zeros((g.n, 2))
+    B[:, 1] = 3.0  # constant: projects to zero
+    X, info, st = lg.lg_solve(h, to_dev(B))
+    assert st == 0
+    assert np.all(X.cpu().numpy() == 0.0)
+    assert info[0]["iters"] == 0 and info[1]["iters"] == 0
+
+
+def test_tiny_graphs(built):
+    for g in [gg.from_edges(1, [], []), gg.path(2), gg.path(3), gg.star(3)]:
+        say(f"[case] tiny n={g.n}")
+        h = gpu_setup(g)
+        ho = oracle.Hierarchy(g, oracle_opts(h.opts))
+        compare_hierarchies(h, ho)
+        b = gg.rhs(g.n, 1, 2)
+        X, info, st = lg.lg_solve(h, to_dev(b))
+        xo = ho.solve(b[:, 0])[0]
+        assert st == 0
+        assert np.allclose(X.cpu().numpy()[:, 0], xo, atol=1e-12)
+
+
+def test_invalid_graphs_are_rejected(built):
+    g = gg.grid2d(8, 8)
+    bad = g.copy()
+    bad.w[5] *= 2
+    with pytest.raises(lg.LgError) as e:
+        gpu_setup(bad)
+    assert e.value.code == lg.LG_E_GRAPH
+    bad = g.copy()
+    bad.w[0] = -1.0
+    with pytest.raises(lg.LgError) as e:
+        gpu_setup(bad)
+    assert e.value.code == lg.LG_E_GRAPH
+    bad = g.copy()
+    bad.col[[1, 2]] = bad.col[[2, 1]]
+    with pytest.raises(lg.LgError) as e:
+        gpu_setup(bad)
+    assert e.value.code == lg.LG_E_GRAPH
+    two = gg.from_edges(6, [0, 1, 3, 4], [1, 2, 4, 5])
+    with pytest.raises(lg.LgError) as e:
+        gpu_setup(two)
+    assert e.value.code == lg.LG_E_DISCONNECTED
+    h = gpu_setup(g, max_rhs=2)
+    with pytest.raises(lg.LgError) as e:
+        lg.lg_solve(h, to_dev(np.zeros((g.n, 3))))
+    assert e.value.code == lg.LG_E_ARG
+
+
+def test_every_level_is_a_laplacian(built):
+    g = CASES["chunglu_30k_hubs"]()
+    h = gpu_setup(g)
+    for l, s in enumerate(lg.lg_hierarchy_stats(h)):
+        rp, col, w, d, mp = lg.lg_export_level(h, l)
+        check_laplacian_level(rp, col, w, d)
