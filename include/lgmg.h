@@ -127,8 +127,9 @@ lg_status lg_solve(lg_hierarchy* h, const double* B, double* X, int32_t k, doubl
 
 /* One application of the preconditioner (Algorithm 1 from the finest level
  * with zero initial guess; V- or K-cycle and precision as in setup):
- * X = M B for device n x k fp64 arrays.  No projection.  Used to compare the
- * cycle with a reference implementation. */
+ * X = M B for device n x k fp64 arrays.  No projection.  The columns of B
+ * should have zero mean, as every vector the solver preconditions does: the
+ * K-cycle's inner Krylov steps are otherwise inconsistent singular systems. */
 lg_status lg_cycle(lg_hierarchy* h, const double* B, double* X, int32_t k, void* hip_stream);
 
 /* Y = L_l X on hierarchy level l for device n_l x k fp64 arrays (fp64

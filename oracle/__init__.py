@@ -318,8 +318,11 @@ class Hierarchy:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().lgo_free(h)
+        if h and _lib is not None:
+            try:
+                _lib.lgo_free(h)
+            except Exception:
+                pass
             self._h = None
 
     @property

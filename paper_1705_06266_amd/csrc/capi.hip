@@ -209,7 +209,7 @@ extern "C" lg_status lg_export_setup_data(const lg_hierarchy* h, int32_t level, 
     std::vector<int32_t> st(L.n);
     LG_HIP(hipMemcpy(st.data(), L.status, sizeof(int32_t) * L.n, hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < L.n; i++) {
-      if (state) state[i] = st[i] >> 30;
+      if (state) state[i] = lg::status_state(st[i]);
       if (idx) idx[i] = st[i] & lg::kIdxMask;
     }
   }

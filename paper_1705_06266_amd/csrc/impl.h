@@ -11,6 +11,11 @@ namespace lg {
 // State codes equal their rank in the argmax order: Seed > Undecided > Decided.
 constexpr int kDecided = 0, kUndecided = 1, kSeed = 2;
 constexpr int32_t kIdxMask = (1 << 30) - 1;
+constexpr int32_t kNoStatus = -1;  // "no neighbour" in the argmax (state field 3 never occurs)
+__host__ __device__ inline int status_state(int32_t s) { return (int)((uint32_t)s >> 30); }
+__host__ __device__ inline int32_t make_status(int state, int64_t idx) {
+  return (int32_t)(((uint32_t)state << 30) | (uint32_t)idx);
+}
 
 struct Level {
   int type = LG_LEVEL_COARSEST;

@@ -459,9 +459,9 @@ struct VoteAcc {
 };
 
 __device__ __forceinline__ bool vote_better(const VoteAcc& x, const VoteAcc& y) {
-  if (x.st < 0) return false;
-  if (y.st < 0) return true;
-  const int rx = x.st >> 30, ry = y.st >> 30;
+  if (x.st == kNoStatus) return false;
+  if (y.st == kNoStatus) return true;
+  const int rx = status_state(x.st), ry = status_state(y.st);
   if (rx != ry) return rx > ry;
   if (x.s != y.s) return x.s > y.s;
   return (x.st & kIdxMask) < (y.st & kIdxMask);
@@ -477,8 +477,8 @@ struct VoteOp {
   int32_t* __restrict__ next;
   int32_t* __restrict__ votes;
   double tau;
-  __device__ Acc identity() const { return {-1.0, -1, 0}; }
-  __device__ bool active(int64_t row) const { return (status[row] >> 30) == kUndecided; }
+  __device__ Acc identity() const { return {-1.0, kNoStatus, 0}; }
+  __device__ bool active(int64_t row) const { return status_state(status[row]) == kUndecided; }
   __device__ void accum(Acc& a, int64_t, int e) const {
     const double s = S[e];
     if (!(s >= tau)) return;
@@ -492,9 +492,9 @@ struct VoteOp {
     if (lane) return;
     const int32_t st = status[row];
     int32_t out = st;
-    if ((st >> 30) == kUndecided && a.st >= 0) {
-      const int r = a.st >> 30;
-      if (r == kSeed) out = (kDecided << 30) | (a.st & kIdxMask);
+    if (status_state(st) == kUndecided && a.st != kNoStatus) {
+      const int r = status_state(a.st);
+      if (r == kSeed) out = make_status(kDecided, a.st & kIdxMask);
       else if (r == kUndecided) atomicAdd(&votes[a.st & kIdxMask], 1);
     }
     next[row] = out;
@@ -505,7 +505,7 @@ __global__ void k_status_init(int32_t* __restrict__ status, int32_t* __restrict_
                               int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  status[i] = (kUndecided << 30) | (int32_t)i;
+  status[i] = make_status(kUndecided, i);
   votes[i] = 0;
 }
 
@@ -513,8 +513,8 @@ __global__ void k_promote(int32_t* __restrict__ next, const int32_t* __restrict_
                           int64_t n, int seed_votes) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  if (next[i] == ((kUndecided << 30) | (int32_t)i) && votes[i] >= seed_votes)
-    next[i] = (kSeed << 30) | (int32_t)i;
+  if (next[i] == make_status(kUndecided, i) && votes[i] >= seed_votes)
+    next[i] = make_status(kSeed, i);
 }
 
 __global__ void k_root_flags(const int32_t* __restrict__ status, int64_t n,

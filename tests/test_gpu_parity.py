@@ -86,8 +86,11 @@ def test_spmv_every_level(built, name):
 @pytest.mark.parametrize("name", ["grid2d_64x64", "rmat_s12", "chunglu_30k_hubs", "star_6000",
                                   "grid3d_12_loguniform"])
 def test_one_cycle_matches(built, name, cycle):
-    g, hg, ho = _pair(name, cycle=cycle)
+    g, hg, ho = _pair(name, cycle=cycle, max_rhs=3)
+    # the solver only applies the cycle to mean-zero vectors; for other inputs the
+    # K-cycle's inner Krylov steps face inconsistent singular coarse systems
     b = gg.rhs(g.n, 3, 7)
+    b -= b.mean(axis=0)
     X = lg.lg_cycle(hg, to_dev(b)).cpu().numpy()
     for c in range(3):
         xo = ho.cycle(b[:, c])
@@ -111,7 +114,7 @@ def test_solve_fp64_matches(built, name, cycle):
     bp = b - b.mean()
     rel_true = np.linalg.norm(bp - laplacian_apply(g, xg)) / np.linalg.norm(bp)
     assert rel_true <= 1e-8 * 1.001
-    assert abs(info[0]["rel_residual"] - rel_true) <= 1e-3 * rel_true + 1e-15
+    assert abs(info[0]["rel_residual"] - rel_true) <= 1e-3 * rel_true + 1e-13
     assert abs(info[0]["iters"] - ito) <= 1
     # both solve L x = b to 1e-8; the iterates of two fp64 runs of one method differ
     # at rounding level amplified by the iteration: allow 1e-6 in the energy norm
