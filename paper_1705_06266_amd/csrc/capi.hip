@@ -163,7 +163,7 @@ extern "C" lg_status lg_hierarchy_stats(const lg_hierarchy* h, lg_level_stats* o
     out[l].nnz = L.nnz;
     out[l].nc = L.nc;
     out[l].lmax = L.lmax;
-    out[l].n_hub = L.sched.nhub;
+    out[l].n_hub = L.sched.nhub + L.sched.nsplit;
   }
   return LG_OK;
 }

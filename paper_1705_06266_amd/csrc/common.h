@@ -5,17 +5,19 @@
 // semiring products of Algorithms 2 and 3, the Jacobi sweeps and affinities of
 // Section 3.5, the Laplacian SpMV of the smoother and CG) is expressed as an
 // "Op" reduced over the stored entries of each CSR row:
-//   - ordinary rows: a group of G lanes (G = power of two <= 64) per row, the
-//     lanes stride the row, then a butterfly reduction inside the group;
-//   - hub rows (degree > hub_deg): split into HUB_CHUNK-entry chunks, one
-//     256-thread workgroup per chunk writes a partial, and a fix-up pass
-//     combines each hub's partials in chunk order and runs the epilogue.
-// The split keeps a vertex of degree 1e5 from serialising one wavefront.
+//   - ordinary rows: a group of G lanes (G = power of two <= 64, chosen per row
+//     from its degree class) per row, the lanes stride the row, then a
+//     butterfly reduction inside the group;
+//   - hub rows: one 256-thread workgroup per row in the same launch; rows
+//     beyond kSplitDeg entries are split into chunks whose partials a second
+//     pass combines in chunk order.
+// This keeps a vertex of degree 1e5 from serialising one wavefront.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -27,7 +29,7 @@ typedef __int128 s128;
 namespace lg {
 
 constexpr int kBlock = 256;
-constexpr int kHubChunk = 4096;
+constexpr int kHubChunk = 2048;
 constexpr uint64_t kGolden = 0x9e3779b97f4a7c15ULL;
 
 // ------------------------------------------------------------------ errors
@@ -163,53 +165,131 @@ __device__ __forceinline__ T shfl_xor_any(const T& v, int mask) {
 }
 
 // ---------------------------------------------------------- row schedule
+// Rows are grouped by degree once per matrix (a stable counting sort):
+//   class c < 7: degree <= kPerLane * 2^c, processed by 2^c lanes;
+//   class 7:     kPerLane * 64 < degree <= hub_deg, 64 lanes striding the row;
+//   hubs:        hub_deg < degree <= kSplitDeg, one 256-thread workgroup each,
+//                dispatched first in the same launch;
+//   split rows:  degree > kSplitDeg, kHubChunk-entry chunks, one workgroup
+//                each, dispatched first; a second launch combines each row's
+//                partials in chunk order and runs the epilogue.
+// Every row is reduced by one fixed set of lanes in a fixed order, so
+// results do not depend on scheduling.
+constexpr int kClasses = 8;
+constexpr int kPartialBytes = 512;
+constexpr int kSplitDeg = 4096;  // rows above this are split into kHubChunk-entry chunks
+
+struct ClassTable {
+  int32_t cls_start[kClasses + 1];  // row ranges of each class in perm
+  int32_t blk_start[kClasses + 1];  // block ranges of each class (after the hubs)
+};
+
 struct Sched {
   int64_t n = 0, nnz = 0;
-  int G = 8;            // lanes per ordinary row
-  int hub_deg = 1 << 30;  // rows with more entries are hubs
-  int64_t nhub = 0, nchunk = 0;
-  int32_t* hub_rows = nullptr;   // [nhub]
-  int32_t* hub_cptr = nullptr;   // [nhub + 1] first chunk of each hub
-  int32_t* chunk_hub = nullptr;  // [nchunk] hub of each chunk
-  void* partial = nullptr;       // [nchunk * kPartialBytes]
+  int hub_deg = 1024;
+  int min_deg = 0, max_deg = 0;
+  int32_t* perm = nullptr;  // non-hub rows grouped by class
+  ClassTable ct{};
+  int64_t nhub = 0;  // workgroup-per-row hubs
+  int32_t* hub_rows = nullptr;
+  int64_t nsplit = 0, nchunk = 0;  // split rows
+  int32_t* split_rows = nullptr;   // [nsplit]
+  int32_t* split_cptr = nullptr;   // [nsplit + 1] first chunk of each split row
+  int32_t* chunk_split = nullptr;  // [nchunk] split row of each chunk
+  void* partial = nullptr;         // [nchunk * kPartialBytes]
 };
-constexpr int kPartialBytes = 512;
 
-// Ordinary rows: G lanes per row.
+// Target entries per lane: a lane issues this many independent gathers.
+constexpr int kPerLane = 4;
+
+__host__ __device__ inline int degree_class(int d, int hub_deg) {
+  if (d > hub_deg) return kClasses;  // hub or split
+  if (d > kPerLane * 64) return kClasses - 1;
+  int c = 0;
+  while (kPerLane * (1 << c) < d) c++;
+  return c;
+}
+
+// Whole-row reduction by one workgroup; the epilogue runs on thread 0.
+template <class Op>
+__device__ __forceinline__ void block_row(const Op& op, const int32_t* __restrict__ rp,
+                                          int64_t row) {
+  using Acc = typename Op::Acc;
+  Acc acc = op.identity();
+  if (op.active(row)) {
+    const int end = rp[row + 1];
+    int e = rp[row] + (int)threadIdx.x;
+    for (; e + 3 * kBlock < end; e += 4 * kBlock) {
+      op.accum(acc, row, e);
+      op.accum(acc, row, e + kBlock);
+      op.accum(acc, row, e + 2 * kBlock);
+      op.accum(acc, row, e + 3 * kBlock);
+    }
+    for (; e < end; e += kBlock) op.accum(acc, row, e);
+  }
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) op.combine(acc, shfl_xor_any(acc, m));
+  __shared__ Acc red[kBlock / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Acc t = red[0];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; w++) op.combine(t, red[w]);
+    op.finish(row, t, 0, 1);
+  }
+}
+
+// G lanes per row for the rows perm[pos_begin, pos_end).
 template <class Op, int G>
-__global__ __launch_bounds__(kBlock) void k_rows(Op op, const int32_t* __restrict__ rp, int64_t n,
-                                                 int hub_deg) {
-  const int64_t row = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+__device__ __forceinline__ void rows_class(const Op& op, const int32_t* __restrict__ rp,
+                                           const int32_t* __restrict__ perm, int64_t pos_begin,
+                                           int64_t pos_end, int64_t local_block) {
+  const int64_t pos = pos_begin + (local_block * kBlock + threadIdx.x) / G;
   const int lane = threadIdx.x & (G - 1);
-  if (row >= n) return;
-  const int beg = rp[row], end = rp[row + 1];
-  if (end - beg > hub_deg) return;
+  if (pos >= pos_end) return;
+  const int64_t row = perm[pos];
   typename Op::Acc acc = op.identity();
   if (op.active(row)) {
-    for (int e = beg + lane; e < end; e += G) op.accum(acc, row, e);
+    const int end = rp[row + 1];
+    int e = rp[row] + lane;
+    for (; e + 3 * G < end; e += 4 * G) {
+      op.accum(acc, row, e);
+      op.accum(acc, row, e + G);
+      op.accum(acc, row, e + 2 * G);
+      op.accum(acc, row, e + 3 * G);
+    }
+    for (; e < end; e += G) op.accum(acc, row, e);
 #pragma unroll
     for (int m = G / 2; m > 0; m >>= 1) op.combine(acc, shfl_xor_any(acc, m));
   }
   op.finish(row, acc, lane, G);
 }
 
-// Hub rows, phase 1: one workgroup per chunk writes a partial.
+// One chunk of a split row: its partial goes to the chunk's slot; a second
+// launch combines each row's partials in chunk order.
 template <class Op>
-__global__ __launch_bounds__(kBlock) void k_hub_chunks(Op op, const int32_t* __restrict__ rp,
-                                                       const int32_t* __restrict__ hub_rows,
-                                                       const int32_t* __restrict__ hub_cptr,
-                                                       const int32_t* __restrict__ chunk_hub,
-                                                       typename Op::Acc* __restrict__ partial) {
+__device__ __forceinline__ void split_chunk(const Op& op, const int32_t* __restrict__ rp,
+                                            const int32_t* __restrict__ split_rows,
+                                            const int32_t* __restrict__ split_cptr,
+                                            const int32_t* __restrict__ chunk_split,
+                                            typename Op::Acc* __restrict__ partial, int64_t c) {
   using Acc = typename Op::Acc;
-  const int c = blockIdx.x;
-  const int h = chunk_hub[c];
-  const int64_t row = hub_rows[h];
-  const int k = c - hub_cptr[h];
-  const int beg = rp[row] + k * kHubChunk;
+  const int h = chunk_split[c];
+  const int64_t row = split_rows[h];
+  const int beg = rp[row] + (int)(c - split_cptr[h]) * kHubChunk;
   const int end = min(rp[row + 1], beg + kHubChunk);
   Acc acc = op.identity();
-  if (op.active(row))
-    for (int e = beg + (int)threadIdx.x; e < end; e += kBlock) op.accum(acc, row, e);
+  if (op.active(row)) {
+    int e = beg + (int)threadIdx.x;
+    for (; e + 3 * kBlock < end; e += 4 * kBlock) {
+      op.accum(acc, row, e);
+      op.accum(acc, row, e + kBlock);
+      op.accum(acc, row, e + 2 * kBlock);
+      op.accum(acc, row, e + 3 * kBlock);
+    }
+    for (; e < end; e += kBlock) op.accum(acc, row, e);
+  }
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) op.combine(acc, shfl_xor_any(acc, m));
   __shared__ Acc red[kBlock / 64];
@@ -223,48 +303,83 @@ __global__ __launch_bounds__(kBlock) void k_hub_chunks(Op op, const int32_t* __r
   }
 }
 
-// Hub rows, phase 2: combine partials in chunk order, run the epilogue.
+// Split rows, phase 2: combine partials in chunk order, run the epilogue.
 template <class Op>
-__global__ __launch_bounds__(64) void k_hub_fix(Op op, const int32_t* __restrict__ hub_rows,
-                                                const int32_t* __restrict__ hub_cptr,
-                                                const typename Op::Acc* __restrict__ partial,
-                                                int64_t nhub) {
+__global__ __launch_bounds__(64) void k_split_fix(Op op, const int32_t* __restrict__ split_rows,
+                                                  const int32_t* __restrict__ split_cptr,
+                                                  const typename Op::Acc* __restrict__ partial,
+                                                  int64_t nsplit) {
   const int64_t h = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (h >= nhub) return;
-  const int64_t row = hub_rows[h];
+  if (h >= nsplit) return;
+  const int64_t row = split_rows[h];
   typename Op::Acc acc = op.identity();
-  for (int c = hub_cptr[h]; c < hub_cptr[h + 1]; c++) op.combine(acc, partial[c]);
+  for (int c = split_cptr[h]; c < split_cptr[h + 1]; c++) op.combine(acc, partial[c]);
   op.finish(row, acc, 0, 1);
 }
 
-template <class Op, int G>
-inline void launch_rows_g(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st) {
-  const int64_t blocks = ceil_div(s.n * G, kBlock);
-  hipLaunchKernelGGL((k_rows<Op, G>), dim3((unsigned)blocks), dim3(kBlock), 0, st, op, rp, s.n,
-                     s.hub_deg);
+// Ordinary rows run on a bounded grid of workgroups that loop over the
+// logical row blocks (kRowGrid covers the chip several times over): short
+// rows make short-lived waves, and re-dispatching them costs more than the
+// work they do.
+constexpr int64_t kRowGrid = 2048;
+
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_rows(Op op, const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ perm, ClassTable ct,
+                                                 int64_t nhub, const int32_t* __restrict__ hub_rows,
+                                                 int64_t nchunk, const int32_t* __restrict__ split_rows,
+                                                 const int32_t* __restrict__ split_cptr,
+                                                 const int32_t* __restrict__ chunk_split,
+                                                 typename Op::Acc* __restrict__ partial) {
+  int64_t b = blockIdx.x;
+  if (b < nchunk) {
+    split_chunk(op, rp, split_rows, split_cptr, chunk_split, partial, b);
+    return;
+  }
+  b -= nchunk;
+  if (b < nhub) {
+    block_row(op, rp, (int64_t)hub_rows[b]);
+    return;
+  }
+  b -= nhub;
+  const int64_t total = ct.blk_start[kClasses];
+  const int64_t stride = (int64_t)gridDim.x - nchunk - nhub;
+  for (int64_t q = b; q < total; q += stride) {
+    int c = 0;
+#pragma unroll
+    for (int k = 1; k < kClasses; k++) c += (q >= ct.blk_start[k]) ? 1 : 0;
+    const int64_t lb = q - ct.blk_start[c];
+    const int64_t p0 = ct.cls_start[c], p1 = ct.cls_start[c + 1];
+    switch (c) {
+      case 0: rows_class<Op, 1>(op, rp, perm, p0, p1, lb); break;
+      case 1: rows_class<Op, 2>(op, rp, perm, p0, p1, lb); break;
+      case 2: rows_class<Op, 4>(op, rp, perm, p0, p1, lb); break;
+      case 3: rows_class<Op, 8>(op, rp, perm, p0, p1, lb); break;
+      case 4: rows_class<Op, 16>(op, rp, perm, p0, p1, lb); break;
+      case 5: rows_class<Op, 32>(op, rp, perm, p0, p1, lb); break;
+      default: rows_class<Op, 64>(op, rp, perm, p0, p1, lb); break;
+    }
+  }
 }
 
-// Run Op over every row of the CSR described by (s, rp) on stream st.
+// Run Op over every row of the CSR described by (s, rp) on stream st: one launch.
 template <class Op>
 void run_rows(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st) {
   static_assert(sizeof(typename Op::Acc) <= kPartialBytes, "accumulator larger than a partial slot");
+  static_assert(sizeof(typename Op::Acc) % 4 == 0, "accumulator size must be a multiple of 4");
   if (s.n == 0) return;
-  switch (s.G) {
-    case 1: launch_rows_g<Op, 1>(s, rp, op, st); break;
-    case 2: launch_rows_g<Op, 2>(s, rp, op, st); break;
-    case 4: launch_rows_g<Op, 4>(s, rp, op, st); break;
-    case 8: launch_rows_g<Op, 8>(s, rp, op, st); break;
-    case 16: launch_rows_g<Op, 16>(s, rp, op, st); break;
-    case 32: launch_rows_g<Op, 32>(s, rp, op, st); break;
-    default: launch_rows_g<Op, 64>(s, rp, op, st); break;
-  }
+  const int64_t row_blocks = std::min<int64_t>(s.ct.blk_start[kClasses], kRowGrid);
+  const int64_t blocks = s.nchunk + s.nhub + row_blocks;
+  if (blocks == 0) return;
+  hipLaunchKernelGGL((k_rows<Op>), dim3((unsigned)blocks), dim3(kBlock), 0, st, op, rp,
+                     (const int32_t*)s.perm, s.ct, s.nhub, (const int32_t*)s.hub_rows, s.nchunk,
+                     (const int32_t*)s.split_rows, (const int32_t*)s.split_cptr,
+                     (const int32_t*)s.chunk_split, reinterpret_cast<typename Op::Acc*>(s.partial));
   LG_LAUNCH_CHECK();
-  if (s.nhub) {
-    auto* part = reinterpret_cast<typename Op::Acc*>(s.partial);
-    hipLaunchKernelGGL((k_hub_chunks<Op>), dim3((unsigned)s.nchunk), dim3(kBlock), 0, st, op, rp,
-                       s.hub_rows, s.hub_cptr, s.chunk_hub, part);
-    hipLaunchKernelGGL((k_hub_fix<Op>), dim3((unsigned)ceil_div(s.nhub, 64)), dim3(64), 0, st, op,
-                       s.hub_rows, s.hub_cptr, (const typename Op::Acc*)part, s.nhub);
+  if (s.nsplit) {
+    hipLaunchKernelGGL((k_split_fix<Op>), dim3((unsigned)ceil_div(s.nsplit, 64)), dim3(64), 0, st, op,
+                       (const int32_t*)s.split_rows, (const int32_t*)s.split_cptr,
+                       (const typename Op::Acc*)s.partial, s.nsplit);
     LG_LAUNCH_CHECK();
   }
 }
@@ -303,6 +418,18 @@ class Arena {
   size_t cur_ = 0, off_ = 0, total_ = 0, chunk_;
 };
 
+// Setup temporaries live in arenas that are reused across lg_setup calls
+// (a pool, so concurrent setups on different threads do not share one).
+Arena* acquire_temp_arena();
+void release_temp_arena(Arena* a);
+struct TempArena {
+  TempArena() : a(acquire_temp_arena()) {}
+  ~TempArena() { release_temp_arena(a); }
+  TempArena(const TempArena&) = delete;
+  TempArena& operator=(const TempArena&) = delete;
+  Arena* a;
+};
+
 // ------------------------------------------------- profiling (HIP events)
 struct ProfScope {
   ProfScope(const char* family, hipStream_t st, double bytes);
@@ -328,5 +455,6 @@ void radix_sort_pairs(uint64_t* keys, uint64_t* vals, int64_t n, const std::vect
 std::vector<int> digit_shifts(int bits_lo, int bits_hi);  // digits covering [0,bits_lo) and [32,32+bits_hi)
 int bits_for(int64_t max_value);
 int64_t read_i64(const int64_t* dev, hipStream_t st);
+void read_dev(void* host, const void* dev, size_t bytes, hipStream_t st);
 
 }  // namespace lg

@@ -1,6 +1,7 @@
 // prims.hip -- device primitives shared by the setup passes: exclusive scans,
 // a stable LSD radix sort of (key, payload) pairs, the row scheduler, the
 // device arena and the HIP-event profiler behind lg_profile_*.
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -47,6 +48,28 @@ void Arena::release() {
   for (auto& c : chunks_) (void)hipFree(c.p);
   chunks_.clear();
   cur_ = off_ = total_ = 0;
+}
+
+namespace {
+std::mutex g_pool_mu;
+std::vector<Arena*> g_pool;
+}  // namespace
+
+Arena* acquire_temp_arena() {
+  std::lock_guard<std::mutex> g(g_pool_mu);
+  if (!g_pool.empty()) {
+    Arena* a = g_pool.back();
+    g_pool.pop_back();
+    a->rewind({0, 0});
+    return a;
+  }
+  return new Arena((size_t)256 << 20);
+}
+
+void release_temp_arena(Arena* a) {
+  std::lock_guard<std::mutex> g(g_pool_mu);
+  a->rewind({0, 0});
+  g_pool.push_back(a);
 }
 
 // ---------------------------------------------------------------- profiler
@@ -346,40 +369,119 @@ void radix_sort_pairs(uint64_t* keys, uint64_t* vals, int64_t n, const std::vect
 }
 
 // ------------------------------------------------------------ row schedule
-__global__ void k_max_degree(const int32_t* __restrict__ rp, int64_t n, int* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  int d = (i < n) ? rp[i + 1] - rp[i] : 0;
+constexpr int kStat = 16;  // per block: max deg, min deg, 8 class counts, hubs, splits, chunks
+enum { ST_MAX = 0, ST_MIN = 1, ST_CLS = 2, ST_HUB = 10, ST_SPLIT = 11, ST_CHUNK = 12 };
+
+constexpr int kStatRows = 16;  // rows per thread in k_sched_stats
+
+__global__ __launch_bounds__(kBlock) void k_sched_stats(const int32_t* __restrict__ rp, int64_t n,
+                                                        int hub_deg, int* __restrict__ partial) {
+  int v[kStat];
 #pragma unroll
-  for (int m = 32; m > 0; m >>= 1) d = max(d, __shfl_xor(d, m));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, d);
+  for (int k = 0; k < kStat; k++) v[k] = 0;
+  v[ST_MIN] = 0x7fffffff;
+  for (int q = 0; q < kStatRows; q++) {
+    const int64_t i = ((int64_t)blockIdx.x * kStatRows + q) * kBlock + threadIdx.x;
+    if (i >= n) break;
+    const int d = rp[i + 1] - rp[i];
+    const int c = degree_class(d, hub_deg);
+    v[ST_MAX] = max(v[ST_MAX], d);
+    v[ST_MIN] = min(v[ST_MIN], d);
+    if (c < kClasses) v[ST_CLS + c]++;
+    else if (d > kSplitDeg) {
+      v[ST_SPLIT]++;
+      v[ST_CHUNK] += (d + kHubChunk - 1) / kHubChunk;
+    } else {
+      v[ST_HUB]++;
+    }
+  }
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    v[ST_MAX] = max(v[ST_MAX], __shfl_xor(v[ST_MAX], m));
+    v[ST_MIN] = min(v[ST_MIN], __shfl_xor(v[ST_MIN], m));
+#pragma unroll
+    for (int k = 2; k < kStat; k++) v[k] += __shfl_xor(v[k], m);
+  }
+  __shared__ int sm[kBlock / 64][kStat];
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < kStat; k++) sm[threadIdx.x >> 6][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x < kStat) {
+    const int k = threadIdx.x;
+    int r = sm[0][k];
+    for (int w = 1; w < kBlock / 64; w++)
+      r = k == ST_MAX ? max(r, sm[w][k]) : k == ST_MIN ? min(r, sm[w][k]) : r + sm[w][k];
+    partial[(int64_t)blockIdx.x * kStat + k] = r;
+  }
 }
 
-__global__ void k_hub_flags(const int32_t* __restrict__ rp, int64_t n, int hub_deg,
-                            int32_t* __restrict__ flag, int32_t* __restrict__ nch) {
+// One wavefront per statistic, fixed lane order.
+__global__ __launch_bounds__(kStat * 64) void k_sched_final(const int* __restrict__ partial,
+                                                            int64_t nb, int* __restrict__ out) {
+  const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int r = k == ST_MIN ? 0x7fffffff : 0;
+  for (int64_t b = lane; b < nb; b += 64) {
+    const int v = partial[b * kStat + k];
+    r = k == ST_MAX ? max(r, v) : k == ST_MIN ? min(r, v) : r + v;
+  }
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    const int o = __shfl_xor(r, m);
+    r = k == ST_MAX ? max(r, o) : k == ST_MIN ? min(r, o) : r + o;
+  }
+  if (lane == 0) out[k] = r;
+}
+
+__global__ void k_class_keys(const int32_t* __restrict__ rp, int64_t n, int hub_deg,
+                             uint64_t* __restrict__ keys, uint64_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = (uint64_t)degree_class(rp[i + 1] - rp[i], hub_deg);
+  vals[i] = (uint64_t)i;
+}
+
+__global__ void k_u64_to_i32_n(const uint64_t* __restrict__ in, int64_t n, int32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] = (int32_t)in[i];
+}
+
+__global__ void k_sched_lists(const int32_t* __restrict__ rp, int64_t n, int hub_deg,
+                              int* __restrict__ ctr, int32_t* __restrict__ hub_rows,
+                              int32_t* __restrict__ split_rows, int32_t* __restrict__ split_nch) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int d = rp[i + 1] - rp[i];
-  const bool h = d > hub_deg;
-  flag[i] = h;
-  nch[i] = h ? (d + kHubChunk - 1) / kHubChunk : 0;
+  if (d > kSplitDeg) {
+    const int k = atomicAdd(&ctr[1], 1);
+    split_rows[k] = (int32_t)i;
+    split_nch[k] = (d + kHubChunk - 1) / kHubChunk;
+  } else if (d > hub_deg) {
+    hub_rows[atomicAdd(&ctr[0], 1)] = (int32_t)i;
+  }
 }
 
-__global__ void k_hub_lists(const int32_t* __restrict__ flag, const int32_t* __restrict__ nch,
-                            const int64_t* __restrict__ hidx, const int64_t* __restrict__ cstart,
-                            int64_t n, int32_t* __restrict__ hub_rows, int32_t* __restrict__ hub_cptr,
-                            int32_t* __restrict__ chunk_hub) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n || !flag[i]) return;
-  const int64_t h = hidx[i];
-  hub_rows[h] = (int32_t)i;
-  hub_cptr[h] = (int32_t)cstart[i];
-  for (int k = 0; k < nch[i]; k++) chunk_hub[cstart[i] + k] = (int32_t)h;
+__global__ void k_split_chunk_owner(const int32_t* __restrict__ nch, const int64_t* __restrict__ start,
+                                    int64_t nsplit, int32_t* __restrict__ cptr,
+                                    int32_t* __restrict__ chunk_split) {
+  const int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (h > nsplit) return;
+  cptr[h] = (int32_t)start[h];
+  if (h == nsplit) return;
+  for (int k = 0; k < nch[h]; k++) chunk_split[start[h] + k] = (int32_t)h;
 }
 
-__global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
 __global__ void k_zero_i32n(int32_t* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) p[i] = 0;
+}
+
+void read_dev(void* host, const void* dev, size_t bytes, hipStream_t st) {
+  static thread_local char* pinned = nullptr;
+  if (!pinned) LG_HIP(hipHostMalloc((void**)&pinned, 4096, hipHostMallocDefault));
+  if (bytes > 4096) fail(LG_E_ARG, "read_dev: too large");
+  LG_HIP(hipMemcpyAsync(pinned, dev, bytes, hipMemcpyDeviceToHost, st));
+  LG_HIP(hipStreamSynchronize(st));
+  memcpy(host, pinned, bytes);
 }
 
 void build_sched(Sched& s, const int32_t* rp, int64_t n, int64_t nnz, Arena& keep, Arena& tmp,
@@ -388,39 +490,66 @@ void build_sched(Sched& s, const int32_t* rp, int64_t n, int64_t nnz, Arena& kee
   s.n = n;
   s.nnz = nnz;
   if (n == 0) return;
-  const double avg = (double)nnz / (double)n;
-  int G = 4;
-  while (G < 64 && G < avg) G <<= 1;
-  s.G = G;
-  s.hub_deg = 32 * G > 256 ? 32 * G : 256;
+  s.hub_deg = 1024;
   Arena::Mark m = tmp.mark();
-  int32_t* mx = tmp.get<int32_t>(2);
-  hipLaunchKernelGGL(k_zero_i32n, dim3(1), dim3(kBlock), 0, st, mx, (int64_t)2);
-  hipLaunchKernelGGL(k_max_degree, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, st, rp, n,
-                     (int*)mx);
+  const int64_t nb = ceil_div(n, kBlock);
+  const int64_t nbs = ceil_div(n, (int64_t)kBlock * kStatRows);
+  int* part = tmp.get<int>(kStat * nbs);
+  int* tot = tmp.get<int>(kStat);
+  hipLaunchKernelGGL(k_sched_stats, dim3((unsigned)nbs), dim3(kBlock), 0, st, rp, n, s.hub_deg, part);
+  hipLaunchKernelGGL(k_sched_final, dim3(1), dim3(kStat * 64), 0, st, (const int*)part, nbs, tot);
   LG_LAUNCH_CHECK();
-  int64_t both = read_i64((const int64_t*)mx, st);
-  const int maxdeg = (int)(both & 0xffffffff);
-  if (maxdeg <= s.hub_deg) {
-    tmp.rewind(m);
-    return;
+  int t[kStat];
+  read_dev(t, tot, sizeof(t), st);
+  s.max_deg = t[ST_MAX];
+  s.min_deg = t[ST_MIN];
+  s.nhub = t[ST_HUB];
+  s.nsplit = t[ST_SPLIT];
+  s.nchunk = t[ST_CHUNK];
+  int64_t pos = 0, blk = 0;
+  for (int c = 0; c < kClasses; c++) {
+    s.ct.cls_start[c] = (int32_t)pos;
+    s.ct.blk_start[c] = (int32_t)blk;
+    const int G = c < kClasses - 1 ? (1 << c) : 64;
+    pos += t[ST_CLS + c];
+    blk += ceil_div((int64_t)t[ST_CLS + c] * G, kBlock);
   }
-  int32_t* flag = tmp.get<int32_t>(n);
-  int32_t* nch = tmp.get<int32_t>(n);
-  int64_t* hidx = tmp.get<int64_t>(n + 1);
-  int64_t* cstart = tmp.get<int64_t>(n + 1);
-  hipLaunchKernelGGL(k_hub_flags, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, st, rp, n,
-                     s.hub_deg, flag, nch);
-  s.nhub = scan_i32_to_i64(flag, hidx, n, tmp, st, true);
-  s.nchunk = scan_i32_to_i64(nch, cstart, n, tmp, st, true);
-  s.hub_rows = keep.get<int32_t>(s.nhub);
-  s.hub_cptr = keep.get<int32_t>(s.nhub + 1);
-  s.chunk_hub = keep.get<int32_t>(s.nchunk);
-  s.partial = keep.alloc((size_t)s.nchunk * kPartialBytes);
-  hipLaunchKernelGGL(k_hub_lists, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, st, flag,
-                     nch, hidx, cstart, n, s.hub_rows, s.hub_cptr, s.chunk_hub);
-  hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, st, s.hub_cptr + s.nhub, (int32_t)s.nchunk);
-  LG_LAUNCH_CHECK();
+  s.ct.cls_start[kClasses] = (int32_t)pos;
+  s.ct.blk_start[kClasses] = (int32_t)blk;
+  // rows grouped by class, increasing row id inside a class (stable sort)
+  {
+    uint64_t* keys = tmp.get<uint64_t>(n);
+    uint64_t* vals = tmp.get<uint64_t>(n);
+    hipLaunchKernelGGL(k_class_keys, dim3((unsigned)nb), dim3(kBlock), 0, st, rp, n, s.hub_deg, keys,
+                       vals);
+    radix_sort_pairs(keys, vals, n, std::vector<int>{0}, tmp, st);
+    s.perm = keep.get<int32_t>(pos);
+    if (pos)
+      hipLaunchKernelGGL(k_u64_to_i32_n, dim3((unsigned)ceil_div(pos, kBlock)), dim3(kBlock), 0, st,
+                         (const uint64_t*)vals, pos, s.perm);
+    LG_LAUNCH_CHECK();
+  }
+  if (s.nhub || s.nsplit) {
+    int* ctr = tmp.get<int>(2);
+    hipLaunchKernelGGL(k_zero_i32n, dim3(1), dim3(kBlock), 0, st, (int32_t*)ctr, (int64_t)2);
+    s.hub_rows = keep.get<int32_t>(s.nhub);
+    s.split_rows = keep.get<int32_t>(s.nsplit);
+    int32_t* nch = tmp.get<int32_t>(s.nsplit);
+    hipLaunchKernelGGL(k_sched_lists, dim3((unsigned)nb), dim3(kBlock), 0, st, rp, n, s.hub_deg, ctr,
+                       s.hub_rows, s.split_rows, nch);
+    LG_LAUNCH_CHECK();
+    if (s.nsplit) {
+      int64_t* start = tmp.get<int64_t>(s.nsplit + 1);
+      scan_i32_to_i64(nch, start, s.nsplit, tmp, st, false);
+      s.split_cptr = keep.get<int32_t>(s.nsplit + 1);
+      s.chunk_split = keep.get<int32_t>(s.nchunk);
+      s.partial = keep.alloc((size_t)s.nchunk * kPartialBytes);
+      hipLaunchKernelGGL(k_split_chunk_owner, dim3((unsigned)ceil_div(s.nsplit + 1, kBlock)),
+                         dim3(kBlock), 0, st, (const int32_t*)nch, (const int64_t*)start, s.nsplit,
+                         s.split_cptr, s.chunk_split);
+      LG_LAUNCH_CHECK();
+    }
+  }
   tmp.rewind(m);
 }
 

@@ -43,19 +43,16 @@ struct NoAcc {
 };
 
 // Section 2.1: weights positive, undirected (w_ij = w_ji), no self-loops;
-// plus the CSR rules (columns in range, strictly increasing).
-struct ValidateOp {
-  using Acc = NoAcc;
-  const int32_t* __restrict__ rp;
-  const int32_t* __restrict__ col;
-  const double* __restrict__ w;
-  int64_t n;
-  int* flags;
-  __device__ Acc identity() const { return {0}; }
-  __device__ bool active(int64_t) const { return true; }
-  __device__ void accum(Acc& a, int64_t row, int e) const {
+// plus the CSR rules (columns in range, strictly increasing).  One thread per
+// stored entry, so a hub row costs no more than its entries.
+__global__ void k_validate(const int32_t* __restrict__ rowidx, const int32_t* __restrict__ rp,
+                           const int32_t* __restrict__ col, const double* __restrict__ w,
+                           int64_t n, int64_t nnz, int* __restrict__ flags) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int f = 0;
+  if (e < nnz) {
+    const int row = rowidx[e];
     const int j = col[e];
-    int f = 0;
     if (j < 0 || j >= n) {
       f = F_COL;
     } else {
@@ -76,70 +73,54 @@ struct ValidateOp {
       }
       if (found < 0 || w[found] != we) f |= F_ASYM;
     }
-    a.v |= f;
   }
-  __device__ void combine(Acc& a, const Acc& o) const { a.v |= o.v; }
-  __device__ void finish(int64_t, const Acc& a, int lane, int) const {
-    if (lane == 0 && a.v) atomicOr(flags, a.v);
-  }
-};
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) f |= __shfl_xor(f, m);
+  if ((threadIdx.x & 63) == 0 && f) atomicOr(flags, f);
+}
 
-// ------------------------------------------- connectivity (union-find)
-__device__ __forceinline__ int uf_load(int* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ int uf_find(int* parent, int x) {
-  int cur = x;
-  int next = uf_load(&parent[cur]);
-  while (next != cur) {
-    const int nn = uf_load(&parent[next]);
-    if (nn != next) __hip_atomic_store(&parent[cur], nn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    cur = next;
-    next = nn;
+// ------------------------------------------------------------ connectivity
+// Elimination and aggregation keep the connected components of a graph, except
+// that an isolated vertex disappears when it is eliminated.  So the input is
+// connected iff no level with more than one vertex has an isolated vertex and
+// the coarsest level is connected; the latter is checked here by a
+// breadth-first search in one workgroup (the coarsest level is small).
+__global__ __launch_bounds__(1024) void k_coarse_connected(const int32_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ col, int n,
+                                                           int* __restrict__ seen, int* qa, int* qb,
+                                                           int* __restrict__ out) {
+  __shared__ int nq, nnext, total;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) seen[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    seen[0] = 1;
+    qa[0] = 0;
+    nq = 1;
+    total = 1;
   }
-  return cur;
-}
-// Link the larger root under the smaller one; a failed CAS means another
-// thread linked that root first, so every retry follows progress.
-__device__ void uf_unite(int* parent, int a, int b) {
-  for (;;) {
-    a = uf_find(parent, a);
-    b = uf_find(parent, b);
-    if (a == b) return;
-    if (a > b) {
-      const int t = a;
-      a = b;
-      b = t;
+  __syncthreads();
+  for (int it = 0; it < n; it++) {
+    if (nq == 0) break;
+    if (threadIdx.x == 0) nnext = 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < nq; k += blockDim.x) {
+      const int v = qa[k];
+      for (int e = rp[v]; e < rp[v + 1]; e++) {
+        const int j = col[e];
+        if (atomicExch(&seen[j], 1) == 0) qb[atomicAdd(&nnext, 1)] = j;
+      }
     }
-    if (atomicCAS(&parent[b], b, a) == b) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      total += nnext;
+      nq = nnext;
+    }
+    __syncthreads();
+    int* t = qa;
+    qa = qb;
+    qb = t;
   }
-}
-
-struct UniteOp {
-  using Acc = NoAcc;
-  const int32_t* __restrict__ col;
-  int* parent;
-  int64_t n;
-  __device__ Acc identity() const { return {0}; }
-  __device__ bool active(int64_t) const { return true; }
-  __device__ void accum(Acc&, int64_t row, int e) const {
-    const int j = col[e];
-    if (j > row && j < n) uf_unite(parent, (int)row, j);
-  }
-  __device__ void combine(Acc&, const Acc&) const {}
-  __device__ void finish(int64_t, const Acc&, int, int) const {}
-};
-
-__global__ void k_iota(int* __restrict__ p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) p[i] = (int)i;
-}
-
-__global__ void k_count_roots(int* parent, int64_t n, int* __restrict__ count) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool root = i < n && uf_find(parent, (int)i) == (int)i;
-  const uint64_t m = __ballot(root);
-  if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, __popcll(m));
+  if (threadIdx.x == 0) *out = total;
 }
 
 // ------------------------------------------------------ exact row sums
@@ -710,13 +691,16 @@ __device__ int sturm_below(const double* a, const double* b, int m, double x) {
   return c;
 }
 
-// Largest eigenvalue of the Lanczos tridiagonal by Sturm-count bisection.
-__global__ void k_lz_eig(const double* __restrict__ lz, double* __restrict__ out) {
+// Largest eigenvalue of the Lanczos tridiagonal: multisection with one
+// wavefront, 64 Sturm counts per step, inside the Gershgorin interval.
+__global__ __launch_bounds__(64) void k_lz_eig(const double* __restrict__ lz,
+                                               double* __restrict__ out) {
   const int m = (int)lz[LZ_M];
   const double* a = lz + LZ_AL;
   const double* b = lz + LZ_BE;
+  const int lane = threadIdx.x;
   if (m <= 0) {
-    *out = 0.0;
+    if (lane == 0) *out = 0.0;
     return;
   }
   double lo = 1e300, hi = -1e300;
@@ -727,13 +711,20 @@ __global__ void k_lz_eig(const double* __restrict__ lz, double* __restrict__ out
   }
   hi += 1e-12 * fabs(hi) + 1e-300;
   lo -= 1e-12 * fabs(lo) + 1e-300;
-  for (int it = 0; it < 400; it++) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
-    if (sturm_below(a, b, m, mid) == m) hi = mid;
-    else lo = mid;
+  for (int it = 0; it < 16; it++) {
+    const double step = (hi - lo) / 65.0;
+    if (!(step > 0.0)) break;
+    const double x = lo + step * (lane + 1);
+    const bool above = x < hi && sturm_below(a, b, m, x) == m;  // every eigenvalue below x
+    const uint64_t mask = __ballot(above);
+    const int first = mask ? (int)__ffsll((unsigned long long)mask) - 1 : 64;
+    const double nlo = lo + step * first;
+    const double nhi = first == 64 ? hi : lo + step * (first + 1);
+    if (!(nhi > nlo) || (nlo == lo && nhi == hi)) break;
+    lo = nlo;
+    hi = nhi;
   }
-  *out = 0.5 * (lo + hi);
+  if (lane == 0) *out = 0.5 * (lo + hi);
 }
 
 // --------------------------------------------- coarsest pseudo-inverse
@@ -789,7 +780,8 @@ namespace {
 struct Ctx {
   lg_hierarchy* h;
   hipStream_t st;
-  Arena tmp{(size_t)256 << 20};
+  TempArena lease;
+  Arena& tmp = *lease.a;
   int* flags = nullptr;  // device error flags
   uint64_t key = 0;
 };
@@ -805,6 +797,14 @@ void check_flags(Ctx& c) {
   if (f & F_WEIGHT) fail(LG_E_GRAPH, "edge weight not finite and positive");
   if (f & F_ASYM) fail(LG_E_GRAPH, "adjacency not symmetric");
   if (f & F_XSUM) fail(LG_E_RANGE, "sum outside the exact-sum range (total weight too large)");
+}
+
+// A level with more than one vertex and an isolated vertex: the input graph
+// has more than one connected component (Section 2.1 assumes one).
+void check_isolated(const Level& L) {
+  if (L.n > 1 && L.sched.min_deg == 0)
+    fail(LG_E_DISCONNECTED, "graph is not connected (isolated vertex on a level with " +
+                                std::to_string(L.n) + " vertices)");
 }
 
 // Row sums and reciprocals of a level's adjacency.
@@ -848,6 +848,7 @@ void assemble(Ctx& c, uint64_t* keys, double* vals, int64_t m, int64_t nrows, Le
     LG_LAUNCH_CHECK();
   }
   build_sched(out.sched, out.rp, out.n, out.nnz, h->mem, tmp, c.st);
+  check_isolated(out);
   level_diag(c, out);
 }
 
@@ -1036,7 +1037,7 @@ void lanczos(Ctx& c, Level& L, int level, double* out) {
   const int steps = std::min(o.eig_iters, 64);
   hipLaunchKernelGGL(k_lz_init_scalars, dim3(1), dim3(64), 0, c.st, lz);
   if (n < 2 || steps < 1) {
-    hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(1), 0, c.st, lz, out);
+    hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(64), 0, c.st, lz, out);
     return;
   }
   hipLaunchKernelGGL(k_lz_start, dim3(nblk(n)), dim3(kBlock), 0, c.st, q, qp, n, c.key, level);
@@ -1053,7 +1054,7 @@ void lanczos(Ctx& c, Level& L, int level, double* out) {
     hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(1), 0, c.st, lz, j, steps);
     hipLaunchKernelGGL(k_lz_next, dim3(nblk(n)), dim3(kBlock), 0, c.st, u, q, qp, n, lz, j);
   }
-  hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(1), 0, c.st, lz, out);
+  hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(64), 0, c.st, lz, out);
   LG_LAUNCH_CHECK();
 }
 
@@ -1063,6 +1064,20 @@ void coarsest(Ctx& c, Level& L) {
   if (n > kDenseLimit)
     fail(LG_E_ARG, "coarsening stalled: coarsest level has " + std::to_string(n) +
                        " vertices (dense solve limit " + std::to_string(kDenseLimit) + ")");
+  {
+    Arena::Mark m = c.tmp.mark();
+    int* seen = c.tmp.get<int>(n);
+    int* qa = c.tmp.get<int>(n);
+    int* qb = c.tmp.get<int>(n);
+    int* cnt = c.tmp.get<int>(1);
+    hipLaunchKernelGGL(k_coarse_connected, dim3(1), dim3(1024), 0, c.st, L.rp, L.col, (int)n, seen,
+                       qa, qb, cnt);
+    LG_LAUNCH_CHECK();
+    int reached = 0;
+    read_dev(&reached, cnt, sizeof(int), c.st);
+    c.tmp.rewind(m);
+    if (reached != n) fail(LG_E_DISCONNECTED, "graph is not connected (coarsest level splits)");
+  }
   h->Lplus = h->mem.get<double>(n * n);
   hipLaunchKernelGGL(k_dense_lap, dim3((unsigned)n), dim3(kBlock), 0, c.st, L.rp, L.col, L.w, L.d,
                      n, h->Lplus);
@@ -1123,14 +1138,21 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
     c.tmp.rewind(m);
   }
   build_sched(L0->sched, L0->rp, n, nnz, h->mem, c.tmp, st);
-  if (o.validate) {
-    run_rows(L0->sched, L0->rp, ValidateOp{L0->rp, L0->col, L0->w, n, c.flags}, st);
+  check_isolated(*L0);
+  if (o.validate && nnz) {
+    Arena::Mark m = c.tmp.mark();
+    int32_t* rowidx = c.tmp.get<int32_t>(nnz);
+    run_rows(L0->sched, L0->rp, RowIdxOp{rowidx}, st);
+    hipLaunchKernelGGL(k_validate, dim3(nblk(nnz)), dim3(kBlock), 0, st, rowidx, L0->rp, L0->col,
+                       L0->w, n, nnz, c.flags);
+    LG_LAUNCH_CHECK();
     check_flags(c);
+    c.tmp.rewind(m);
   }
   level_diag(c, *L0);
   check_flags(c);
   {
-    // total weight guard of the exact sums, and connectivity (Section 2.1)
+    // total weight guard of the exact sums
     Arena::Mark m = c.tmp.mark();
     double* part = c.tmp.get<double>(kRedBlocks);
     double* tot = c.tmp.get<double>(1);
@@ -1139,20 +1161,6 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
     LG_HIP(hipMemcpyAsync(&total, tot, sizeof(double), hipMemcpyDeviceToHost, st));
     LG_HIP(hipStreamSynchronize(st));
     if (!(total < 0x1p62)) fail(LG_E_RANGE, "total edge weight must be below 2^62");
-    if (o.validate) {
-      int* parent = c.tmp.get<int>(n);
-      int* cnt = c.tmp.get<int>(2);
-      hipLaunchKernelGGL(k_iota, dim3(nblk(n)), dim3(kBlock), 0, st, parent, n);
-      hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, st, (int32_t*)cnt, (int64_t)2, 0);
-      run_rows(L0->sched, L0->rp, UniteOp{L0->col, parent, n}, st);
-      hipLaunchKernelGGL(k_count_roots, dim3(nblk(n)), dim3(kBlock), 0, st, parent, n, cnt);
-      LG_LAUNCH_CHECK();
-      int roots = 0;
-      LG_HIP(hipMemcpyAsync(&roots, cnt, sizeof(int), hipMemcpyDeviceToHost, st));
-      LG_HIP(hipStreamSynchronize(st));
-      if (roots != 1)
-        fail(LG_E_DISCONNECTED, "graph has " + std::to_string(roots) + " connected components");
-    }
     c.tmp.rewind(m);
   }
 

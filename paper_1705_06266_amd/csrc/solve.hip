@@ -203,15 +203,23 @@ __global__ __launch_bounds__(kBlock) void k_dots(const T* __restrict__ a0, const
   }
 }
 
+// One workgroup per (product, column): a fixed tree over the block partials.
 template <int K, int ND>
-__global__ void k_dots_final(const double* __restrict__ partial, int nb, double* __restrict__ out0,
-                             double* __restrict__ out1) {
-  const int t = threadIdx.x;
-  if (t >= ND * K) return;
+__global__ __launch_bounds__(kBlock) void k_dots_final(const double* __restrict__ partial, int nb,
+                                                       double* __restrict__ out0,
+                                                       double* __restrict__ out1) {
+  const int t = blockIdx.x;
   const int d = t / K, c = t % K;
+  __shared__ double sm[kBlock];
   double s = 0.0;
-  for (int b = 0; b < nb; b++) s += partial[((int64_t)b * ND + d) * K + c];
-  (d == 0 ? out0 : out1)[c] = s;
+  for (int b = threadIdx.x; b < nb; b += kBlock) s += partial[((int64_t)b * ND + d) * K + c];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int m = kBlock / 2; m > 0; m >>= 1) {
+    if ((int)threadIdx.x < m) sm[threadIdx.x] += sm[threadIdx.x + m];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) (d == 0 ? out0 : out1)[c] = sm[0];
 }
 
 template <int K>
@@ -369,7 +377,7 @@ struct Engine {
     const int64_t m = n * K;
     const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ceil_div(m, kBlock)));
     hipLaunchKernelGGL((k_dots<T, K, ND>), dim3(nb), dim3(kBlock), 0, st, a0, b0, a1, b1, m, h->red);
-    hipLaunchKernelGGL((k_dots_final<K, ND>), dim3(1), dim3(64), 0, st, (const double*)h->red, nb,
+    hipLaunchKernelGGL((k_dots_final<K, ND>), dim3(ND * K), dim3(kBlock), 0, st, (const double*)h->red, nb,
                        out0, out1);
   }
 
@@ -560,7 +568,7 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     hipLaunchKernelGGL((k_dots<double, K, 1>), dim3(nb), dim3(kBlock), 0, st, v,
                        (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, m,
                        h->red);
-    hipLaunchKernelGGL((k_dots_final<K, 1>), dim3(1), dim3(64), 0, st, (const double*)h->red, nb,
+    hipLaunchKernelGGL((k_dots_final<K, 1>), dim3(K), dim3(kBlock), 0, st, (const double*)h->red, nb,
                        sl(S_MEAN), (double*)nullptr);
     hipLaunchKernelGGL((k_sub_mean<K>), dim3(g), dim3(kBlock), 0, st, v, (const double*)sl(S_MEAN), n);
   };
@@ -568,7 +576,7 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ceil_div(m, kBlock)));
     hipLaunchKernelGGL((k_dots<double, K, 1>), dim3(nb), dim3(kBlock), 0, st, a, b,
                        (const double*)nullptr, (const double*)nullptr, m, h->red);
-    hipLaunchKernelGGL((k_dots_final<K, 1>), dim3(1), dim3(64), 0, st, (const double*)h->red, nb,
+    hipLaunchKernelGGL((k_dots_final<K, 1>), dim3(K), dim3(kBlock), 0, st, (const double*)h->red, nb,
                        sl(slot), (double*)nullptr);
   };
   auto dot64x2 = [&](const double* a0, const double* b0, const double* a1, const double* b1,
@@ -576,7 +584,7 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ceil_div(m, kBlock)));
     hipLaunchKernelGGL((k_dots<double, K, 2>), dim3(nb), dim3(kBlock), 0, st, a0, b0, a1, b1, m,
                        h->red);
-    hipLaunchKernelGGL((k_dots_final<K, 2>), dim3(1), dim3(64), 0, st, (const double*)h->red, nb,
+    hipLaunchKernelGGL((k_dots_final<K, 2>), dim3(2 * K), dim3(kBlock), 0, st, (const double*)h->red, nb,
                        sl(s0), sl(s1));
   };
 

@@ -25,6 +25,7 @@ CASES = {
     "rmat_s12": lambda: gg.rmat(12, 16, seed=2),
     "chunglu_30k_hubs": lambda: gg.chung_lu(30000, seed=6, max_deg=9000),
     "star_6000": lambda: gg.star(6000),
+    "star_40000_split_hub": lambda: gg.star(40000),
     "path_333": lambda: gg.path(333),
     "gnp_700": lambda: gg.gnp(700, 0.01, seed=3),
     "cycle_64": lambda: gg.cycle(64),
