@@ -39,6 +39,14 @@ WORKLOADS = {
                      label="rmat_s18_ef16_lcc_u01_fp64_1rhs"),
     "grid2d_64": dict(cfg="c1_grid2d_64", precision="fp64", k=1,
                       label="grid2d_64x64_unit_fp64_1rhs"),
+    "grid3d_128_mixed": dict(cfg="c3_grid3d_128", precision="mixed", k=32,
+                             label="grid3d_128cube_loguniform_mixed_32rhs"),
+    "grid3d_128_fp64": dict(cfg="c3_grid3d_128", precision="fp64", k=32,
+                            label="grid3d_128cube_loguniform_fp64_32rhs"),
+    "chunglu_4m_mixed": dict(cfg="c4_chunglu_4m", precision="mixed", k=16,
+                             label="chunglu_4m_g2.1_d16_mixed_16rhs"),
+    "chunglu_4m_fp64": dict(cfg="c4_chunglu_4m", precision="fp64", k=16,
+                            label="chunglu_4m_g2.1_d16_fp64_16rhs"),
 }
 
 
@@ -162,7 +170,8 @@ def main():
 
     # fp64 SpMV bandwidth on the finest level (algorithmic bytes)
     n0, m0 = stats[0]["n"], stats[0]["nnz"]
-    x = torch.randn(n0, 1, dtype=torch.float64, device=dev)
+    kk = 1 if wl["k"] == 1 else min(32, 1 << (wl["k"] - 1).bit_length())
+    x = torch.randn(n0, kk, dtype=torch.float64, device=dev)
     y = torch.empty_like(x)
     for _ in range(3):
         lg.lg_spmv(h, 0, x, y)
@@ -213,9 +222,10 @@ def main():
                        "p99_ms": float(np.percentile(lat, 99)), "solves": int(lat.size)},
         "spmv_fp64_gbs": spmv_gbs,
         "spmv_fp64_ms": sp_ms / sp_n if sp_n else None,
+        "spmv_fp64_rhs": kk,
     }
     del h
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload in ("rmat_s18", "grid2d_64"):
         out["cpu_baseline"] = cpu_baseline(g, b_host)
     print(json.dumps(out), flush=True)
 

@@ -384,6 +384,176 @@ void run_rows(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st) {
   }
 }
 
+// ----------------------------------------------- column-split row ops
+// For k right-hand sides whose row of values spans at least 32 bytes, kL =
+// k * sizeof(T) / 16 lanes share each matrix entry and each lane owns one
+// 16-byte slice of the k columns (one vector load per entry).  An ordinary row
+// is reduced by one such group with no cross-lane sums; a hub row by all the
+// groups of a workgroup; a split row by one workgroup per chunk plus a second
+// pass.  Op interface: kL, Acc, identity(), active(row),
+// accum(acc, row, e, part), combine(a, b), finish(row, acc, part).
+// M groups of kL lanes per row for the rows perm[p0, p1): group g takes entries
+// beg + g, beg + g + M, ...; the groups' sums are combined by a butterfly.
+template <class Op, int M>
+__device__ __forceinline__ void col_rows(const Op& op, const int32_t* __restrict__ rp,
+                                         const int32_t* __restrict__ perm, int64_t p0, int64_t p1,
+                                         int64_t lb) {
+  constexpr int L = Op::kL, T = L * M;
+  const int64_t pos = p0 + (lb * kBlock + threadIdx.x) / T;
+  const int part = threadIdx.x & (L - 1);
+  const int grp = (threadIdx.x / L) & (M - 1);
+  if (pos >= p1) return;
+  const int64_t row = perm[pos];
+  typename Op::Acc acc = op.identity();
+  if (op.active(row)) {
+    const int end = rp[row + 1];
+    int e = rp[row] + grp;
+    for (; e + 3 * M < end; e += 4 * M) {
+      op.accum(acc, row, e, part);
+      op.accum(acc, row, e + M, part);
+      op.accum(acc, row, e + 2 * M, part);
+      op.accum(acc, row, e + 3 * M, part);
+    }
+    for (; e < end; e += M) op.accum(acc, row, e, part);
+#pragma unroll
+    for (int m = T / 2; m >= L; m >>= 1) op.combine(acc, shfl_xor_any(acc, m));
+  }
+  if (grp == 0) op.finish(row, acc, part);
+}
+
+// Entries [beg, end) of `row` by all kBlock / kL groups of the workgroup; the
+// per-part totals end up on threads 0 .. kL-1 (returned there, identity elsewhere).
+template <class Op>
+__device__ __forceinline__ typename Op::Acc col_block_reduce(const Op& op, int64_t row, int beg,
+                                                             int end) {
+  using Acc = typename Op::Acc;
+  constexpr int L = Op::kL, NG = kBlock / L;
+  const int grp = threadIdx.x / L, part = threadIdx.x & (L - 1);
+  Acc acc = op.identity();
+  if (op.active(row)) {
+    int e = beg + grp;
+    for (; e + 3 * NG < end; e += 4 * NG) {
+      op.accum(acc, row, e, part);
+      op.accum(acc, row, e + NG, part);
+      op.accum(acc, row, e + 2 * NG, part);
+      op.accum(acc, row, e + 3 * NG, part);
+    }
+    for (; e < end; e += NG) op.accum(acc, row, e, part);
+  }
+#pragma unroll
+  for (int m = 32; m >= L; m >>= 1) op.combine(acc, shfl_xor_any(acc, m));
+  __shared__ Acc red[kBlock / 64][L];
+  if ((threadIdx.x & 63) < L) red[threadIdx.x >> 6][threadIdx.x & 63] = acc;
+  __syncthreads();
+  Acc t = op.identity();
+  if (threadIdx.x < L) {
+    t = red[0][threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; w++) op.combine(t, red[w][threadIdx.x]);
+  }
+  return t;
+}
+
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_rows_col(Op op, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ perm,
+                                                     ClassTable ct, int64_t nhub,
+                                                     const int32_t* __restrict__ hub_rows,
+                                                     int64_t nchunk,
+                                                     const int32_t* __restrict__ split_rows,
+                                                     const int32_t* __restrict__ split_cptr,
+                                                     const int32_t* __restrict__ chunk_split,
+                                                     typename Op::Acc* __restrict__ partial) {
+  constexpr int L = Op::kL;
+  int64_t b = blockIdx.x;
+  if (b < nchunk) {
+    const int h = chunk_split[b];
+    const int64_t row = split_rows[h];
+    const int beg = rp[row] + (int)(b - split_cptr[h]) * kHubChunk;
+    const int end = min(rp[row + 1], beg + kHubChunk);
+    const typename Op::Acc t = col_block_reduce(op, row, beg, end);
+    if (threadIdx.x < L) partial[b * L + threadIdx.x] = t;
+    return;
+  }
+  b -= nchunk;
+  if (b < nhub) {
+    const int64_t row = hub_rows[b];
+    const typename Op::Acc t = col_block_reduce(op, row, rp[row], rp[row + 1]);
+    if (threadIdx.x < L) op.finish(row, t, (int)threadIdx.x);
+    return;
+  }
+  b -= nhub;
+  const int64_t total = ct.blk_start[kClasses];
+  const int64_t stride = (int64_t)gridDim.x - nchunk - nhub;
+  for (int64_t q = b; q < total; q += stride) {
+    int c = 0;
+#pragma unroll
+    for (int k = 1; k < kClasses; k++) c += (q >= ct.blk_start[k]) ? 1 : 0;
+    const int64_t p0 = ct.cls_start[c], p1 = ct.cls_start[c + 1], lb = q - ct.blk_start[c];
+    constexpr int MM = 64 / L;  // most groups a row may span inside one wavefront
+    switch (c) {
+      case 0: col_rows<Op, 1>(op, rp, perm, p0, p1, lb); break;
+      case 1: col_rows<Op, (2 < MM ? 2 : MM)>(op, rp, perm, p0, p1, lb); break;
+      case 2: col_rows<Op, (4 < MM ? 4 : MM)>(op, rp, perm, p0, p1, lb); break;
+      case 3: col_rows<Op, (8 < MM ? 8 : MM)>(op, rp, perm, p0, p1, lb); break;
+      case 4: col_rows<Op, (16 < MM ? 16 : MM)>(op, rp, perm, p0, p1, lb); break;
+      case 5: col_rows<Op, (32 < MM ? 32 : MM)>(op, rp, perm, p0, p1, lb); break;
+      case 6: col_rows<Op, MM>(op, rp, perm, p0, p1, lb); break;
+      default: {  // one workgroup per row
+        const int64_t row = perm[p0 + lb];
+        const typename Op::Acc t = col_block_reduce(op, row, rp[row], rp[row + 1]);
+        if (threadIdx.x < L) op.finish(row, t, (int)threadIdx.x);
+        __syncthreads();  // the next row reuses the reduction buffer
+        break;
+      }
+    }
+  }
+}
+
+template <class Op>
+__global__ __launch_bounds__(64) void k_split_fix_col(Op op, const int32_t* __restrict__ split_rows,
+                                                      const int32_t* __restrict__ split_cptr,
+                                                      const typename Op::Acc* __restrict__ partial,
+                                                      int64_t nsplit) {
+  constexpr int L = Op::kL;
+  const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (t >= nsplit * L) return;
+  const int64_t h = t / L;
+  const int part = (int)(t % L);
+  typename Op::Acc acc = op.identity();
+  for (int c = split_cptr[h]; c < split_cptr[h + 1]; c++) op.combine(acc, partial[(int64_t)c * L + part]);
+  op.finish((int64_t)split_rows[h], acc, part);
+}
+
+template <class Op>
+void run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st) {
+  constexpr int L = Op::kL;
+  static_assert(sizeof(typename Op::Acc) * L <= kPartialBytes, "partial slot too small");
+  if (s.n == 0) return;
+  ClassTable ct = s.ct;
+  int64_t blk = 0;
+  for (int c = 0; c < kClasses; c++) {
+    ct.blk_start[c] = (int32_t)blk;
+    const int64_t rows = s.ct.cls_start[c + 1] - s.ct.cls_start[c];
+    const int64_t M = std::min<int64_t>((int64_t)1 << c, 64 / L);
+    blk += c == kClasses - 1 ? rows : ceil_div(rows * L * M, kBlock);
+  }
+  ct.blk_start[kClasses] = (int32_t)blk;
+  const int64_t blocks = s.nchunk + s.nhub + std::min<int64_t>(blk, kRowGrid);
+  if (blocks == 0) return;
+  hipLaunchKernelGGL((k_rows_col<Op>), dim3((unsigned)blocks), dim3(kBlock), 0, st, op, rp,
+                     (const int32_t*)s.perm, ct, s.nhub, (const int32_t*)s.hub_rows, s.nchunk,
+                     (const int32_t*)s.split_rows, (const int32_t*)s.split_cptr,
+                     (const int32_t*)s.chunk_split, reinterpret_cast<typename Op::Acc*>(s.partial));
+  LG_LAUNCH_CHECK();
+  if (s.nsplit) {
+    hipLaunchKernelGGL((k_split_fix_col<Op>), dim3((unsigned)ceil_div(s.nsplit * L, 64)), dim3(64), 0,
+                       st, op, (const int32_t*)s.split_rows, (const int32_t*)s.split_cptr,
+                       (const typename Op::Acc*)s.partial, s.nsplit);
+    LG_LAUNCH_CHECK();
+  }
+}
+
 // ------------------------------------------------------------- memory
 // Bump allocator over large device chunks.  The hierarchy owns one for its
 // lifetime; setup uses a second one for temporaries and rewinds it per level.

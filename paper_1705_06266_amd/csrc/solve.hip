@@ -123,6 +123,77 @@ struct PtOp {
   }
 };
 
+// Column-split forms of the two restrictions (k * sizeof(T) >= 32 bytes).
+template <typename T, int K>
+struct GatherSumColOp {
+  static constexpr int V = 16 / (int)sizeof(T);
+  static constexpr int kL = K / V;
+  using Acc = VecAcc<T, V>;
+  typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
+  const int32_t* __restrict__ idx;
+  const T* __restrict__ src;
+  T* __restrict__ out;
+  __device__ Acc identity() const {
+    Acc a;
+#pragma unroll
+    for (int v = 0; v < V; v++) a.v[v] = T(0);
+    return a;
+  }
+  __device__ bool active(int64_t) const { return true; }
+  __device__ void accum(Acc& a, int64_t, int e, int part) const {
+    const vec_t s = *reinterpret_cast<const vec_t*>(src + (int64_t)idx[e] * K + part * V);
+#pragma unroll
+    for (int v = 0; v < V; v++) a.v[v] += s[v];
+  }
+  __device__ void combine(Acc& a, const Acc& o) const {
+#pragma unroll
+    for (int v = 0; v < V; v++) a.v[v] += o.v[v];
+  }
+  __device__ void finish(int64_t row, const Acc& a, int part) const {
+    vec_t o;
+#pragma unroll
+    for (int v = 0; v < V; v++) o[v] = a.v[v];
+    *reinterpret_cast<vec_t*>(out + row * K + part * V) = o;
+  }
+};
+
+template <typename T, int K>
+struct PtColOp {
+  static constexpr int V = 16 / (int)sizeof(T);
+  static constexpr int kL = K / V;
+  using Acc = VecAcc<T, V>;
+  typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
+  const int32_t* __restrict__ ptf;
+  const T* __restrict__ ptc;
+  const int32_t* __restrict__ cvert;
+  const T* __restrict__ b;
+  T* __restrict__ bc;
+  __device__ Acc identity() const {
+    Acc a;
+#pragma unroll
+    for (int v = 0; v < V; v++) a.v[v] = T(0);
+    return a;
+  }
+  __device__ bool active(int64_t) const { return true; }
+  __device__ void accum(Acc& a, int64_t, int e, int part) const {
+    const T cf = ptc[e];
+    const vec_t s = *reinterpret_cast<const vec_t*>(b + (int64_t)ptf[e] * K + part * V);
+#pragma unroll
+    for (int v = 0; v < V; v++) a.v[v] += cf * s[v];
+  }
+  __device__ void combine(Acc& a, const Acc& o) const {
+#pragma unroll
+    for (int v = 0; v < V; v++) a.v[v] += o.v[v];
+  }
+  __device__ void finish(int64_t row, const Acc& a, int part) const {
+    const vec_t bv = *reinterpret_cast<const vec_t*>(b + (int64_t)cvert[row] * K + part * V);
+    vec_t o;
+#pragma unroll
+    for (int v = 0; v < V; v++) o[v] = bv[v] + a.v[v];
+    *reinterpret_cast<vec_t*>(bc + row * K + part * V) = o;
+  }
+};
+
 // Coarsest level: x = L^+ b with the fp64 dense pseudo-inverse; one wavefront per row.
 template <typename T, int K>
 __global__ __launch_bounds__(kBlock) void k_coarse(const double* __restrict__ Lp,
@@ -366,9 +437,13 @@ struct Engine {
   void lap(const Level& L, const T* x, T* y, const T* b, T* p, T c1, T c2, const char* fam,
            int vecs) {
     Vals<T> v = vals_of<T>(L);
-    LapOp<T, K, MODE> op{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2};
     ProfScope ps(fam, st, spmm_bytes(L, K, (int)sizeof(T), vecs) + (MODE >= LAP_CHEB ? 8.0 * L.n : 0));
-    run_rows(L.sched, L.rp, op, st);
+    if constexpr (use_col_split<T, K>()) {
+      run_rows_col(L.sched, L.rp, LapColOp<T, K, MODE>{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2},
+                   st);
+    } else {
+      run_rows(L.sched, L.rp, LapOp<T, K, MODE>{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2}, st);
+    }
   }
 
   template <int ND>
@@ -398,7 +473,10 @@ struct Engine {
       T* bc = (T*)C.vb;
       {
         ProfScope ps("restrict", st, 0.0);
-        run_rows(L.ptsched, L.ptrp, PtOp<T, K>{L.ptf, v.ptc, L.cvert, b, bc}, st);
+        if constexpr (use_col_split<T, K>())
+          run_rows_col(L.ptsched, L.ptrp, PtColOp<T, K>{L.ptf, v.ptc, L.cvert, b, bc}, st);
+        else
+          run_rows(L.ptsched, L.ptrp, PtOp<T, K>{L.ptf, v.ptc, L.cvert, b, bc}, st);
       }
       const T* xc = level(l + 1, bc);  // elimination interpolates exactly: no Krylov step here
       ProfScope ps("prolong", st, 0.0);
@@ -435,7 +513,10 @@ struct Engine {
     T* bc = (T*)C.vb;
     {
       ProfScope ps("restrict", st, 4.0 * (L.nc + 1) + 4.0 * n + 2.0 * K * n * sizeof(T));
-      run_rows(L.msched, L.mptr, GatherSumOp<T, K>{L.mem, r, bc}, st);
+      if constexpr (use_col_split<T, K>())
+        run_rows_col(L.msched, L.mptr, GatherSumColOp<T, K>{L.mem, r, bc}, st);
+      else
+        run_rows(L.msched, L.mptr, GatherSumOp<T, K>{L.mem, r, bc}, st);
     }
     const T* xc = (o.cycle == LG_CYCLE_K && C.type != LG_LEVEL_COARSEST) ? fcg2(l + 1, bc)
                                                                           : level(l + 1, bc);
@@ -514,12 +595,24 @@ void lap64(lg_hierarchy* h, int l, const double* x, double* y, const double* b, 
            const char* fam) {
   const Level& L = h->lev[l];
   ProfScope ps(fam, st, spmm_bytes(L, K, 8, b ? 3 : 2));
-  if (b) {
-    LapOp<double, K, LAP_RESID> op{L.col, L.w, L.d, L.dinv, x, y, b, nullptr, 0.0, 0.0};
-    run_rows(L.sched, L.rp, op, st);
+  if constexpr (use_col_split<double, K>()) {
+    if (b)
+      run_rows_col(L.sched, L.rp,
+                   LapColOp<double, K, LAP_RESID>{L.col, L.w, L.d, L.dinv, x, y, b, nullptr, 0.0, 0.0},
+                   st);
+    else
+      run_rows_col(L.sched, L.rp,
+                   LapColOp<double, K, LAP_SPMV>{L.col, L.w, L.d, L.dinv, x, y, nullptr, nullptr, 0.0,
+                                                 0.0},
+                   st);
   } else {
-    LapOp<double, K, LAP_SPMV> op{L.col, L.w, L.d, L.dinv, x, y, nullptr, nullptr, 0.0, 0.0};
-    run_rows(L.sched, L.rp, op, st);
+    if (b)
+      run_rows(L.sched, L.rp,
+               LapOp<double, K, LAP_RESID>{L.col, L.w, L.d, L.dinv, x, y, b, nullptr, 0.0, 0.0}, st);
+    else
+      run_rows(L.sched, L.rp,
+               LapOp<double, K, LAP_SPMV>{L.col, L.w, L.d, L.dinv, x, y, nullptr, nullptr, 0.0, 0.0},
+               st);
   }
 }
 
