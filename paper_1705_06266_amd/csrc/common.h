@@ -320,8 +320,27 @@ __global__ __launch_bounds__(64) void k_split_fix(Op op, const int32_t* __restri
 // Ordinary rows run on a bounded grid of workgroups that loop over the
 // logical row blocks (kRowGrid covers the chip several times over): short
 // rows make short-lived waves, and re-dispatching them costs more than the
-// work they do.
+// work they do.  Workgroups are dealt to the 8 XCDs round-robin by index and
+// each XCD has its own L2, so the row region starts at a multiple of 8 and
+// XCD x takes the x-th contiguous eighth of every degree class: neighbouring
+// rows (which share cache lines and, on meshes, neighbours) stay in one L2,
+// while each XCD still gets an equal share of every class.
 constexpr int64_t kRowGrid = 2048;
+constexpr int kXcds = 8;
+
+__host__ __device__ inline int64_t round_up8(int64_t v) { return (v + kXcds - 1) / kXcds * kXcds; }
+
+// Calls f(c, q) for the logical blocks q of class c owned by this workgroup.
+template <class F>
+__device__ __forceinline__ void for_class_blocks(const ClassTable& ct, int64_t b, int64_t slots,
+                                                 F&& f) {
+  const int64_t x = b % kXcds, s = b / kXcds;
+  for (int c = 0; c < kClasses; c++) {
+    const int64_t c0 = ct.blk_start[c], nbc = ct.blk_start[c + 1] - c0;
+    const int64_t lo = c0 + x * nbc / kXcds, hi = c0 + (x + 1) * nbc / kXcds;
+    for (int64_t q = lo + s; q < hi; q += slots) f(c, q - c0);
+  }
+}
 
 template <class Op>
 __global__ __launch_bounds__(kBlock) void k_rows(Op op, const int32_t* __restrict__ rp,
@@ -342,8 +361,11 @@ __global__ __launch_bounds__(kBlock) void k_rows(Op op, const int32_t* __restric
     return;
   }
   b -= nhub;
+  const int64_t pad = round_up8(nchunk + nhub) - nchunk - nhub;
+  if (b < pad) return;
+  b -= pad;
   const int64_t total = ct.blk_start[kClasses];
-  const int64_t stride = (int64_t)gridDim.x - nchunk - nhub;
+  const int64_t stride = (int64_t)gridDim.x - nchunk - nhub - pad;
   for (int64_t q = b; q < total; q += stride) {
     int c = 0;
 #pragma unroll
@@ -368,8 +390,8 @@ void run_rows(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st) {
   static_assert(sizeof(typename Op::Acc) <= kPartialBytes, "accumulator larger than a partial slot");
   static_assert(sizeof(typename Op::Acc) % 4 == 0, "accumulator size must be a multiple of 4");
   if (s.n == 0) return;
-  const int64_t row_blocks = std::min<int64_t>(s.ct.blk_start[kClasses], kRowGrid);
-  const int64_t blocks = s.nchunk + s.nhub + row_blocks;
+  const int64_t total = s.ct.blk_start[kClasses];
+  const int64_t blocks = round_up8(s.nchunk + s.nhub) + round_up8(std::min<int64_t>(total, kRowGrid));
   if (blocks == 0) return;
   hipLaunchKernelGGL((k_rows<Op>), dim3((unsigned)blocks), dim3(kBlock), 0, st, op, rp,
                      (const int32_t*)s.perm, s.ct, s.nhub, (const int32_t*)s.hub_rows, s.nchunk,
@@ -483,22 +505,21 @@ __global__ __launch_bounds__(kBlock) void k_rows_col(Op op, const int32_t* __res
     return;
   }
   b -= nhub;
-  const int64_t total = ct.blk_start[kClasses];
-  const int64_t stride = (int64_t)gridDim.x - nchunk - nhub;
-  for (int64_t q = b; q < total; q += stride) {
-    int c = 0;
-#pragma unroll
-    for (int k = 1; k < kClasses; k++) c += (q >= ct.blk_start[k]) ? 1 : 0;
-    const int64_t p0 = ct.cls_start[c], p1 = ct.cls_start[c + 1], lb = q - ct.blk_start[c];
-    constexpr int MM = 64 / L;  // most groups a row may span inside one wavefront
+  const int64_t pad = round_up8(nchunk + nhub) - nchunk - nhub;
+  if (b < pad) return;
+  b -= pad;
+  const int64_t slots = ((int64_t)gridDim.x - nchunk - nhub - pad) / kXcds;
+  constexpr int MM = 64 / L;  // most groups a row may span inside one wavefront
+  for_class_blocks(ct, b, slots, [&](int c, int64_t lb) {
+    const int64_t p0 = ct.cls_start[c], p1 = ct.cls_start[c + 1];
     switch (c) {
       case 0: col_rows<Op, 1>(op, rp, perm, p0, p1, lb); break;
-      case 1: col_rows<Op, (2 < MM ? 2 : MM)>(op, rp, perm, p0, p1, lb); break;
-      case 2: col_rows<Op, (4 < MM ? 4 : MM)>(op, rp, perm, p0, p1, lb); break;
-      case 3: col_rows<Op, (8 < MM ? 8 : MM)>(op, rp, perm, p0, p1, lb); break;
-      case 4: col_rows<Op, (16 < MM ? 16 : MM)>(op, rp, perm, p0, p1, lb); break;
-      case 5: col_rows<Op, (32 < MM ? 32 : MM)>(op, rp, perm, p0, p1, lb); break;
-      case 6: col_rows<Op, MM>(op, rp, perm, p0, p1, lb); break;
+      case 1: col_rows<Op, 1>(op, rp, perm, p0, p1, lb); break;
+      case 2: col_rows<Op, (2 < MM ? 2 : MM)>(op, rp, perm, p0, p1, lb); break;
+      case 3: col_rows<Op, (4 < MM ? 4 : MM)>(op, rp, perm, p0, p1, lb); break;
+      case 4: col_rows<Op, (8 < MM ? 8 : MM)>(op, rp, perm, p0, p1, lb); break;
+      case 5: col_rows<Op, (16 < MM ? 16 : MM)>(op, rp, perm, p0, p1, lb); break;
+      case 6: col_rows<Op, (32 < MM ? 32 : MM)>(op, rp, perm, p0, p1, lb); break;
       default: {  // one workgroup per row
         const int64_t row = perm[p0 + lb];
         const typename Op::Acc t = col_block_reduce(op, row, rp[row], rp[row + 1]);
@@ -507,7 +528,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_col(Op op, const int32_t* __res
         break;
       }
     }
-  }
+  });
 }
 
 template <class Op>
@@ -535,11 +556,11 @@ void run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_t s
   for (int c = 0; c < kClasses; c++) {
     ct.blk_start[c] = (int32_t)blk;
     const int64_t rows = s.ct.cls_start[c + 1] - s.ct.cls_start[c];
-    const int64_t M = std::min<int64_t>((int64_t)1 << c, 64 / L);
+    const int64_t M = std::min<int64_t>(c == 0 ? 1 : (int64_t)1 << (c - 1), 64 / L);
     blk += c == kClasses - 1 ? rows : ceil_div(rows * L * M, kBlock);
   }
   ct.blk_start[kClasses] = (int32_t)blk;
-  const int64_t blocks = s.nchunk + s.nhub + std::min<int64_t>(blk, kRowGrid);
+  const int64_t blocks = round_up8(s.nchunk + s.nhub) + round_up8(std::min<int64_t>(blk, kRowGrid));
   if (blocks == 0) return;
   hipLaunchKernelGGL((k_rows_col<Op>), dim3((unsigned)blocks), dim3(kBlock), 0, st, op, rp,
                      (const int32_t*)s.perm, ct, s.nhub, (const int32_t*)s.hub_rows, s.nchunk,

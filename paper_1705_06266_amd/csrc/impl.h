@@ -91,7 +91,8 @@ struct lg_hierarchy {
 };
 
 namespace lg {
-constexpr int kRedBlocks = 240;  // fixed grid of the two-stage reductions
+constexpr int kRedBlocks = 240;   // grid of the setup's scalar reductions
+constexpr int kDotPartials = 2048;  // most workgroups of a column-dot launch
 // scalar slots (each K wide) of lg_hierarchy::scal
 enum {
   S_BN = 0, S_RZ, S_PQ, S_ALPHA, S_BETA, S_RR, S_PR, S_ZQ, S_ACTIVE, S_MEAN, S_TMP, S_TR,

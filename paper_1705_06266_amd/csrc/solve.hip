@@ -250,25 +250,55 @@ __global__ void k_pad_out(const double* __restrict__ in, int K, double* __restri
 }
 
 // Two-stage deterministic column dot products: ND products (a_d . b_d) per
-// column, or column sums where b_d is null.  Fixed grid and reduction order.
+// column, or column sums where b_d is null.  Each thread reads 16-byte
+// vectors; the grid is sized to the data (up to kDotBlocks workgroups) and its
+// mapping, hence the summation order, is fixed.
+constexpr int kDotBlocks = kDotPartials;
+
 template <typename T, int K, int ND>
 __global__ __launch_bounds__(kBlock) void k_dots(const T* __restrict__ a0, const T* __restrict__ b0,
                                                  const T* __restrict__ a1, const T* __restrict__ b1,
                                                  int64_t m, double* __restrict__ partial) {
-  double s0 = 0.0, s1 = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
-       i += (int64_t)gridDim.x * kBlock) {
-    s0 += b0 ? (double)a0[i] * (double)b0[i] : (double)a0[i];
-    if (ND > 1) s1 += (double)a1[i] * (double)b1[i];
+  constexpr int V = 16 / (int)sizeof(T);
+  typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
+  double s0[V], s1[V];
+#pragma unroll
+  for (int v = 0; v < V; v++) s0[v] = s1[v] = 0.0;
+  const int64_t nvec = m / V;  // m = n * K is a multiple of V whenever K >= V; else tail below
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nvec; q += stride) {
+    const vec_t x0 = reinterpret_cast<const vec_t*>(a0)[q];
+    vec_t y0;
+    if (b0) y0 = reinterpret_cast<const vec_t*>(b0)[q];
+#pragma unroll
+    for (int v = 0; v < V; v++) s0[v] += b0 ? (double)x0[v] * (double)y0[v] : (double)x0[v];
+    if (ND > 1) {
+      const vec_t x1 = reinterpret_cast<const vec_t*>(a1)[q];
+      const vec_t y1 = reinterpret_cast<const vec_t*>(b1)[q];
+#pragma unroll
+      for (int v = 0; v < V; v++) s1[v] += (double)x1[v] * (double)y1[v];
+    }
   }
-  __shared__ double sm[ND][kBlock];
-  sm[0][threadIdx.x] = s0;
-  if (ND > 1) sm[ND - 1][threadIdx.x] = s1;
+  // scalar tail (only when m is not a multiple of V, i.e. K < V and n odd)
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int64_t i = nvec * V; i < m; i++) {
+      const int v = (int)(i % V);
+      s0[v] += b0 ? (double)a0[i] * (double)b0[i] : (double)a0[i];
+      if (ND > 1) s1[v] += (double)a1[i] * (double)b1[i];
+    }
+  }
+  // element t*V+v of any block belongs to column (t*V+v) % K
+  __shared__ double sm[ND][kBlock * V];
+#pragma unroll
+  for (int v = 0; v < V; v++) {
+    sm[0][threadIdx.x * V + v] = s0[v];
+    if (ND > 1) sm[ND - 1][threadIdx.x * V + v] = s1[v];
+  }
   __syncthreads();
   if ((int)threadIdx.x < K) {
     for (int d = 0; d < ND; d++) {
       double t = 0.0;
-      for (int q = threadIdx.x; q < kBlock; q += K) t += sm[d][q];
+      for (int q = threadIdx.x; q < kBlock * V; q += K) t += sm[d][q];
       partial[((int64_t)blockIdx.x * ND + d) * K + threadIdx.x] = t;
     }
   }
@@ -424,6 +454,14 @@ inline Vals<float> vals_of<float>(const Level& L) {
   return {L.wf, L.df, L.dinvf, L.ptcf};
 }
 
+// Workgroups of a column-dot launch: about four 16-byte loads per thread,
+// at most kDotBlocks.
+template <typename T>
+inline int dot_blocks(int64_t m) {
+  const int64_t vecs = ceil_div(m, 16 / (int64_t)sizeof(T));
+  return (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, ceil_div(vecs, (int64_t)kBlock * 4)));
+}
+
 inline double spmm_bytes(const Level& L, int K, int s, int vecs) {
   return 4.0 * (L.n + 1) + (double)L.nnz * (4 + s) + (double)L.n * s + (double)vecs * K * L.n * s;
 }
@@ -450,7 +488,7 @@ struct Engine {
   void dots(const T* a0, const T* b0, const T* a1, const T* b1, int64_t n, double* out0,
             double* out1) {
     const int64_t m = n * K;
-    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ceil_div(m, kBlock)));
+    const int nb = dot_blocks<T>(m);
     hipLaunchKernelGGL((k_dots<T, K, ND>), dim3(nb), dim3(kBlock), 0, st, a0, b0, a1, b1, m, h->red);
     hipLaunchKernelGGL((k_dots_final<K, ND>), dim3(ND * K), dim3(kBlock), 0, st, (const double*)h->red, nb,
                        out0, out1);
@@ -657,7 +695,7 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
                           st));
   };
   auto project64 = [&](double* v) {
-    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ceil_div(m, kBlock)));
+    const int nb = dot_blocks<double>(m);
     hipLaunchKernelGGL((k_dots<double, K, 1>), dim3(nb), dim3(kBlock), 0, st, v,
                        (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, m,
                        h->red);
@@ -666,7 +704,7 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     hipLaunchKernelGGL((k_sub_mean<K>), dim3(g), dim3(kBlock), 0, st, v, (const double*)sl(S_MEAN), n);
   };
   auto dot64 = [&](const double* a, const double* b, int slot) {
-    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ceil_div(m, kBlock)));
+    const int nb = dot_blocks<double>(m);
     hipLaunchKernelGGL((k_dots<double, K, 1>), dim3(nb), dim3(kBlock), 0, st, a, b,
                        (const double*)nullptr, (const double*)nullptr, m, h->red);
     hipLaunchKernelGGL((k_dots_final<K, 1>), dim3(K), dim3(kBlock), 0, st, (const double*)h->red, nb,
@@ -674,7 +712,7 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
   };
   auto dot64x2 = [&](const double* a0, const double* b0, const double* a1, const double* b1,
                      int s0, int s1) {
-    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ceil_div(m, kBlock)));
+    const int nb = dot_blocks<double>(m);
     hipLaunchKernelGGL((k_dots<double, K, 2>), dim3(nb), dim3(kBlock), 0, st, a0, b0, a1, b1, m,
                        h->red);
     hipLaunchKernelGGL((k_dots_final<K, 2>), dim3(2 * K), dim3(kBlock), 0, st, (const double*)h->red, nb,
@@ -904,7 +942,7 @@ void alloc_solve_workspace(lg_hierarchy* h, hipStream_t st) {
   h->pt = h->mem.get<double>(m);
   if (h->opts.precision == LG_MIXED) h->cyc_in = h->mem.alloc((size_t)m * s);
   h->scal = h->mem.get<double>(S_COUNT * K);
-  h->red = h->mem.get<double>((int64_t)kRedBlocks * 2 * K);
+  h->red = h->mem.get<double>((int64_t)kDotPartials * 2 * K);
   LG_HIP(hipHostMalloc((void**)&h->host_scal, sizeof(double) * S_COUNT * K, hipHostMallocDefault));
   (void)st;
 }
