@@ -317,15 +317,16 @@ __global__ __launch_bounds__(64) void k_split_fix(Op op, const int32_t* __restri
   op.finish(row, acc, 0, 1);
 }
 
-// Ordinary rows run on a bounded grid of workgroups that loop over the
-// logical row blocks (kRowGrid covers the chip several times over): short
-// rows make short-lived waves, and re-dispatching them costs more than the
-// work they do.  Workgroups are dealt to the 8 XCDs round-robin by index and
-// each XCD has its own L2, so the row region starts at a multiple of 8 and
-// XCD x takes the x-th contiguous eighth of every degree class: neighbouring
-// rows (which share cache lines and, on meshes, neighbours) stay in one L2,
-// while each XCD still gets an equal share of every class.
-constexpr int64_t kRowGrid = 2048;
+// Ordinary rows run on a persistent grid of workgroups (as many as the chip
+// holds at once, see resident_grid) that loop over the logical row blocks:
+// short rows make short-lived waves, and re-dispatching them costs more than
+// the work they do.  Workgroups are dealt to the 8 XCDs round-robin by index
+// and each XCD has its own L2.  The column-split kernels therefore start the
+// row region at a multiple of 8 and let XCD x take the x-th contiguous eighth
+// of every degree class: neighbouring rows (which share cache lines and, on
+// meshes, neighbours) stay in one L2, while each XCD still gets an equal
+// share of every class.  The one-column kernels, whose rows are 8 bytes wide,
+// keep the plain round-robin order, which measured faster for them.
 constexpr int kXcds = 8;
 
 __host__ __device__ inline int64_t round_up8(int64_t v) { return (v + kXcds - 1) / kXcds * kXcds; }
@@ -385,13 +386,31 @@ __global__ __launch_bounds__(kBlock) void k_rows(Op op, const int32_t* __restric
 }
 
 // Run Op over every row of the CSR described by (s, rp) on stream st: one launch.
+// Workgroups of kBlock threads that the whole chip holds at once for this
+// kernel (its occupancy times the compute units): the size of a persistent
+// row grid, so that no workgroup waits for a second round.  Computed once
+// per kernel.
+template <typename KernelT>
+inline int64_t resident_grid(KernelT kernel) {
+  static int64_t cached = 0;
+  if (cached == 0) {
+    int per_cu = 0, dev = 0, cus = 0;
+    LG_HIP(hipGetDevice(&dev));
+    LG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    LG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0));
+    cached = std::max<int64_t>(1, (int64_t)per_cu * cus);
+  }
+  return cached;
+}
+
 template <class Op>
 void run_rows(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st) {
   static_assert(sizeof(typename Op::Acc) <= kPartialBytes, "accumulator larger than a partial slot");
   static_assert(sizeof(typename Op::Acc) % 4 == 0, "accumulator size must be a multiple of 4");
   if (s.n == 0) return;
   const int64_t total = s.ct.blk_start[kClasses];
-  const int64_t blocks = round_up8(s.nchunk + s.nhub) + round_up8(std::min<int64_t>(total, kRowGrid));
+  const int64_t blocks =
+      round_up8(s.nchunk + s.nhub) + round_up8(std::min<int64_t>(total, resident_grid(k_rows<Op>)));
   if (blocks == 0) return;
   hipLaunchKernelGGL((k_rows<Op>), dim3((unsigned)blocks), dim3(kBlock), 0, st, op, rp,
                      (const int32_t*)s.perm, s.ct, s.nhub, (const int32_t*)s.hub_rows, s.nchunk,
@@ -426,21 +445,24 @@ __device__ __forceinline__ void col_rows(const Op& op, const int32_t* __restrict
   const int grp = (threadIdx.x / L) & (M - 1);
   if (pos >= p1) return;
   const int64_t row = perm[pos];
+  typename Op::Pre pre;
+  if (grp == 0) pre = op.prefetch(row, part);
   typename Op::Acc acc = op.identity();
   if (op.active(row)) {
     const int end = rp[row + 1];
-    int e = rp[row] + grp;
-    for (; e + 3 * M < end; e += 4 * M) {
-      op.accum(acc, row, e, part);
-      op.accum(acc, row, e + M, part);
-      op.accum(acc, row, e + 2 * M, part);
-      op.accum(acc, row, e + 3 * M, part);
+    // eight entries per trip, all loads issued together: slots past the row's
+    // end re-read its last entry with weight zero
+    for (int e = rp[row] + grp; e < end; e += 8 * M) {
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        const int eu = e + u * M;
+        op.accum(acc, row, eu < end ? eu : end - 1, part, eu < end);
+      }
     }
-    for (; e < end; e += M) op.accum(acc, row, e, part);
 #pragma unroll
     for (int m = T / 2; m >= L; m >>= 1) op.combine(acc, shfl_xor_any(acc, m));
   }
-  if (grp == 0) op.finish(row, acc, part);
+  if (grp == 0) op.finish(row, acc, part, pre);
 }
 
 // Entries [beg, end) of `row` by all kBlock / kL groups of the workgroup; the
@@ -560,7 +582,8 @@ void run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_t s
     blk += c == kClasses - 1 ? rows : ceil_div(rows * L * M, kBlock);
   }
   ct.blk_start[kClasses] = (int32_t)blk;
-  const int64_t blocks = round_up8(s.nchunk + s.nhub) + round_up8(std::min<int64_t>(blk, kRowGrid));
+  const int64_t blocks =
+      round_up8(s.nchunk + s.nhub) + round_up8(std::min<int64_t>(blk, resident_grid(k_rows_col<Op>)));
   if (blocks == 0) return;
   hipLaunchKernelGGL((k_rows_col<Op>), dim3((unsigned)blocks), dim3(kBlock), 0, st, op, rp,
                      (const int32_t*)s.perm, ct, s.nhub, (const int32_t*)s.hub_rows, s.nchunk,

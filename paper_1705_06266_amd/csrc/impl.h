@@ -57,7 +57,6 @@ struct Level {
   void* vx = nullptr;
   void* vx2 = nullptr;
   void* vr = nullptr;
-  void* vp = nullptr;
   // K-cycle workspace (levels whose coarse solve is FCG)
   void* kr = nullptr;
   void* kp1 = nullptr;
@@ -96,6 +95,7 @@ constexpr int kDotPartials = 2048;  // most workgroups of a column-dot launch
 // scalar slots (each K wide) of lg_hierarchy::scal
 enum {
   S_BN = 0, S_RZ, S_PQ, S_ALPHA, S_BETA, S_RR, S_PR, S_ZQ, S_ACTIVE, S_MEAN, S_TMP, S_TR,
+  S_ZSUM, S_ZY, S_YSUM, S_RESTART,
   S_COUNT = 32
 };
 

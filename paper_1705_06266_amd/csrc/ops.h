@@ -11,13 +11,18 @@ struct VecAcc {
   T v[K];
 };
 
-enum { LAP_SPMV = 0, LAP_RESID = 1, LAP_CHEB = 2, LAP_CHEB_FIRST = 3 };
+enum { LAP_SPMV = 0, LAP_RESID = 1, LAP_CHEB = 2, LAP_CHEB_FIRST = 3, LAP_CHEB_ZERO = 4 };
 
-// Row i: s = sum_j w_ij x_j (k columns), (L x)_i = d_i x_i - s.
+// Row i: s = sum_j w_ij x_j (k columns), (L x)_i = d_i x_i - s.  The Chebyshev
+// modes use the three-term recurrence on iterates (Section 3.6 smoother):
 //  LAP_SPMV:       y = L x
 //  LAP_RESID:      y = b - L x
-//  LAP_CHEB:       r = dinv (b - L x); p = c1 p + c2 r; xo = x + p
-//  LAP_CHEB_FIRST: same with p = c2 r (p is not read)
+//  LAP_CHEB:       y = x + c1 (x - y) + c2 dinv (b - L x)   (y holds the previous
+//                  iterate on entry and is overwritten in place, row by row)
+//  LAP_CHEB_FIRST: y = x + c2 dinv (b - L x)
+//  LAP_CHEB_ZERO:  the first two steps from a zero guess in one pass: with
+//                  x1 = c0 dinv b (never stored unless p is set, then p = x1),
+//                  y = x1 + c1 x1 + c2 dinv (b - L x1); x must point at b.
 template <typename T, int K, int MODE>
 struct LapOp {
   using Acc = VecAcc<T, K>;
@@ -29,7 +34,7 @@ struct LapOp {
   T* __restrict__ y;
   const T* __restrict__ b;
   T* __restrict__ p;
-  T c1, c2;
+  T c1, c2, c0;
 
   __device__ __forceinline__ Acc identity() const {
     Acc a;
@@ -42,8 +47,14 @@ struct LapOp {
     const int j = col[e];
     const T wv = w[e];
     const T* xj = x + (int64_t)j * K;
+    if (MODE == LAP_CHEB_ZERO) {
+      const T dj = dinv[j];
 #pragma unroll
-    for (int c = 0; c < K; c++) a.v[c] += wv * xj[c];
+      for (int c = 0; c < K; c++) a.v[c] += wv * ((dj * xj[c]) * c0);
+    } else {
+#pragma unroll
+      for (int c = 0; c < K; c++) a.v[c] += wv * xj[c];
+    }
   }
   __device__ __forceinline__ void combine(Acc& a, const Acc& o) const {
 #pragma unroll
@@ -55,7 +66,7 @@ struct LapOp {
     for (int c = 0; c < K; c++) {
       if (c % G != lane) continue;  // lanes share the k columns of the row
       const int64_t idx = row * K + c;
-      const T xi = x[idx];
+      const T xi = MODE == LAP_CHEB_ZERO ? (dinv[row] * x[idx]) * c0 : x[idx];
       const T lx = di * xi - a.v[c];
       if (MODE == LAP_SPMV) {
         y[idx] = lx;
@@ -63,8 +74,11 @@ struct LapOp {
         y[idx] = b[idx] - lx;
       } else {
         const T r = dinv[row] * (b[idx] - lx);
-        const T pn = (MODE == LAP_CHEB_FIRST) ? c2 * r : c1 * p[idx] + c2 * r;
-        p[idx] = pn;
+        T pn;
+        if (MODE == LAP_CHEB_FIRST) pn = c2 * r;
+        else if (MODE == LAP_CHEB) pn = c1 * (xi - y[idx]) + c2 * r;
+        else pn = c1 * xi + c2 * r;
+        if (MODE == LAP_CHEB_ZERO && p) p[idx] = xi;
         y[idx] = xi + pn;
       }
     }
@@ -88,7 +102,7 @@ struct LapColOp {
   T* __restrict__ y;
   const T* __restrict__ b;
   T* __restrict__ p;
-  T c1, c2;
+  T c1, c2, c0;
 
   __device__ __forceinline__ Acc identity() const {
     Acc a;
@@ -97,42 +111,69 @@ struct LapColOp {
     return a;
   }
   __device__ __forceinline__ bool active(int64_t) const { return true; }
-  __device__ __forceinline__ void accum(Acc& a, int64_t, int e, int part) const {
+  // keep = false: a padding slot of an unrolled loop (e is a valid index, weight 0)
+  __device__ __forceinline__ void accum(Acc& a, int64_t, int e, int part, bool keep = true) const {
     const int j = col[e];
-    const T wv = w[e];
+    const T wv = keep ? w[e] : T(0);
     const vec_t xv = *reinterpret_cast<const vec_t*>(x + (int64_t)j * K + part * V);
+    if (MODE == LAP_CHEB_ZERO) {
+      const T dj = dinv[j];
 #pragma unroll
-    for (int v = 0; v < V; v++) a.v[v] += wv * xv[v];
+      for (int v = 0; v < V; v++) a.v[v] += wv * ((dj * xv[v]) * c0);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; v++) a.v[v] += wv * xv[v];
+    }
   }
   __device__ __forceinline__ void combine(Acc& a, const Acc& o) const {
 #pragma unroll
     for (int v = 0; v < V; v++) a.v[v] += o.v[v];
   }
-  __device__ __forceinline__ void finish(int64_t row, const Acc& a, int part) const {
-    const T di = d[row];
+  // Row-local operands of finish, loaded before the row's gather so that
+  // their latency overlaps it.
+  struct Pre {
+    T di, dv;
+    vec_t xv, bv, yv;
+  };
+  __device__ __forceinline__ Pre prefetch(int64_t row, int part) const {
+    Pre q;
     const int64_t base = row * K + part * V;
-    const vec_t xv = *reinterpret_cast<const vec_t*>(x + base);
+    q.di = d[row];
+    q.xv = *reinterpret_cast<const vec_t*>(x + base);
+    if (MODE != LAP_SPMV) q.bv = MODE == LAP_CHEB_ZERO ? q.xv : *reinterpret_cast<const vec_t*>(b + base);
+    if (MODE >= LAP_CHEB) q.dv = dinv[row];
+    if (MODE == LAP_CHEB) q.yv = *reinterpret_cast<const vec_t*>(y + base);
+    return q;
+  }
+  __device__ __forceinline__ void finish(int64_t row, const Acc& a, int part) const {
+    finish(row, a, part, prefetch(row, part));
+  }
+  __device__ __forceinline__ void finish(int64_t row, const Acc& a, int part, const Pre& q) const {
+    const T di = q.di;
+    const int64_t base = row * K + part * V;
+    vec_t xv = q.xv;
+    if (MODE == LAP_CHEB_ZERO) {
+#pragma unroll
+      for (int v = 0; v < V; v++) xv[v] = (q.dv * xv[v]) * c0;
+    }
     vec_t out;
     if (MODE == LAP_SPMV) {
 #pragma unroll
       for (int v = 0; v < V; v++) out[v] = di * xv[v] - a.v[v];
     } else if (MODE == LAP_RESID) {
-      const vec_t bv = *reinterpret_cast<const vec_t*>(b + base);
 #pragma unroll
-      for (int v = 0; v < V; v++) out[v] = bv[v] - (di * xv[v] - a.v[v]);
+      for (int v = 0; v < V; v++) out[v] = q.bv[v] - (di * xv[v] - a.v[v]);
     } else {
-      const vec_t bv = *reinterpret_cast<const vec_t*>(b + base);
-      const T dv = dinv[row];
-      vec_t pv;
-      if (MODE == LAP_CHEB) pv = *reinterpret_cast<const vec_t*>(p + base);
 #pragma unroll
       for (int v = 0; v < V; v++) {
-        const T r = dv * (bv[v] - (di * xv[v] - a.v[v]));
-        const T pn = (MODE == LAP_CHEB_FIRST) ? c2 * r : c1 * pv[v] + c2 * r;
-        pv[v] = pn;
+        const T r = q.dv * (q.bv[v] - (di * xv[v] - a.v[v]));
+        T pn;
+        if (MODE == LAP_CHEB_FIRST) pn = c2 * r;
+        else if (MODE == LAP_CHEB) pn = c1 * (xv[v] - q.yv[v]) + c2 * r;
+        else pn = c1 * xv[v] + c2 * r;
         out[v] = xv[v] + pn;
       }
-      *reinterpret_cast<vec_t*>(p + base) = pv;
+      if (MODE == LAP_CHEB_ZERO && p) *reinterpret_cast<vec_t*>(p + base) = xv;
     }
     *reinterpret_cast<vec_t*>(y + base) = out;
   }

@@ -19,44 +19,120 @@ namespace lg {
 static inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)ceil_div(n, b); }
 
 // ------------------------------------------------------- vector kernels
-template <typename T, int K>
-__global__ void k_cheb_zero(const T* __restrict__ b, const T* __restrict__ dinv,
-                            T* __restrict__ p, T* __restrict__ x, int64_t n, T inv_theta) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n * K) return;
-  const T v = dinv[i / K] * b[i] * inv_theta;
-  p[i] = v;
-  x[i] = v;
+// Elementwise kernels handle V = 16 / sizeof(T) consecutive entries of an
+// n x K multi-vector per thread.  When K is a multiple of V those entries lie
+// in one row and move as one 16-byte vector; otherwise (K < V) each entry
+// finds its own row.
+template <typename T>
+struct Vec16 {
+  static constexpr int V = 16 / (int)sizeof(T);
+  typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
+};
+
+template <typename T>
+__device__ __forceinline__ typename Vec16<T>::type ld16(const T* p) {
+  return *reinterpret_cast<const typename Vec16<T>::type*>(p);
+}
+template <typename T>
+__device__ __forceinline__ void st16(T* p, const typename Vec16<T>::type& v) {
+  *reinterpret_cast<typename Vec16<T>::type*>(p) = v;
 }
 
+template <typename T, int K>
+inline unsigned vec_blocks(int64_t n) {
+  return (unsigned)ceil_div(ceil_div(n * K, (int64_t)Vec16<T>::V), (int64_t)kBlock);
+}
+
+// x = c0 D^-1 b (one Chebyshev step from a zero guess)
+template <typename T, int K>
+__global__ void k_cheb_zero(const T* __restrict__ b, const T* __restrict__ dinv,
+                            T* __restrict__ x, int64_t n, T c0) {
+  constexpr int V = Vec16<T>::V;
+  const int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * V;
+  if (i0 >= n * K) return;
+  if constexpr (K % V == 0) {
+    const T di = dinv[i0 / K];
+    typename Vec16<T>::type v = ld16(b + i0);
+#pragma unroll
+    for (int e = 0; e < V; e++) v[e] = (di * v[e]) * c0;
+    st16(x + i0, v);
+  } else {
+    for (int e = 0; e < V && i0 + e < n * K; e++)
+      x[i0 + e] = (dinv[(i0 + e) / K] * b[i0 + e]) * c0;
+  }
+}
+
+// out = x + P xc with P the aggregation's piecewise-constant prolongation
 template <typename T, int K>
 __global__ void k_agg_prolong(const T* __restrict__ x, const T* __restrict__ xc,
                               const int32_t* __restrict__ agg, T* __restrict__ out, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n * K) return;
-  const int64_t row = i / K;
-  out[i] = x[i] + xc[(int64_t)agg[row] * K + (i - row * K)];
+  constexpr int V = Vec16<T>::V;
+  const int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * V;
+  if (i0 >= n * K) return;
+  if constexpr (K % V == 0) {
+    const int64_t row = i0 / K;
+    const int c = (int)(i0 - row * K);
+    typename Vec16<T>::type v = ld16(x + i0);
+    const typename Vec16<T>::type u = ld16(xc + (int64_t)agg[row] * K + c);
+#pragma unroll
+    for (int e = 0; e < V; e++) v[e] += u[e];
+    st16(out + i0, v);
+  } else {
+    for (int e = 0; e < V && i0 + e < n * K; e++) {
+      const int64_t i = i0 + e, row = i / K;
+      out[i] = x[i] + xc[(int64_t)agg[row] * K + (i - row * K)];
+    }
+  }
 }
 
-// x = P_elim x_c + [D_FF^-1 b_F; 0] (Section 3.4, additive two-level form)
+// x = P_elim x_c + [D_FF^-1 b_F; 0] (Section 3.4, additive two-level form):
+// a kept vertex copies its coarse value, an eliminated one averages its
+// (kept) neighbours' coarse values and adds its own D^-1 b.
 template <typename T, int K>
 __global__ void k_elim_prolong(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                const T* __restrict__ w, const T* __restrict__ dinv,
                                const int32_t* __restrict__ cidx, const T* __restrict__ xc,
                                const T* __restrict__ b, T* __restrict__ x, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n * K) return;
-  const int64_t row = i / K;
-  const int c = (int)(i - row * K);
-  const int ci = cidx[row];
-  if (ci >= 0) {
-    x[i] = xc[(int64_t)ci * K + c];
-    return;
+  constexpr int V = Vec16<T>::V;
+  const int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * V;
+  if (i0 >= n * K) return;
+  if constexpr (K % V == 0) {
+    const int64_t row = i0 / K;
+    const int c = (int)(i0 - row * K);
+    const int ci = cidx[row];
+    if (ci >= 0) {
+      st16(x + i0, ld16(xc + (int64_t)ci * K + c));
+      return;
+    }
+    const T di = dinv[row];
+    typename Vec16<T>::type s;
+#pragma unroll
+    for (int e = 0; e < V; e++) s[e] = T(0);
+    for (int q = rp[row]; q < rp[row + 1]; q++) {
+      const T f = w[q] * di;
+      const typename Vec16<T>::type u = ld16(xc + (int64_t)cidx[col[q]] * K + c);
+#pragma unroll
+      for (int e = 0; e < V; e++) s[e] += f * u[e];
+    }
+    const typename Vec16<T>::type bv = ld16(b + i0);
+#pragma unroll
+    for (int e = 0; e < V; e++) s[e] += bv[e] * di;
+    st16(x + i0, s);
+  } else {
+    for (int e = 0; e < V && i0 + e < n * K; e++) {
+      const int64_t i = i0 + e, row = i / K;
+      const int c = (int)(i - row * K);
+      const int ci = cidx[row];
+      if (ci >= 0) {
+        x[i] = xc[(int64_t)ci * K + c];
+        continue;
+      }
+      const T di = dinv[row];
+      T s = T(0);
+      for (int q = rp[row]; q < rp[row + 1]; q++) s += (w[q] * di) * xc[(int64_t)cidx[col[q]] * K + c];
+      x[i] = s + b[i] * di;
+    }
   }
-  const T di = dinv[row];
-  T s = T(0);
-  for (int e = rp[row]; e < rp[row + 1]; e++) s += (w[e] * di) * xc[(int64_t)cidx[col[e]] * K + c];
-  x[i] = s + b[i] * di;
 }
 
 // b_c[I] = sum of r over the members of aggregate I (R r, Section 3.5)
@@ -140,16 +216,18 @@ struct GatherSumColOp {
     return a;
   }
   __device__ bool active(int64_t) const { return true; }
-  __device__ void accum(Acc& a, int64_t, int e, int part) const {
+  __device__ void accum(Acc& a, int64_t, int e, int part, bool keep = true) const {
     const vec_t s = *reinterpret_cast<const vec_t*>(src + (int64_t)idx[e] * K + part * V);
 #pragma unroll
-    for (int v = 0; v < V; v++) a.v[v] += s[v];
+    for (int v = 0; v < V; v++) a.v[v] += keep ? s[v] : T(0);
   }
   __device__ void combine(Acc& a, const Acc& o) const {
 #pragma unroll
     for (int v = 0; v < V; v++) a.v[v] += o.v[v];
   }
-  __device__ void finish(int64_t row, const Acc& a, int part) const {
+  struct Pre {};
+  __device__ Pre prefetch(int64_t, int) const { return Pre{}; }
+  __device__ void finish(int64_t row, const Acc& a, int part, const Pre& = Pre{}) const {
     vec_t o;
 #pragma unroll
     for (int v = 0; v < V; v++) o[v] = a.v[v];
@@ -175,8 +253,8 @@ struct PtColOp {
     return a;
   }
   __device__ bool active(int64_t) const { return true; }
-  __device__ void accum(Acc& a, int64_t, int e, int part) const {
-    const T cf = ptc[e];
+  __device__ void accum(Acc& a, int64_t, int e, int part, bool keep = true) const {
+    const T cf = keep ? ptc[e] : T(0);
     const vec_t s = *reinterpret_cast<const vec_t*>(b + (int64_t)ptf[e] * K + part * V);
 #pragma unroll
     for (int v = 0; v < V; v++) a.v[v] += cf * s[v];
@@ -185,8 +263,17 @@ struct PtColOp {
 #pragma unroll
     for (int v = 0; v < V; v++) a.v[v] += o.v[v];
   }
+  struct Pre {
+    vec_t bv;
+  };
+  __device__ Pre prefetch(int64_t row, int part) const {
+    return Pre{*reinterpret_cast<const vec_t*>(b + (int64_t)cvert[row] * K + part * V)};
+  }
   __device__ void finish(int64_t row, const Acc& a, int part) const {
-    const vec_t bv = *reinterpret_cast<const vec_t*>(b + (int64_t)cvert[row] * K + part * V);
+    finish(row, a, part, prefetch(row, part));
+  }
+  __device__ void finish(int64_t row, const Acc& a, int part, const Pre& q) const {
+    const vec_t bv = q.bv;
     vec_t o;
 #pragma unroll
     for (int v = 0; v < V; v++) o[v] = bv[v] + a.v[v];
@@ -249,53 +336,25 @@ __global__ void k_pad_out(const double* __restrict__ in, int K, double* __restri
   X[i] = in[row * K + c];
 }
 
-// Two-stage deterministic column dot products: ND products (a_d . b_d) per
-// column, or column sums where b_d is null.  Each thread reads 16-byte
-// vectors; the grid is sized to the data (up to kDotBlocks workgroups) and its
-// mapping, hence the summation order, is fixed.
+// Deterministic column reductions.  A pass over an n x K multi-vector runs a
+// grid sized to the data (at most kDotBlocks workgroups, fixed for a given
+// size) with V consecutive entries per thread per step; since the grid's
+// stride is a multiple of K, slot v of thread t always holds column
+// (t V + v) mod K.  Each workgroup folds its slots per column through LDS in
+// a fixed order into partial[(block * ND + d) * K + c]; k_dots_final then
+// reduces the partials of each (product, column) with a fixed tree.
 constexpr int kDotBlocks = kDotPartials;
 
-template <typename T, int K, int ND>
-__global__ __launch_bounds__(kBlock) void k_dots(const T* __restrict__ a0, const T* __restrict__ b0,
-                                                 const T* __restrict__ a1, const T* __restrict__ b1,
-                                                 int64_t m, double* __restrict__ partial) {
-  constexpr int V = 16 / (int)sizeof(T);
-  typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
-  double s0[V], s1[V];
-#pragma unroll
-  for (int v = 0; v < V; v++) s0[v] = s1[v] = 0.0;
-  const int64_t nvec = m / V;  // m = n * K is a multiple of V whenever K >= V; else tail below
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nvec; q += stride) {
-    const vec_t x0 = reinterpret_cast<const vec_t*>(a0)[q];
-    vec_t y0;
-    if (b0) y0 = reinterpret_cast<const vec_t*>(b0)[q];
-#pragma unroll
-    for (int v = 0; v < V; v++) s0[v] += b0 ? (double)x0[v] * (double)y0[v] : (double)x0[v];
-    if (ND > 1) {
-      const vec_t x1 = reinterpret_cast<const vec_t*>(a1)[q];
-      const vec_t y1 = reinterpret_cast<const vec_t*>(b1)[q];
-#pragma unroll
-      for (int v = 0; v < V; v++) s1[v] += (double)x1[v] * (double)y1[v];
-    }
-  }
-  // scalar tail (only when m is not a multiple of V, i.e. K < V and n odd)
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    for (int64_t i = nvec * V; i < m; i++) {
-      const int v = (int)(i % V);
-      s0[v] += b0 ? (double)a0[i] * (double)b0[i] : (double)a0[i];
-      if (ND > 1) s1[v] += (double)a1[i] * (double)b1[i];
-    }
-  }
-  // element t*V+v of any block belongs to column (t*V+v) % K
+template <int K, int V, int ND>
+__device__ __forceinline__ void col_partials(const double (&s)[ND][V], double* __restrict__ partial) {
   __shared__ double sm[ND][kBlock * V];
 #pragma unroll
-  for (int v = 0; v < V; v++) {
-    sm[0][threadIdx.x * V + v] = s0[v];
-    if (ND > 1) sm[ND - 1][threadIdx.x * V + v] = s1[v];
-  }
+  for (int d = 0; d < ND; d++)
+#pragma unroll
+    for (int v = 0; v < V; v++) sm[d][threadIdx.x * V + v] = s[d][v];
   __syncthreads();
   if ((int)threadIdx.x < K) {
+#pragma unroll
     for (int d = 0; d < ND; d++) {
       double t = 0.0;
       for (int q = threadIdx.x; q < kBlock * V; q += K) t += sm[d][q];
@@ -304,11 +363,48 @@ __global__ __launch_bounds__(kBlock) void k_dots(const T* __restrict__ a0, const
   }
 }
 
+// ND products a_d . b_d per column, or column sums of a_d where b_d is null.
+template <typename T, int K, int ND>
+__global__ __launch_bounds__(kBlock) void k_dots(const T* __restrict__ a0, const T* __restrict__ b0,
+                                                 const T* __restrict__ a1, const T* __restrict__ b1,
+                                                 int64_t m, double* __restrict__ partial) {
+  constexpr int V = Vec16<T>::V;
+  double s[ND][V];
+#pragma unroll
+  for (int d = 0; d < ND; d++)
+#pragma unroll
+    for (int v = 0; v < V; v++) s[d][v] = 0.0;
+  const int64_t nvec = m / V;  // whole vectors; the rest (only when K < V) below
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nvec; q += stride) {
+    const typename Vec16<T>::type x0 = ld16(a0 + q * V);
+    typename Vec16<T>::type y0;
+    if (b0) y0 = ld16(b0 + q * V);
+#pragma unroll
+    for (int v = 0; v < V; v++) s[0][v] += b0 ? (double)x0[v] * (double)y0[v] : (double)x0[v];
+    if (ND > 1) {
+      const typename Vec16<T>::type x1 = ld16(a1 + q * V);
+      const typename Vec16<T>::type y1 = ld16(b1 + q * V);
+#pragma unroll
+      for (int v = 0; v < V; v++) s[ND - 1][v] += (double)x1[v] * (double)y1[v];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int64_t i = nvec * V; i < m; i++) {
+      const int v = (int)(i % V);
+      s[0][v] += b0 ? (double)a0[i] * (double)b0[i] : (double)a0[i];
+      if (ND > 1) s[ND - 1][v] += (double)a1[i] * (double)b1[i];
+    }
+  }
+  col_partials<K, V, ND>(s, partial);
+}
+
 // One workgroup per (product, column): a fixed tree over the block partials.
 template <int K, int ND>
 __global__ __launch_bounds__(kBlock) void k_dots_final(const double* __restrict__ partial, int nb,
                                                        double* __restrict__ out0,
-                                                       double* __restrict__ out1) {
+                                                       double* __restrict__ out1,
+                                                       double* __restrict__ out2) {
   const int t = blockIdx.x;
   const int d = t / K, c = t % K;
   __shared__ double sm[kBlock];
@@ -320,7 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_dots_final(const double* __restrict_
     if ((int)threadIdx.x < m) sm[threadIdx.x] += sm[threadIdx.x + m];
     __syncthreads();
   }
-  if (threadIdx.x == 0) (d == 0 ? out0 : out1)[c] = sm[0];
+  if (threadIdx.x == 0) (d == 0 ? out0 : d == 1 ? out1 : out2)[c] = sm[0];
 }
 
 template <int K>
@@ -349,52 +445,160 @@ __global__ void k_alpha(double* __restrict__ scal, int flexible) {
   scal[S_ALPHA * K + c] = a;
 }
 
+// x += alpha p, r -= alpha q per column, with the column sums of r . r of the
+// new r, and rc = r in the cycle's precision when rc is set (one pass).
+template <int K, typename TC>
+__global__ __launch_bounds__(kBlock) void k_update_xr(double* __restrict__ x, double* __restrict__ r,
+                                                      const double* __restrict__ p,
+                                                      const double* __restrict__ q,
+                                                      const double* __restrict__ scal, int64_t m,
+                                                      TC* __restrict__ rc,
+                                                      double* __restrict__ partial) {
+  constexpr int V = 2;
+  double s[1][V] = {{0.0, 0.0}};
+  double a[V];
+#pragma unroll
+  for (int v = 0; v < V; v++) a[v] = scal[S_ALPHA * K + ((int)threadIdx.x * V + v) % K];
+  typedef TC tc2 __attribute__((ext_vector_type(2)));
+  const int64_t nvec = m / V;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  // two vectors per trip (t and t + stride) so that eight loads are in flight
+  for (int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x; t0 < nvec; t0 += 2 * stride) {
+    typename Vec16<double>::type xv[2], rv[2], pv[2], qv[2];
+    const bool two = t0 + stride < nvec;
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      const int64_t t = h && two ? t0 + stride : t0;
+      xv[h] = ld16(x + t * V);
+      rv[h] = ld16(r + t * V);
+      pv[h] = ld16(p + t * V);
+      qv[h] = ld16(q + t * V);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      if (h && !two) break;
+      const int64_t t = t0 + h * stride;
+#pragma unroll
+      for (int v = 0; v < V; v++) {
+        xv[h][v] += a[v] * pv[h][v];
+        rv[h][v] -= a[v] * qv[h][v];
+        s[0][v] += rv[h][v] * rv[h][v];
+      }
+      st16(x + t * V, xv[h]);
+      st16(r + t * V, rv[h]);
+      if (rc) {
+        tc2 o;
+        o[0] = (TC)rv[h][0];
+        o[1] = (TC)rv[h][1];
+        *reinterpret_cast<tc2*>(rc + t * V) = o;
+      }
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {  // odd m (K = 1): last entry, column 0
+    for (int64_t i = nvec * V; i < m; i++) {
+      const double al = scal[S_ALPHA * K + (int)(i % K)];
+      x[i] += al * p[i];
+      r[i] -= al * q[i];
+      s[0][i % V] += r[i] * r[i];
+      if (rc) rc[i] = (TC)r[i];
+    }
+  }
+  col_partials<K, V, 1>(s, partial);
+}
+
+// Column sums of z (the cycle's output, precision T), of z . y and of y, with
+// y the fp64 residual (CG) or q = L p (flexible CG): enough to project z to
+// mean zero and form the projected z . y without storing the projection.
+template <typename T, int K>
+__global__ __launch_bounds__(kBlock) void k_zstats(const T* __restrict__ z,
+                                                   const double* __restrict__ y, int64_t m,
+                                                   double* __restrict__ partial) {
+  constexpr int V = Vec16<T>::V;
+  double s[3][V];
+#pragma unroll
+  for (int d = 0; d < 3; d++)
+#pragma unroll
+    for (int v = 0; v < V; v++) s[d][v] = 0.0;
+  const int64_t nvec = m / V;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < nvec; t += stride) {
+    const typename Vec16<T>::type zv = ld16(z + t * V);
+#pragma unroll
+    for (int u = 0; u < V; u += 2) {
+      const typename Vec16<double>::type yv = ld16(y + t * V + u);
+#pragma unroll
+      for (int e = 0; e < 2; e++) {
+        const double zd = (double)zv[u + e];
+        s[0][u + e] += zd;
+        s[1][u + e] += zd * yv[e];
+        s[2][u + e] += yv[e];
+      }
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int64_t i = nvec * V; i < m; i++) {
+      const int v = (int)(i % V);
+      const double zd = (double)z[i];
+      s[0][v] += zd;
+      s[1][v] += zd * y[i];
+      s[2][v] += y[i];
+    }
+  }
+  col_partials<K, V, 3>(s, partial);
+}
+
+// From the sums of k_zstats: the mean of z, the projected product
+// (z - mean) . y = z . y - mean * sum(y), and beta.  CG: beta = rz_new / rz_old
+// (rz_old replaced); flexible CG: beta = -(z . q) / (p . q).  first: the
+// initial direction (beta = 0, CG records rz).
 template <int K>
-__global__ void k_beta(double* __restrict__ scal, int flexible) {
+__global__ void k_beta_z(double* __restrict__ scal, double inv_n, int flexible, int first) {
   const int c = threadIdx.x;
   if (c >= K) return;
+  const double mean = scal[S_ZSUM * K + c] * inv_n;
+  const double zy = scal[S_ZY * K + c] - mean * scal[S_YSUM * K + c];
+  scal[S_MEAN * K + c] = mean;
   const double act = scal[S_ACTIVE * K + c];
   double b = 0.0;
-  if (act > 0.0) {
-    if (flexible) {
-      const double pq = scal[S_PQ * K + c];
-      b = pq > 0.0 ? -scal[S_ZQ * K + c] / pq : 0.0;
-    } else {
-      const double rz = scal[S_RZ * K + c];
-      const double rz2 = scal[S_TMP * K + c];
-      b = rz != 0.0 ? rz2 / rz : 0.0;
-      scal[S_RZ * K + c] = rz2;
-    }
+  if (flexible) {
+    const double pq = scal[S_PQ * K + c];
+    if (!first && act > 0.0 && pq > 0.0) b = -zy / pq;
+  } else if (first) {
+    scal[S_RZ * K + c] = zy;
+  } else if (act > 0.0) {
+    const double rz = scal[S_RZ * K + c];
+    b = rz != 0.0 ? zy / rz : 0.0;
+    scal[S_RZ * K + c] = zy;
   }
   scal[S_BETA * K + c] = b;
 }
 
-template <int K>
-__global__ void k_update_xr(double* __restrict__ x, double* __restrict__ r,
-                            const double* __restrict__ p, const double* __restrict__ q,
-                            const double* __restrict__ scal, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n * K) return;
-  const double a = scal[S_ALPHA * K + (i % K)];
-  x[i] += a * p[i];
-  r[i] -= a * q[i];
-}
-
-template <int K>
-__global__ void k_xpby(double* __restrict__ p, const double* __restrict__ z,
-                       const double* __restrict__ scal, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n * K) return;
-  p[i] = z[i] + scal[S_BETA * K + (i % K)] * p[i];
-}
-
-// p = z only in restarted columns (flag[c] = 1)
-template <int K>
-__global__ void k_restart_p(double* __restrict__ p, const double* __restrict__ z,
-                            const double* __restrict__ flag, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n * K) return;
-  if (flag[i % K] > 0.0) p[i] = z[i];
+// p = (z - mean) + beta p, or p = z - mean where every column restarts
+// (all = 1) or the column's restart flag is set.
+template <typename T, int K>
+__global__ void k_xpby_z(double* __restrict__ p, const T* __restrict__ z,
+                         const double* __restrict__ scal, const double* __restrict__ flag,
+                         int all, int64_t m) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i0 = t * 2;
+  if (i0 >= m) return;
+  if (i0 + 1 < m) {
+    typename Vec16<double>::type pv;
+    if (!all) pv = ld16(p + i0);
+#pragma unroll
+    for (int e = 0; e < 2; e++) {
+      const int c = (int)((i0 + e) % K);
+      const double zp = (double)z[i0 + e] - scal[S_MEAN * K + c];
+      const bool fresh = all || (flag && flag[c] > 0.0);
+      pv[e] = fresh ? zp : zp + scal[S_BETA * K + c] * pv[e];
+    }
+    st16(p + i0, pv);
+  } else {
+    const int c = (int)(i0 % K);
+    const double zp = (double)z[i0] - scal[S_MEAN * K + c];
+    const bool fresh = all || (flag && flag[c] > 0.0);
+    p[i0] = fresh ? zp : zp + scal[S_BETA * K + c] * p[i0];
+  }
 }
 
 // ---- inner FCG(2) scalars of the K-cycle: [d1 a1 alpha1 zq d2 a2] x K
@@ -471,16 +675,18 @@ struct Engine {
   lg_hierarchy* h;
   hipStream_t st;
 
+  // vecs: n x K vectors streamed (reads and writes); the smoother modes also read D^-1
   template <int MODE>
-  void lap(const Level& L, const T* x, T* y, const T* b, T* p, T c1, T c2, const char* fam,
+  void lap(const Level& L, const T* x, T* y, const T* b, T* p, T c1, T c2, T c0, const char* fam,
            int vecs) {
     Vals<T> v = vals_of<T>(L);
-    ProfScope ps(fam, st, spmm_bytes(L, K, (int)sizeof(T), vecs) + (MODE >= LAP_CHEB ? 8.0 * L.n : 0));
+    ProfScope ps(fam, st,
+                 spmm_bytes(L, K, (int)sizeof(T), vecs) + (MODE >= LAP_CHEB ? (double)sizeof(T) * L.n : 0));
     if constexpr (use_col_split<T, K>()) {
-      run_rows_col(L.sched, L.rp, LapColOp<T, K, MODE>{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2},
-                   st);
+      run_rows_col(L.sched, L.rp,
+                   LapColOp<T, K, MODE>{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2, c0}, st);
     } else {
-      run_rows(L.sched, L.rp, LapOp<T, K, MODE>{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2}, st);
+      run_rows(L.sched, L.rp, LapOp<T, K, MODE>{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2, c0}, st);
     }
   }
 
@@ -491,7 +697,7 @@ struct Engine {
     const int nb = dot_blocks<T>(m);
     hipLaunchKernelGGL((k_dots<T, K, ND>), dim3(nb), dim3(kBlock), 0, st, a0, b0, a1, b1, m, h->red);
     hipLaunchKernelGGL((k_dots_final<K, ND>), dim3(ND * K), dim3(kBlock), 0, st, (const double*)h->red, nb,
-                       out0, out1);
+                       out0, out1, (double*)nullptr);
   }
 
   // Algorithm 1 from level l with zero initial guess; returns the buffer holding x.
@@ -518,14 +724,13 @@ struct Engine {
       }
       const T* xc = level(l + 1, bc);  // elimination interpolates exactly: no Krylov step here
       ProfScope ps("prolong", st, 0.0);
-      hipLaunchKernelGGL((k_elim_prolong<T, K>), dim3(nblk(n * K)), dim3(kBlock), 0, st, L.rp, L.col,
+      hipLaunchKernelGGL((k_elim_prolong<T, K>), dim3(vec_blocks<T, K>(n)), dim3(kBlock), 0, st, L.rp, L.col,
                          v.w, v.dinv, L.cidx, xc, b, x, n);
       return x;
     }
     // aggregation level
     T* x2 = (T*)L.vx2;
     T* r = (T*)L.vr;
-    T* p = (T*)L.vp;
     const lg_setup_opts& o = h->opts;
     const int deg = o.cheb_degree;
     const double lo = o.cheb_lo * L.lmax, hi = o.cheb_hi * L.lmax;
@@ -534,20 +739,27 @@ struct Engine {
     const bool smooth = deg >= 1 && L.lmax > 0.0;
     T* cur = x;
     T* nxt = x2;
-    if (smooth) {
-      hipLaunchKernelGGL((k_cheb_zero<T, K>), dim3(nblk(n * K)), dim3(kBlock), 0, st, b, v.dinv, p,
-                         cur, n, (T)(1.0 / theta));
+    if (smooth && deg == 1) {
+      hipLaunchKernelGGL((k_cheb_zero<T, K>), dim3(vec_blocks<T, K>(n)), dim3(kBlock), 0, st, b,
+                         v.dinv, cur, n, (T)(1.0 / theta));
+    } else if (smooth) {
+      // steps 0 and 1 in one pass; step 0's iterate is stored only if more follow
       double rho = 1.0 / sigma;
-      for (int s = 1; s < deg; s++) {
-        const double rho1 = 1.0 / (2.0 * sigma - rho);
-        lap<LAP_CHEB>(L, cur, nxt, b, p, (T)(rho1 * rho), (T)(2.0 * rho1 / delta), "cheb", 5);
+      double rho1 = 1.0 / (2.0 * sigma - rho);
+      lap<LAP_CHEB_ZERO>(L, b, cur, b, deg > 2 ? nxt : nullptr, (T)(rho1 * rho),
+                         (T)(2.0 * rho1 / delta), (T)(1.0 / theta), "cheb", deg > 2 ? 3 : 2);
+      rho = rho1;
+      for (int s = 2; s < deg; s++) {
+        rho1 = 1.0 / (2.0 * sigma - rho);
+        lap<LAP_CHEB>(L, cur, nxt, b, nullptr, (T)(rho1 * rho), (T)(2.0 * rho1 / delta), T(0),
+                      "cheb", 4);
         std::swap(cur, nxt);
         rho = rho1;
       }
     } else {
       hipLaunchKernelGGL((k_fill<T>), dim3(nblk(n * K)), dim3(kBlock), 0, st, cur, n * K, T(0));
     }
-    lap<LAP_RESID>(L, cur, r, b, nullptr, T(0), T(0), "resid", 3);
+    lap<LAP_RESID>(L, cur, r, b, nullptr, T(0), T(0), T(0), "resid", 3);
     T* bc = (T*)C.vb;
     {
       ProfScope ps("restrict", st, 4.0 * (L.nc + 1) + 4.0 * n + 2.0 * K * n * sizeof(T));
@@ -560,17 +772,19 @@ struct Engine {
                                                                           : level(l + 1, bc);
     {
       ProfScope ps("prolong", st, 4.0 * n + 3.0 * K * n * sizeof(T));
-      hipLaunchKernelGGL((k_agg_prolong<T, K>), dim3(nblk(n * K)), dim3(kBlock), 0, st, cur, xc,
-                         L.agg, nxt, n);
+      hipLaunchKernelGGL((k_agg_prolong<T, K>), dim3(vec_blocks<T, K>(n)), dim3(kBlock), 0, st, cur,
+                         xc, L.agg, nxt, n);
       std::swap(cur, nxt);
     }
     if (smooth) {
-      lap<LAP_CHEB_FIRST>(L, cur, nxt, b, p, T(0), (T)(1.0 / theta), "cheb", 4);
+      // nxt keeps the previous iterate, which each further step overwrites
+      lap<LAP_CHEB_FIRST>(L, cur, nxt, b, nullptr, T(0), (T)(1.0 / theta), T(0), "cheb", 3);
       std::swap(cur, nxt);
       double rho = 1.0 / sigma;
       for (int s = 1; s < deg; s++) {
         const double rho1 = 1.0 / (2.0 * sigma - rho);
-        lap<LAP_CHEB>(L, cur, nxt, b, p, (T)(rho1 * rho), (T)(2.0 * rho1 / delta), "cheb", 5);
+        lap<LAP_CHEB>(L, cur, nxt, b, nullptr, (T)(rho1 * rho), (T)(2.0 * rho1 / delta), T(0),
+                      "cheb", 4);
         std::swap(cur, nxt);
         rho = rho1;
       }
@@ -593,7 +807,7 @@ struct Engine {
     LG_HIP(hipMemcpyAsync(r, b, sizeof(T) * n * K, hipMemcpyDeviceToDevice, st));
     const T* z = level(l, r);
     LG_HIP(hipMemcpyAsync(p1, z, sizeof(T) * n * K, hipMemcpyDeviceToDevice, st));
-    lap<LAP_SPMV>(C, p1, q1, nullptr, nullptr, T(0), T(0), "spmm_inner", 2);
+    lap<LAP_SPMV>(C, p1, q1, nullptr, nullptr, T(0), T(0), T(0), "spmm_inner", 2);
     dots<2>(p1, q1, p1, r, n, ks + 0 * K, ks + 1 * K);
     hipLaunchKernelGGL((k_fcg_alpha1<K>), dim3(1), dim3(64), 0, st, ks);
     hipLaunchKernelGGL((k_fcg_step1<T, K>), dim3(g), dim3(kBlock), 0, st, x, r, p1, q1,
@@ -601,7 +815,7 @@ struct Engine {
     T* z2 = level(l, r);
     dots<1>(z2, q1, nullptr, nullptr, n, ks + 3 * K, nullptr);
     hipLaunchKernelGGL((k_fcg_p2<T, K>), dim3(g), dim3(kBlock), 0, st, z2, p1, (const double*)ks, n);
-    lap<LAP_SPMV>(C, z2, q2, nullptr, nullptr, T(0), T(0), "spmm_inner", 2);
+    lap<LAP_SPMV>(C, z2, q2, nullptr, nullptr, T(0), T(0), T(0), "spmm_inner", 2);
     dots<2>(z2, q2, z2, r, n, ks + 4 * K, ks + 5 * K);
     hipLaunchKernelGGL((k_fcg_final<T, K>), dim3(g), dim3(kBlock), 0, st, x, z2, (const double*)ks,
                        n);
@@ -609,21 +823,22 @@ struct Engine {
     return x;
   }
 
-  // z = M r (fp64 in and out) with M one cycle in precision T.
-  void precond(const double* r, double* z) {
-    const Level& L0 = h->lev[0];
-    const int64_t m = L0.n * K;
+  // One cycle on the fp64 residual r: returns M r in precision T (the
+  // finest level's output buffer).  In the mixed form the cycle reads its
+  // fp32 copy of r from h->cyc_in, refreshed here unless r_ready says the
+  // caller has written it already.
+  const T* precond(const double* r, bool r_ready) {
+    const int64_t m = h->lev[0].n * K;
     const T* in;
     if (sizeof(T) == sizeof(double)) {
       in = (const T*)r;
     } else {
-      hipLaunchKernelGGL((k_convert<double, T>), dim3(nblk(m)), dim3(kBlock), 0, st, r,
-                         (T*)h->cyc_in, m);
+      if (!r_ready)
+        hipLaunchKernelGGL((k_convert<double, T>), dim3(nblk(m)), dim3(kBlock), 0, st, r,
+                           (T*)h->cyc_in, m);
       in = (const T*)h->cyc_in;
     }
-    const T* res = level(0, in);
-    hipLaunchKernelGGL((k_convert<T, double>), dim3(nblk(m)), dim3(kBlock), 0, st, res, z, m);
-    LG_LAUNCH_CHECK();
+    return level(0, in);
   }
 };
 
@@ -681,7 +896,9 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
   const int64_t n = L0.n;
   const int64_t m = n * K;
   const unsigned g = nblk(m);
+  const unsigned g2 = nblk(ceil_div(m, (int64_t)2));
   const bool flex = h->opts.cycle == LG_CYCLE_K;
+  const bool mixed = sizeof(T) != sizeof(double);
   double* sc = h->scal;
   double* hs = h->host_scal;
   auto sl = [&](int slot) { return sc + slot * K; };
@@ -694,29 +911,41 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     LG_HIP(hipMemcpyAsync(sc + slot * K, hs + slot * K, sizeof(double) * K, hipMemcpyHostToDevice,
                           st));
   };
+  const int nb = dot_blocks<double>(m);
+  auto final1 = [&](int slot) {
+    hipLaunchKernelGGL((k_dots_final<K, 1>), dim3(K), dim3(kBlock), 0, st, (const double*)h->red, nb,
+                       sl(slot), (double*)nullptr, (double*)nullptr);
+  };
   auto project64 = [&](double* v) {
-    const int nb = dot_blocks<double>(m);
     hipLaunchKernelGGL((k_dots<double, K, 1>), dim3(nb), dim3(kBlock), 0, st, v,
                        (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, m,
                        h->red);
-    hipLaunchKernelGGL((k_dots_final<K, 1>), dim3(K), dim3(kBlock), 0, st, (const double*)h->red, nb,
-                       sl(S_MEAN), (double*)nullptr);
-    hipLaunchKernelGGL((k_sub_mean<K>), dim3(g), dim3(kBlock), 0, st, v, (const double*)sl(S_MEAN), n);
+    final1(S_TMP);
+    hipLaunchKernelGGL((k_sub_mean<K>), dim3(g), dim3(kBlock), 0, st, v, (const double*)sl(S_TMP), n);
   };
   auto dot64 = [&](const double* a, const double* b, int slot) {
-    const int nb = dot_blocks<double>(m);
     hipLaunchKernelGGL((k_dots<double, K, 1>), dim3(nb), dim3(kBlock), 0, st, a, b,
                        (const double*)nullptr, (const double*)nullptr, m, h->red);
-    hipLaunchKernelGGL((k_dots_final<K, 1>), dim3(K), dim3(kBlock), 0, st, (const double*)h->red, nb,
-                       sl(slot), (double*)nullptr);
+    final1(slot);
   };
   auto dot64x2 = [&](const double* a0, const double* b0, const double* a1, const double* b1,
                      int s0, int s1) {
-    const int nb = dot_blocks<double>(m);
     hipLaunchKernelGGL((k_dots<double, K, 2>), dim3(nb), dim3(kBlock), 0, st, a0, b0, a1, b1, m,
                        h->red);
-    hipLaunchKernelGGL((k_dots_final<K, 2>), dim3(2 * K), dim3(kBlock), 0, st, (const double*)h->red, nb,
-                       sl(s0), sl(s1));
+    hipLaunchKernelGGL((k_dots_final<K, 2>), dim3(2 * K), dim3(kBlock), 0, st, (const double*)h->red,
+                       nb, sl(s0), sl(s1), (double*)nullptr);
+  };
+  // z = M r, projected to mean zero, enters p = z + beta p without being stored
+  const int nbz = dot_blocks<T>(m);
+  auto new_direction = [&](const T* z, bool first, const double* flags) {
+    hipLaunchKernelGGL((k_zstats<T, K>), dim3(nbz), dim3(kBlock), 0, st, z,
+                       (const double*)(flex && !first ? h->pq : h->pr), m, h->red);
+    hipLaunchKernelGGL((k_dots_final<K, 3>), dim3(3 * K), dim3(kBlock), 0, st, (const double*)h->red,
+                       nbz, sl(S_ZSUM), sl(S_ZY), sl(S_YSUM));
+    hipLaunchKernelGGL((k_beta_z<K>), dim3(1), dim3(64), 0, st, sc, 1.0 / (double)n, flex ? 1 : 0,
+                       first ? 1 : 0);
+    hipLaunchKernelGGL((k_xpby_z<T, K>), dim3(g2), dim3(kBlock), 0, st, h->pp, z, (const double*)sc,
+                       flags, first ? 1 : 0, m);
   };
 
   const double cw = cycle_work(h, 0);
@@ -744,20 +973,18 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     return false;
   };
   if (any_active()) {
-    eng.precond(h->pr, h->pz);
-    project64(h->pz);
+    new_direction(eng.precond(h->pr, false), true, nullptr);
     for (int c = 0; c < K; c++) work[c] += active[c] > 0.0 ? cw : 0.0;
-    LG_HIP(hipMemcpyAsync(h->pp, h->pz, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
-    dot64(h->pr, h->pz, S_RZ);
   }
   for (int it = 1; it <= max_iter && any_active(); it++) {
     lap64<K>(h, 0, h->pp, h->pq, nullptr, st, "spmm");
     if (flex) dot64x2(h->pp, h->pq, h->pp, h->pr, S_PQ, S_PR);
     else dot64(h->pp, h->pq, S_PQ);
     hipLaunchKernelGGL((k_alpha<K>), dim3(1), dim3(64), 0, st, sc, flex ? 1 : 0);
-    hipLaunchKernelGGL((k_update_xr<K>), dim3(g), dim3(kBlock), 0, st, h->px, h->pr,
-                       (const double*)h->pp, (const double*)h->pq, (const double*)sc, n);
-    dot64(h->pr, h->pr, S_RR);
+    hipLaunchKernelGGL((k_update_xr<K, T>), dim3(nb), dim3(kBlock), 0, st, h->px, h->pr,
+                       (const double*)h->pp, (const double*)h->pq, (const double*)sc, m,
+                       mixed ? (T*)h->cyc_in : (T*)nullptr, h->red);
+    final1(S_RR);
     read_scal();
     std::vector<int> newly;
     for (int c = 0; c < K; c++) {
@@ -794,26 +1021,11 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     if (!any_active()) break;
     if (restart) {  // continue from the true residual with a fresh direction
       LG_HIP(hipMemcpyAsync(h->pr, h->pt, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+      write_slot(S_RESTART, rflag);
     }
-    eng.precond(h->pr, h->pz);
-    project64(h->pz);
+    const T* z = eng.precond(h->pr, !restart);
     for (int c = 0; c < K; c++) work[c] += active[c] > 0.0 ? cw : 0.0;
-    if (flex) {
-      dot64(h->pz, h->pq, S_ZQ);
-      hipLaunchKernelGGL((k_beta<K>), dim3(1), dim3(64), 0, st, sc, 1);
-      hipLaunchKernelGGL((k_xpby<K>), dim3(g), dim3(kBlock), 0, st, h->pp, (const double*)h->pz,
-                         (const double*)sc, n);
-    } else {
-      dot64(h->pr, h->pz, S_TMP);
-      hipLaunchKernelGGL((k_beta<K>), dim3(1), dim3(64), 0, st, sc, 0);
-      hipLaunchKernelGGL((k_xpby<K>), dim3(g), dim3(kBlock), 0, st, h->pp, (const double*)h->pz,
-                         (const double*)sc, n);
-    }
-    if (restart) {
-      write_slot(S_MEAN, rflag);  // S_MEAN is free here: restart flags
-      hipLaunchKernelGGL((k_restart_p<K>), dim3(g), dim3(kBlock), 0, st, h->pp,
-                         (const double*)h->pz, (const double*)sl(S_MEAN), n);
-    }
+    new_direction(z, false, restart ? (const double*)sl(S_RESTART) : nullptr);
     LG_LAUNCH_CHECK();
   }
   lg_status status = LG_OK;
@@ -851,9 +1063,14 @@ void cycle_once(lg_hierarchy* h, const double* B, double* X, int k, hipStream_t 
   Engine<T, K> eng{h, st};
   const int64_t n = h->lev[0].n;
   hipLaunchKernelGGL(k_pad_in, dim3(nblk(n * K)), dim3(kBlock), 0, st, B, k, h->pb, K, n);
-  eng.precond(h->pb, h->pz);
-  hipLaunchKernelGGL(k_pad_out, dim3(nblk(n * k)), dim3(kBlock), 0, st, (const double*)h->pz, K, X,
-                     k, n);
+  const T* z = eng.precond(h->pb, false);
+  const double* z64 = (const double*)z;
+  if (sizeof(T) != sizeof(double)) {
+    hipLaunchKernelGGL((k_convert<T, double>), dim3(nblk(n * K)), dim3(kBlock), 0, st, z, h->pz,
+                       n * K);
+    z64 = h->pz;
+  }
+  hipLaunchKernelGGL(k_pad_out, dim3(nblk(n * k)), dim3(kBlock), 0, st, z64, K, X, k, n);
   LG_LAUNCH_CHECK();
 }
 
@@ -919,7 +1136,6 @@ void alloc_solve_workspace(lg_hierarchy* h, hipStream_t st) {
     if (L.type == LG_LEVEL_AGG) {
       L.vx2 = h->mem.alloc(v);
       L.vr = h->mem.alloc(v);
-      L.vp = h->mem.alloc(v);
     }
     const bool fcg_target = h->opts.cycle == LG_CYCLE_K && l > 0 &&
                             h->lev[l - 1].type == LG_LEVEL_AGG && L.type != LG_LEVEL_COARSEST;
@@ -942,7 +1158,7 @@ void alloc_solve_workspace(lg_hierarchy* h, hipStream_t st) {
   h->pt = h->mem.get<double>(m);
   if (h->opts.precision == LG_MIXED) h->cyc_in = h->mem.alloc((size_t)m * s);
   h->scal = h->mem.get<double>(S_COUNT * K);
-  h->red = h->mem.get<double>((int64_t)kDotPartials * 2 * K);
+  h->red = h->mem.get<double>((int64_t)kDotPartials * 3 * K);
   LG_HIP(hipHostMalloc((void**)&h->host_scal, sizeof(double) * S_COUNT * K, hipHostMallocDefault));
   (void)st;
 }
