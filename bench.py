@@ -25,6 +25,7 @@ import time
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+PROFILES = os.path.join(ROOT, "profiles")
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
@@ -34,19 +35,27 @@ KERNEL_SOURCES = ["paper_1705_06266_amd/csrc/common.h", "paper_1705_06266_amd/cs
                   "paper_1705_06266_amd/csrc/solve.hip", "paper_1705_06266_amd/csrc/setup.hip",
                   "paper_1705_06266_amd/csrc/prims.hip"]
 
+# family: the kernel timed for the roofline (one kernel instance per workload);
+# kernel: its symbol as rocprofv3 prints it.
 WORKLOADS = {
     "rmat_s18": dict(cfg="c2_rmat_s18", precision="fp64", k=1,
-                     label="rmat_s18_ef16_lcc_u01_fp64_1rhs"),
+                     label="rmat_s18_ef16_lcc_u01_fp64_1rhs", family="spmv",
+                     kernel="k_rows<lg::LapOp<double, 1, 0, 0> >"),
     "grid2d_64": dict(cfg="c1_grid2d_64", precision="fp64", k=1,
-                      label="grid2d_64x64_unit_fp64_1rhs"),
+                      label="grid2d_64x64_unit_fp64_1rhs", family="spmv",
+                      kernel="k_rows<lg::LapOp<double, 1, 0, 0> >"),
     "grid3d_128_mixed": dict(cfg="c3_grid3d_128", precision="mixed", k=32,
-                             label="grid3d_128cube_loguniform_mixed_32rhs"),
+                             label="grid3d_128cube_loguniform_mixed_32rhs", family="cheb",
+                             kernel="k_rows_col<lg::LapColOp<float, 32, 2, 0> >"),
     "grid3d_128_fp64": dict(cfg="c3_grid3d_128", precision="fp64", k=32,
-                            label="grid3d_128cube_loguniform_fp64_32rhs"),
+                            label="grid3d_128cube_loguniform_fp64_32rhs", family="cheb",
+                            kernel="k_rows_col<lg::LapColOp<double, 32, 2, 0> >"),
     "chunglu_4m_mixed": dict(cfg="c4_chunglu_4m", precision="mixed", k=16,
-                             label="chunglu_4m_g2.1_d16_mixed_16rhs"),
+                             label="chunglu_4m_g2.1_d16_mixed_16rhs", family="cheb",
+                             kernel="k_rows_col<lg::LapColOp<float, 16, 2, 0> >"),
     "chunglu_4m_fp64": dict(cfg="c4_chunglu_4m", precision="fp64", k=16,
-                            label="chunglu_4m_g2.1_d16_fp64_16rhs"),
+                            label="chunglu_4m_g2.1_d16_fp64_16rhs", family="cheb",
+                            kernel="k_rows_col<lg::LapColOp<double, 16, 2, 0> >"),
 }
 
 
@@ -58,14 +67,22 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def pmc_path(family, workload):
+    return os.path.join(PROFILES, f"{family}_{workload}_pmc.txt")
+
+
 def load_traffic(family, workload):
-    """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was
-    taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"{family}_{workload}_pmc.json")
+    """HBM bytes per launch of the roofline kernel from a committed rocprofv3
+    counter summary (its "json:" line), if it was taken on the current kernel
+    sources; else None."""
+    path = pmc_path(family, workload)
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        rec = json.load(f)
+        line = [ln for ln in f if ln.startswith("json: ")]
+    if not line:
+        return None
+    rec = json.loads(line[-1][len("json: "):])
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
@@ -92,6 +109,114 @@ def cpu_baseline(g, b, seconds_target=20.0):
                        f"workload, {el:.1f} s single-threaded")
 
 
+# ------------------------------------------------------------ profile summaries
+def _kernels_from_db(db_path):
+    import sqlite3
+
+    db = sqlite3.connect(db_path)
+    return list(db.execute("select name, duration from kernels order by start"))
+
+
+def _short(name):
+    return name.split("(")[0].replace("void ", "").replace("lg::", "", 1).strip()
+
+
+def pmc_summary(args):
+    """Turns two rocprofv3 counter runs of this script (FETCH_SIZE, WRITE_SIZE,
+    each with --calibration-copy) into HBM bytes per launch of the roofline
+    kernel: every counter is scaled by what it reads for a copy of known size."""
+    import sqlite3
+
+    wl = WORKLOADS[args.workload]
+    out = {}
+    for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        path = os.path.join(args.pmc_summary, counter.lower(), "run_results.db")
+        db = sqlite3.connect(path)
+        rows = list(db.execute(
+            "select kernel_name, value from counters_collection where counter_name = ?", (counter,)))
+        copy_kib = [v for n, v in rows if "copyBuffer" in n or "elementwise" in n]
+        # the calibration copy moves 512 MiB each way: its largest dispatch
+        cal = max(copy_kib)
+        scale = (512 * 1024) / cal
+        vals = [v for n, v in rows if _short(n) == wl["kernel"]]
+        if not vals:
+            raise SystemExit(f"{wl['kernel']} not found in {path}")
+        out[counter] = dict(kib_per_launch_raw=float(np.mean(vals)), calibration_kib=cal,
+                            scale=scale, launches=len(vals),
+                            bytes_per_launch=float(np.mean(vals)) * scale * 1024)
+    rec = dict(workload=args.workload, family=wl["family"], kernel=wl["kernel"],
+               kernel_source_hash=kernel_source_hash(),
+               read_bytes_per_launch=out["FETCH_SIZE"]["bytes_per_launch"],
+               write_bytes_per_launch=out["WRITE_SIZE"]["bytes_per_launch"],
+               hbm_bytes_per_launch=out["FETCH_SIZE"]["bytes_per_launch"]
+               + out["WRITE_SIZE"]["bytes_per_launch"],
+               counters=out, command=args.command)
+    f_, w_ = out["FETCH_SIZE"], out["WRITE_SIZE"]
+    lines = [f"# rocprofv3 byte counters, workload {wl['label']}", "",
+             "commands (one run per counter):", "  " + args.command, "",
+             f"kernel {wl['kernel']} ({f_['launches']} dispatches)",
+             f"FETCH_SIZE {f_['kib_per_launch_raw']:.1f} KiB/dispatch; calibration copy of 512 MiB "
+             f"reads {f_['calibration_kib']:.0f} KiB -> scale {f_['scale']:.4f} -> "
+             f"{f_['bytes_per_launch'] / 1e6:.2f} MB read per dispatch",
+             f"WRITE_SIZE {w_['kib_per_launch_raw']:.1f} KiB/dispatch; calibration copy of 512 MiB "
+             f"reads {w_['calibration_kib']:.0f} KiB -> scale {w_['scale']:.4f} -> "
+             f"{w_['bytes_per_launch'] / 1e6:.2f} MB written per dispatch",
+             f"HBM traffic {rec['hbm_bytes_per_launch'] / 1e6:.2f} MB per dispatch",
+             "", "json: " + json.dumps(rec)]
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(pmc_path(wl["family"], args.workload), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def trace_summary(args):
+    """Writes a text summary of a rocprofv3 --kernel-trace --stats run of this
+    script: per-kernel totals and averages, and the roofline kernel's row."""
+    import csv
+
+    wl = WORKLOADS[args.workload]
+    stats = None
+    for root, _, files in os.walk(args.trace_summary):
+        for f in files:
+            if f.endswith("kernel_stats.csv"):
+                stats = os.path.join(root, f)
+    if stats is None:
+        raise SystemExit("no kernel_stats.csv under " + args.trace_summary)
+    with open(stats) as f:
+        rows = list(csv.DictReader(f))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# rocprofv3 kernel statistics, workload {wl['label']}",
+             "", "command:", "  " + args.command, "",
+             f"{'total ms':>10} {'share':>6} {'calls':>7} {'avg us':>9}  kernel"]
+    target = None
+    for r in rows[:40]:
+        name = _short(r["Name"])
+        t = float(r["TotalDurationNs"])
+        lines.append(f"{t / 1e6:10.3f} {100 * t / tot:5.1f}% {int(r['Calls']):7d} "
+                     f"{float(r['AverageNs']) / 1e3:9.2f}  {name}")
+    for r in rows:
+        if _short(r["Name"]) == wl["kernel"]:
+            target = r
+    lines.append("")
+    if target:
+        lines.append(f"roofline kernel {wl['kernel']}: {int(target['Calls'])} calls, "
+                     f"average {float(target['AverageNs']) / 1e3:.2f} us (rocprofv3)")
+    if args.bench_log:
+        with open(args.bench_log) as f:
+            rec = json.loads([ln for ln in f if ln.startswith("{")][-1])
+        r = rec["roofline"]
+        lines.append(f"same run, HIP events in bench.py over the timed steps: {r['launches']} launches, "
+                     f"average {r['avg_launch_ms'] * 1e3:.2f} us, "
+                     f"{r['algorithmic_bytes_per_launch'] / 1e6:.2f} MB algorithmic per launch, "
+                     f"{r['achieved']:.0f} GB/s")
+    os.makedirs(PROFILES, exist_ok=True)
+    path = os.path.join(PROFILES, f"{wl['family']}_{args.workload}_kernel_stats.txt")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,14 +224,28 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat_s18", choices=list(WORKLOADS))
     ap.add_argument("--latency-solves", type=int, default=100)
-    ap.add_argument("--family", default="cheb", help="kernel family timed for the roofline")
+    ap.add_argument("--family", default=None, help="kernel family timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="end with a 512 MiB device copy (scale for rocprofv3 byte counters)")
+    ap.add_argument("--pmc-summary", default=None,
+                    help="directory with fetch_size/ and write_size/ rocprofv3 runs: write the "
+                         "traffic summary and exit (no GPU)")
+    ap.add_argument("--trace-summary", default=None,
+                    help="directory of a rocprofv3 --stats csv run: write the summary and exit")
+    ap.add_argument("--command", default="", help="command line recorded in summaries")
+    ap.add_argument("--bench-log", default=None, help="bench output of the profiled run (summaries)")
     args = ap.parse_args()
+
+    if args.pmc_summary:
+        return pmc_summary(args)
+    if args.trace_summary:
+        return trace_summary(args)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(a batch of right-hand sides or a pool of graphs would shard by replication; "
-              "see the design notes)", file=sys.stderr)
+              "(batches of right-hand sides or a pool of graphs would shard by keeping a "
+              "replica of each hierarchy per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -116,6 +255,7 @@ def main():
 
     dev = torch.device("cuda:0")
     wl = WORKLOADS[args.workload]
+    family = args.family or wl["family"]
     g = gg.config_graph(wl["cfg"])
     b_host = gg.config_rhs(wl["cfg"], g.n, wl["k"])
     rp = torch.as_tensor(g.row_ptr).to(dev)
@@ -135,7 +275,7 @@ def main():
         h, info = step()
         del h
 
-    lg.lg_profile_enable(args.family)
+    lg.lg_profile_enable(family)
     setup_ms, solve_ms, infos = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -168,8 +308,8 @@ def main():
     lat = np.array(lat)
     stats = lg.lg_hierarchy_stats(h)
 
-    # fp64 SpMV bandwidth on the finest level (algorithmic bytes)
-    n0, m0 = stats[0]["n"], stats[0]["nnz"]
+    # fp64 SpMV bandwidth on the finest level (algorithmic bytes), lg_spmv's own kernels
+    n0 = stats[0]["n"]
     kk = 1 if wl["k"] == 1 else min(32, 1 << (wl["k"] - 1).bit_length())
     x = torch.randn(n0, kk, dtype=torch.float64, device=dev)
     y = torch.empty_like(x)
@@ -185,7 +325,7 @@ def main():
     spmv_gbs = sp_bytes / (sp_ms * 1e-3) / 1e9 if sp_ms > 0 else None
 
     achieved = fam_bytes / (fam_ms * 1e-3) / 1e9 if fam_ms > 0 else 0.0
-    traffic = load_traffic(args.family, args.workload)
+    traffic = load_traffic(family, args.workload) if family == wl["family"] else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -203,12 +343,13 @@ def main():
                    "step": "setup+solve", "levels": len(stats)},
         "roofline": {
             "bound": "hbm",
-            "kernel_family": args.family,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "kernel": wl["kernel"] if family == wl["family"] else None,
+            "kernel_family": family,
             "launches": launches,
             "avg_launch_ms": fam_ms / launches if launches else None,
             "algorithmic_bytes_per_launch": fam_bytes / launches if launches else None,
@@ -217,14 +358,22 @@ def main():
         "solve_ms": float(np.median(solve_ms)),
         "iters": infos[-1][0]["iters"],
         "wda": infos[-1][0]["wda"],
-        "solve_only": {"solves_per_s": wl["k"] * 1e3 / float(lat.mean()),
-                       "p50_ms": float(np.percentile(lat, 50)),
-                       "p99_ms": float(np.percentile(lat, 99)), "solves": int(lat.size)},
         "spmv_fp64_gbs": spmv_gbs,
         "spmv_fp64_ms": sp_ms / sp_n if sp_n else None,
         "spmv_fp64_rhs": kk,
     }
+    if lat.size:
+        out["solve_only"] = {"solves_per_s": wl["k"] * 1e3 / float(lat.mean()),
+                             "p50_ms": float(np.percentile(lat, 50)),
+                             "p99_ms": float(np.percentile(lat, 99)), "solves": int(lat.size)}
     del h
+    if args.calibration_copy:
+        src = torch.empty(64 << 20, dtype=torch.float64, device=dev)  # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline and args.workload in ("rmat_s18", "grid2d_64"):
         out["cpu_baseline"] = cpu_baseline(g, b_host)
     print(json.dumps(out), flush=True)

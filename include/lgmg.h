@@ -171,10 +171,14 @@ double lg_setup_ms(const lg_hierarchy* h);
 void lg_free(lg_hierarchy* h);
 
 /* Kernel timing with HIP events for one kernel family (name as listed by
- * lg_profile_names, e.g. "spmm"), recorded around each of its launches on the
- * launch stream while enabled.  lg_profile_read returns the launch count, the
- * summed event time and the summed algorithmic bytes of those launches, then
- * resets the counters.  Disabled by default (family NULL). */
+ * lg_profile_names), recorded around each of its launches on the launch
+ * stream while enabled.  Families of the sparse products time the row kernel
+ * alone: "spmv" the fp64 L x of setup's Lanczos steps and of the CG iteration,
+ * "spmm" lg_spmv's own launches, "cheb0" the zero-start smoother step, "cheb1"
+ * the first step from a nonzero iterate, "cheb" the later steps, "resid" the
+ * cycle's residual, "resid64" the CG's true residual.  lg_profile_read returns
+ * the launch count, the summed event time and the summed algorithmic bytes of
+ * those launches, then resets the counters.  Disabled by default (NULL). */
 lg_status lg_profile_enable(const char* family);
 lg_status lg_profile_read(int64_t* launches, double* total_ms, double* total_bytes);
 const char* lg_profile_names(void);

@@ -14,6 +14,7 @@
 // This keeps a vertex of degree 1e5 from serialising one wavefront.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -201,6 +202,24 @@ struct Sched {
 
 // Target entries per lane: a lane issues this many independent gathers.
 constexpr int kPerLane = 4;
+
+// ------------------------------------------------- profiling (HIP events)
+// Times the launches between construction and destruction when family is
+// the enabled one.  attached = true: the scope encloses exactly one launch,
+// which takes start() and stop() as the events of its own dispatch
+// (hipExtLaunchKernelGGL), so the time is the kernel's alone; otherwise the
+// events are recorded on the stream around the enclosed work.
+struct ProfScope {
+  ProfScope(const char* family, hipStream_t st, double bytes, bool attached = false);
+  ~ProfScope();
+  hipEvent_t start() const { return on ? a : nullptr; }
+  hipEvent_t stop() const { return on ? b : nullptr; }
+  bool on;
+  bool attached;
+  hipStream_t st;
+  double bytes;
+  hipEvent_t a, b;
+};
 
 __host__ __device__ inline int degree_class(int d, int hub_deg) {
   if (d > hub_deg) return kClasses;  // hub or split
@@ -403,8 +422,11 @@ inline int64_t resident_grid(KernelT kernel) {
   return cached;
 }
 
+// fam/bytes: the kernel-timing family and algorithmic bytes of this product;
+// the events enclose the row kernel alone (not the split-row epilogue).
 template <class Op>
-void run_rows(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st) {
+void run_rows(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st,
+              const char* fam = "", double bytes = 0.0) {
   static_assert(sizeof(typename Op::Acc) <= kPartialBytes, "accumulator larger than a partial slot");
   static_assert(sizeof(typename Op::Acc) % 4 == 0, "accumulator size must be a multiple of 4");
   if (s.n == 0) return;
@@ -412,10 +434,14 @@ void run_rows(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st) {
   const int64_t blocks =
       round_up8(s.nchunk + s.nhub) + round_up8(std::min<int64_t>(total, resident_grid(k_rows<Op>)));
   if (blocks == 0) return;
-  hipLaunchKernelGGL((k_rows<Op>), dim3((unsigned)blocks), dim3(kBlock), 0, st, op, rp,
-                     (const int32_t*)s.perm, s.ct, s.nhub, (const int32_t*)s.hub_rows, s.nchunk,
-                     (const int32_t*)s.split_rows, (const int32_t*)s.split_cptr,
-                     (const int32_t*)s.chunk_split, reinterpret_cast<typename Op::Acc*>(s.partial));
+  {
+    ProfScope ps(fam, st, bytes, true);
+    hipExtLaunchKernelGGL((k_rows<Op>), dim3((unsigned)blocks), dim3(kBlock), 0, st, ps.start(),
+                          ps.stop(), 0, op, rp, (const int32_t*)s.perm, s.ct, s.nhub,
+                          (const int32_t*)s.hub_rows, s.nchunk, (const int32_t*)s.split_rows,
+                          (const int32_t*)s.split_cptr, (const int32_t*)s.chunk_split,
+                          reinterpret_cast<typename Op::Acc*>(s.partial));
+  }
   LG_LAUNCH_CHECK();
   if (s.nsplit) {
     hipLaunchKernelGGL((k_split_fix<Op>), dim3((unsigned)ceil_div(s.nsplit, 64)), dim3(64), 0, st, op,
@@ -569,7 +595,8 @@ __global__ __launch_bounds__(64) void k_split_fix_col(Op op, const int32_t* __re
 }
 
 template <class Op>
-void run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st) {
+void run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st,
+                  const char* fam = "", double bytes = 0.0) {
   constexpr int L = Op::kL;
   static_assert(sizeof(typename Op::Acc) * L <= kPartialBytes, "partial slot too small");
   if (s.n == 0) return;
@@ -585,10 +612,14 @@ void run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_t s
   const int64_t blocks =
       round_up8(s.nchunk + s.nhub) + round_up8(std::min<int64_t>(blk, resident_grid(k_rows_col<Op>)));
   if (blocks == 0) return;
-  hipLaunchKernelGGL((k_rows_col<Op>), dim3((unsigned)blocks), dim3(kBlock), 0, st, op, rp,
-                     (const int32_t*)s.perm, ct, s.nhub, (const int32_t*)s.hub_rows, s.nchunk,
-                     (const int32_t*)s.split_rows, (const int32_t*)s.split_cptr,
-                     (const int32_t*)s.chunk_split, reinterpret_cast<typename Op::Acc*>(s.partial));
+  {
+    ProfScope ps(fam, st, bytes, true);
+    hipExtLaunchKernelGGL((k_rows_col<Op>), dim3((unsigned)blocks), dim3(kBlock), 0, st, ps.start(),
+                          ps.stop(), 0, op, rp, (const int32_t*)s.perm, ct, s.nhub,
+                          (const int32_t*)s.hub_rows, s.nchunk, (const int32_t*)s.split_rows,
+                          (const int32_t*)s.split_cptr, (const int32_t*)s.chunk_split,
+                          reinterpret_cast<typename Op::Acc*>(s.partial));
+  }
   LG_LAUNCH_CHECK();
   if (s.nsplit) {
     hipLaunchKernelGGL((k_split_fix_col<Op>), dim3((unsigned)ceil_div(s.nsplit * L, 64)), dim3(64), 0,
@@ -644,15 +675,6 @@ struct TempArena {
   Arena* a;
 };
 
-// ------------------------------------------------- profiling (HIP events)
-struct ProfScope {
-  ProfScope(const char* family, hipStream_t st, double bytes);
-  ~ProfScope();
-  bool on;
-  hipStream_t st;
-  double bytes;
-  hipEvent_t a, b;
-};
 
 // ------------------------------------------------------------- helpers
 void build_sched(Sched& s, const int32_t* rp, int64_t n, int64_t nnz, Arena& keep, Arena& tmp,
@@ -664,8 +686,11 @@ int64_t scan_i64(const int64_t* in, int64_t* out, int64_t n, Arena& tmp, hipStre
 int64_t scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, Arena& tmp, hipStream_t st,
                         bool want_total);
 // Stable LSD radix sort of (key, val) pairs over the listed 8-bit digit shifts.
+// pack > 0: keys are (hi << 32 | lo) with hi, lo < 2^pack and the shifts index
+// the packed value (hi << pack | lo) (see pair_shifts).
 void radix_sort_pairs(uint64_t* keys, uint64_t* vals, int64_t n, const std::vector<int>& shifts,
-                      Arena& tmp, hipStream_t st);
+                      Arena& tmp, hipStream_t st, int pack = 0);
+std::vector<int> pair_shifts(int bits);  // digits of a packed pair of two bits-wide halves
 std::vector<int> digit_shifts(int bits_lo, int bits_hi);  // digits covering [0,bits_lo) and [32,32+bits_hi)
 int bits_for(int64_t max_value);
 int64_t read_i64(const int64_t* dev, hipStream_t st);

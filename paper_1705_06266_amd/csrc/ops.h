@@ -11,7 +11,7 @@ struct VecAcc {
   T v[K];
 };
 
-enum { LAP_SPMV = 0, LAP_RESID = 1, LAP_CHEB = 2, LAP_CHEB_FIRST = 3, LAP_CHEB_ZERO = 4 };
+enum { LAP_SPMV = 0, LAP_RESID = 1, LAP_CHEB = 2, LAP_CHEB_FIRST = 3, LAP_CHEB_ZERO = 4, LAP_CHEB_X1 = 5 };
 
 // Row i: s = sum_j w_ij x_j (k columns), (L x)_i = d_i x_i - s.  The Chebyshev
 // modes use the three-term recurrence on iterates (Section 3.6 smoother):
@@ -23,7 +23,12 @@ enum { LAP_SPMV = 0, LAP_RESID = 1, LAP_CHEB = 2, LAP_CHEB_FIRST = 3, LAP_CHEB_Z
 //  LAP_CHEB_ZERO:  the first two steps from a zero guess in one pass: with
 //                  x1 = c0 dinv b (never stored unless p is set, then p = x1),
 //                  y = x1 + c1 x1 + c2 dinv (b - L x1); x must point at b.
-template <typename T, int K, int MODE>
+//  LAP_CHEB_X1:    the second step from a zero guess with x1 stored in x:
+//                  y = x + c1 x + c2 dinv (b - L x).  (CHEB_ZERO gathers dinv
+//                  with every neighbour, which pays off only for wide rows.)
+// TAG only separates kernel instances (lg_spmv's own launches from the
+// solver's) so that profiles attribute time per call site.
+template <typename T, int K, int MODE, int TAG = 0>
 struct LapOp {
   using Acc = VecAcc<T, K>;
   const int32_t* __restrict__ col;
@@ -77,7 +82,7 @@ struct LapOp {
         T pn;
         if (MODE == LAP_CHEB_FIRST) pn = c2 * r;
         else if (MODE == LAP_CHEB) pn = c1 * (xi - y[idx]) + c2 * r;
-        else pn = c1 * xi + c2 * r;
+        else pn = c1 * xi + c2 * r;  // CHEB_ZERO, CHEB_X1
         if (MODE == LAP_CHEB_ZERO && p) p[idx] = xi;
         y[idx] = xi + pn;
       }
@@ -87,7 +92,7 @@ struct LapOp {
 
 // Column-split form of LapOp for k * sizeof(T) >= 32 bytes: each of kL lanes
 // owns V = 16 / sizeof(T) consecutive columns.
-template <typename T, int K, int MODE>
+template <typename T, int K, int MODE, int TAG = 0>
 struct LapColOp {
   static constexpr int V = 16 / (int)sizeof(T);
   static constexpr int kL = K / V;
@@ -170,7 +175,7 @@ struct LapColOp {
         T pn;
         if (MODE == LAP_CHEB_FIRST) pn = c2 * r;
         else if (MODE == LAP_CHEB) pn = c1 * (xv[v] - q.yv[v]) + c2 * r;
-        else pn = c1 * xv[v] + c2 * r;
+        else pn = c1 * xv[v] + c2 * r;  // CHEB_ZERO, CHEB_X1
         out[v] = xv[v] + pn;
       }
       if (MODE == LAP_CHEB_ZERO && p) *reinterpret_cast<vec_t*>(p + base) = xv;

@@ -99,13 +99,14 @@ hipEvent_t take_event(Prof& p) {
 }
 }  // namespace
 
-ProfScope::ProfScope(const char* family, hipStream_t s, double b) : on(false), st(s), bytes(b) {
+ProfScope::ProfScope(const char* family, hipStream_t s, double b, bool att)
+    : on(false), attached(att), st(s), bytes(b) {
   Prof& p = prof();
   if (p.family.empty() || p.family != family) return;
   std::lock_guard<std::mutex> g(p.mu);
   a = take_event(p);
   this->b = take_event(p);
-  LG_HIP(hipEventRecord(a, st));
+  if (!attached) LG_HIP(hipEventRecord(a, st));
   on = true;
 }
 
@@ -113,7 +114,7 @@ ProfScope::~ProfScope() {
   if (!on) return;
   Prof& p = prof();
   std::lock_guard<std::mutex> g(p.mu);
-  (void)hipEventRecord(b, st);
+  if (!attached) (void)hipEventRecord(b, st);
   p.pending.push_back({a, b});
   p.pending_bytes.push_back(bytes);
 }
@@ -156,8 +157,8 @@ extern "C" lg_status lg_profile_read(int64_t* launches, double* total_ms, double
 }
 
 extern "C" const char* lg_profile_names(void) {
-  return "spmm,cheb,resid,restrict,prolong,coarse,pcg_vec,jacobi_xsum,affinity,vote,"
-         "elim_select,radix,galerkin_reduce";
+  return "spmv,spmm,resid64,cheb0,cheb1,cheb,resid,spmm_inner,restrict,prolong,coarse,"
+         "jacobi_xsum,affinity,vote,elim_select,radix,galerkin_reduce";
 }
 
 namespace lg {
@@ -169,7 +170,8 @@ constexpr int kScanTile = kBlock * kScanIPT;
 template <typename TI>
 __global__ __launch_bounds__(kBlock) void k_scan_tiles(const TI* __restrict__ in,
                                                        int64_t* __restrict__ out,
-                                                       int64_t* __restrict__ sums, int64_t n) {
+                                                       int64_t* __restrict__ sums, int64_t n,
+                                                       int64_t* __restrict__ total) {
   __shared__ int64_t wsum[kBlock / 64];
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -198,15 +200,18 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const TI* __restrict__ in
     if (i < n) out[i] = run;
     run += v[k];
   }
-  if (t == kBlock - 1) sums[blockIdx.x] = wpre + x;
+  if (t == kBlock - 1) {
+    sums[blockIdx.x] = wpre + x;
+    if (total) *total = wpre + x;  // single-tile scan: the tile sum is the total
+  }
 }
 
+// out[i] += offset of its tile for i < n; out[n] = total (offs[nb]).
 __global__ void k_scan_add(int64_t* __restrict__ out, const int64_t* __restrict__ offs, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) out[i] += offs[i / kScanTile];
+  else if (i == n) out[n] = offs[(n + kScanTile - 1) / kScanTile];
 }
-
-__global__ void k_copy_i64(int64_t* dst, const int64_t* src) { *dst = *src; }
 __global__ void k_zero_i64(int64_t* dst) { *dst = 0; }
 
 template <typename TI>
@@ -217,15 +222,13 @@ static void scan_core(const TI* in, int64_t* out, int64_t n, Arena& tmp, hipStre
   }
   const int64_t nb = ceil_div(n, kScanTile);
   int64_t* sums = tmp.get<int64_t>(nb);
-  hipLaunchKernelGGL((k_scan_tiles<TI>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, out, sums, n);
-  if (nb == 1) {
-    hipLaunchKernelGGL(k_copy_i64, dim3(1), dim3(1), 0, st, out + n, sums);
-  } else {
+  hipLaunchKernelGGL((k_scan_tiles<TI>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, out, sums, n,
+                     nb == 1 ? out + n : (int64_t*)nullptr);
+  if (nb > 1) {
     int64_t* offs = tmp.get<int64_t>(nb + 1);
     scan_core<int64_t>(sums, offs, nb, tmp, st);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, st, out,
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)ceil_div(n + 1, kBlock)), dim3(kBlock), 0, st, out,
                        offs, n);
-    hipLaunchKernelGGL(k_copy_i64, dim3(1), dim3(1), 0, st, out + n, offs + nb);
   }
   LG_LAUNCH_CHECK();
 }
@@ -260,9 +263,17 @@ int64_t scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, Arena& tmp, 
 constexpr int kRadixIPT = 16;
 constexpr int kRadixTile = kBlock * kRadixIPT;
 
+// Digit of a key.  pack > 0: the key holds a pair (hi << 32 | lo) with
+// hi, lo < 2^pack, and digits are taken from the contiguous (hi << pack | lo),
+// which sorts in the same order with fewer digits.
+__device__ __forceinline__ int radix_digit(uint64_t key, int shift, int pack) {
+  if (pack) key = ((key >> 32) << pack) | (key & 0xffffffffULL);
+  return (int)((key >> shift) & 255);
+}
+
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n,
-                                                       int shift, int32_t* __restrict__ hist,
-                                                       int64_t nb) {
+                                                       int shift, int pack,
+                                                       int32_t* __restrict__ hist, int64_t nb) {
   __shared__ int cnt[256];
   const int t = threadIdx.x;
   cnt[t] = 0;
@@ -271,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t* __restric
 #pragma unroll 4
   for (int r = 0; r < kRadixIPT; r++) {
     const int64_t i = base + (int64_t)r * kBlock + t;
-    if (i < n) atomicAdd(&cnt[(int)((keys[i] >> shift) & 255)], 1);
+    if (i < n) atomicAdd(&cnt[radix_digit(keys[i], shift, pack)], 1);
   }
   __syncthreads();
   hist[(int64_t)t * nb + blockIdx.x] = cnt[t];
@@ -281,7 +292,8 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t* __restric
 // index order inside the tile; equal digits keep that order.
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     const uint64_t* __restrict__ kin, const uint64_t* __restrict__ vin, uint64_t* __restrict__ kout,
-    uint64_t* __restrict__ vout, int64_t n, int shift, const int64_t* __restrict__ offs, int64_t nb) {
+    uint64_t* __restrict__ vout, int64_t n, int shift, int pack, const int64_t* __restrict__ offs,
+    int64_t nb) {
   __shared__ int64_t run[256];
   __shared__ int wc[kBlock / 64][256];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -299,7 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     if (valid) {
       key = kin[i];
       val = vin[i];
-      d = (int)((key >> shift) & 255);
+      d = radix_digit(key, shift, pack);
     }
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -339,8 +351,14 @@ std::vector<int> digit_shifts(int bits_lo, int bits_hi) {
   return s;
 }
 
+std::vector<int> pair_shifts(int bits) {
+  std::vector<int> s;
+  for (int b = 0; b < 2 * bits; b += 8) s.push_back(b);
+  return s;
+}
+
 void radix_sort_pairs(uint64_t* keys, uint64_t* vals, int64_t n, const std::vector<int>& shifts,
-                      Arena& tmp, hipStream_t st) {
+                      Arena& tmp, hipStream_t st, int pack) {
   if (n <= 1 || shifts.empty()) return;
   ProfScope prof_scope("radix", st, (double)n * 32.0 * shifts.size());
   Arena::Mark m = tmp.mark();
@@ -351,12 +369,13 @@ void radix_sort_pairs(uint64_t* keys, uint64_t* vals, int64_t n, const std::vect
   int64_t* offs = tmp.get<int64_t>(256 * nb + 1);
   uint64_t *ka = keys, *va = vals, *kb = k2, *vb = v2;
   for (int sh : shifts) {
-    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, st, ka, n, sh, hist, nb);
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, st, ka, n, sh, pack, hist,
+                       nb);
     Arena::Mark m2 = tmp.mark();
     scan_core<int32_t>(hist, offs, 256 * nb, tmp, st);
     tmp.rewind(m2);
     hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kBlock), 0, st, ka, va, kb, vb, n,
-                       sh, offs, nb);
+                       sh, pack, offs, nb);
     LG_LAUNCH_CHECK();
     std::swap(ka, kb);
     std::swap(va, vb);

@@ -249,53 +249,88 @@ __global__ void k_cidx(const int32_t* __restrict__ keepC, const int64_t* __restr
 // 1 if b stays, deg(b) - 1 fill entries if b is eliminated, 0 if a is.
 __global__ void k_elim_count(const int32_t* __restrict__ rowidx, const int32_t* __restrict__ col,
                              const int32_t* __restrict__ rp, const int32_t* __restrict__ cidx,
-                             int64_t nnz, int32_t* __restrict__ cnt, int32_t* __restrict__ ptflag) {
+                             int64_t nnz, int32_t* __restrict__ direct, int32_t* __restrict__ fill,
+                             int32_t* __restrict__ ptflag) {
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e >= nnz) return;
   const int a = rowidx[e], b = col[e];
-  int c = 0, f = 0;
+  int c = 0, f = 0, fl = 0;
   if (cidx[a] >= 0) {
     if (cidx[b] >= 0) {
       c = 1;
     } else {
-      c = rp[b + 1] - rp[b] - 1;
+      fl = rp[b + 1] - rp[b] - 1;
       f = 1;
     }
   }
-  cnt[e] = c;
+  direct[e] = c;
+  fill[e] = fl;
   ptflag[e] = f;
 }
 
-// Schur complement entries (Section 3.4): (a', b') <- w_ab, and for an
-// eliminated neighbour f of a, (a', c') <- (w_fa * w_fc) / d_f for each other
-// neighbour c of f.
+// Schur complement entries (Section 3.4) in two streams: the kept edges
+// (a', b') <- w_ab, in CSR order, which is already (a', b') order because C
+// keeps increasing ids; and the fill (a', c') <- (w_fa * w_fc) / d_f for each
+// eliminated neighbour f of a and each other neighbour c of f.
 __global__ void k_elim_emit(const int32_t* __restrict__ rowidx, const int32_t* __restrict__ rp,
                             const int32_t* __restrict__ col, const double* __restrict__ w,
                             const double* __restrict__ d, const int32_t* __restrict__ cidx,
-                            const int64_t* __restrict__ off, int64_t nnz,
-                            uint64_t* __restrict__ keys, double* __restrict__ vals) {
+                            const int64_t* __restrict__ offd, const int64_t* __restrict__ offf,
+                            int64_t nnz, uint64_t* __restrict__ dkeys, double* __restrict__ dvals,
+                            uint64_t* __restrict__ fkeys, double* __restrict__ fvals) {
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e >= nnz) return;
   const int a = rowidx[e];
   const int ca = cidx[a];
   if (ca < 0) return;
   const int b = col[e];
-  int64_t pos = off[e];
   const uint64_t hi = (uint64_t)ca << 32;
   if (cidx[b] >= 0) {
-    keys[pos] = hi | (uint32_t)cidx[b];
-    vals[pos] = w[e];
+    dkeys[offd[e]] = hi | (uint32_t)cidx[b];
+    dvals[offd[e]] = w[e];
     return;
   }
+  int64_t pos = offf[e];
   const double w_fa = w[e];
   const double d_f = d[b];
   for (int e2 = rp[b]; e2 < rp[b + 1]; e2++) {
     const int c = col[e2];
     if (c == a) continue;
-    keys[pos] = hi | (uint32_t)cidx[c];
-    vals[pos] = (w_fa * w[e2]) / d_f;
+    fkeys[pos] = hi | (uint32_t)cidx[c];
+    fvals[pos] = (w_fa * w[e2]) / d_f;
     pos++;
   }
+}
+
+// Merge of a sorted stream A with a sorted stream B into out (ties: A first).
+// B entries find their slot by binary search in A and flag it; A entries then
+// fill the unflagged slots in order (k_merge_a, after a scan of the flags).
+__global__ void k_merge_b(const uint64_t* __restrict__ ak, int64_t na, const uint64_t* __restrict__ bk,
+                          const double* __restrict__ bv, int64_t nb, uint64_t* __restrict__ ok,
+                          double* __restrict__ ov, int32_t* __restrict__ flag) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= nb) return;
+  const uint64_t k = bk[j];
+  int64_t lo = 0, hi = na;  // first A entry > k
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (ak[mid] <= k) lo = mid + 1;
+    else hi = mid;
+  }
+  const int64_t p = j + lo;
+  ok[p] = k;
+  ov[p] = bv[j];
+  flag[p] = 1;
+}
+
+__global__ void k_merge_a(const uint64_t* __restrict__ ak, const double* __restrict__ av,
+                          const int32_t* __restrict__ flag, const int64_t* __restrict__ before,
+                          int64_t m, uint64_t* __restrict__ ok, double* __restrict__ ov) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= m || flag[p]) return;
+  const int64_t i = p - before[p];
+  ok[p] = ak[i];
+  ov[p] = av[i];
 }
 
 // F-part of P^T: coarse row of a lists (f, w_af / d_f) for eliminated neighbours f.
@@ -783,6 +818,7 @@ struct Ctx {
   TempArena lease;
   Arena& tmp = *lease.a;
   int* flags = nullptr;  // device error flags
+  int64_t* pair = nullptr;  // two device words for reading totals back together
   uint64_t key = 0;
 };
 
@@ -895,19 +931,49 @@ void build_elim(Ctx& c, Level& L, const ElimChoice& ch, Level& out) {
                      L.cvert);
   int32_t* rowidx = tmp.get<int32_t>(nnz);
   row_index(c, L, rowidx);
-  int32_t* cnt = tmp.get<int32_t>(nnz);
+  int32_t* dcnt = tmp.get<int32_t>(nnz);
+  int32_t* fcnt = tmp.get<int32_t>(nnz);
   int32_t* ptflag = tmp.get<int32_t>(nnz);
   hipLaunchKernelGGL(k_elim_count, dim3(nblk(nnz)), dim3(kBlock), 0, c.st, rowidx, L.col, L.rp,
-                     L.cidx, nnz, cnt, ptflag);
-  int64_t* off = tmp.get<int64_t>(nnz + 1);
-  const int64_t m = scan_i32_to_i64(cnt, off, nnz, tmp, c.st, true);
-  uint64_t* keys = tmp.get<uint64_t>(m);
-  double* vals = tmp.get<double>(m);
+                     L.cidx, nnz, dcnt, fcnt, ptflag);
+  int64_t* offd = tmp.get<int64_t>(nnz + 1);
+  int64_t* offf = tmp.get<int64_t>(nnz + 1);
+  scan_i32_to_i64(dcnt, offd, nnz, tmp, c.st, false);
+  scan_i32_to_i64(fcnt, offf, nnz, tmp, c.st, false);
+  int64_t tot[2];
+  LG_HIP(hipMemcpyAsync(c.pair, offd + nnz, sizeof(int64_t), hipMemcpyDeviceToDevice, c.st));
+  LG_HIP(hipMemcpyAsync(c.pair + 1, offf + nnz, sizeof(int64_t), hipMemcpyDeviceToDevice, c.st));
+  read_dev(tot, c.pair, sizeof(tot), c.st);  // both totals, one synchronisation
+  const int64_t na = tot[0], nfill = tot[1], m = na + nfill;
+  uint64_t* dkeys = tmp.get<uint64_t>(na);
+  double* dvals = tmp.get<double>(na);
+  uint64_t* fkeys = tmp.get<uint64_t>(nfill);
+  double* fvals = tmp.get<double>(nfill);
   hipLaunchKernelGGL(k_elim_emit, dim3(nblk(nnz)), dim3(kBlock), 0, c.st, rowidx, L.rp, L.col, L.w,
-                     L.d, L.cidx, off, nnz, keys, vals);
+                     L.d, L.cidx, offd, offf, nnz, dkeys, dvals, fkeys, fvals);
   LG_LAUNCH_CHECK();
   const int b = bits_for(nc > 0 ? nc - 1 : 0);
-  radix_sort_pairs(keys, (uint64_t*)vals, m, digit_shifts(b, b), tmp, c.st);
+  radix_sort_pairs(fkeys, (uint64_t*)fvals, nfill, pair_shifts(b), tmp, c.st, b);
+  uint64_t* keys = tmp.get<uint64_t>(m);
+  double* vals = tmp.get<double>(m);
+  {
+    Arena::Mark mm = tmp.mark();
+    int32_t* flag = tmp.get<int32_t>(m);
+    int64_t* before = tmp.get<int64_t>(m + 1);
+    if (m > 0) {
+      hipLaunchKernelGGL(k_fill_i32, dim3(nblk(m)), dim3(kBlock), 0, c.st, flag, m, 0);
+      if (nfill > 0)
+        hipLaunchKernelGGL(k_merge_b, dim3(nblk(nfill)), dim3(kBlock), 0, c.st,
+                           (const uint64_t*)dkeys, na, (const uint64_t*)fkeys, (const double*)fvals,
+                           nfill, keys, vals, flag);
+      scan_i32_to_i64(flag, before, m, tmp, c.st, false);
+      hipLaunchKernelGGL(k_merge_a, dim3(nblk(m)), dim3(kBlock), 0, c.st, (const uint64_t*)dkeys,
+                         (const double*)dvals, (const int32_t*)flag, (const int64_t*)before, m, keys,
+                         vals);
+      LG_LAUNCH_CHECK();
+    }
+    tmp.rewind(mm);
+  }
   // transfer data: F-part of P^T
   int64_t* off2 = tmp.get<int64_t>(nnz + 1);
   const int64_t npt = scan_i32_to_i64(ptflag, off2, nnz, tmp, c.st, true);
@@ -1020,7 +1086,7 @@ void galerkin(Ctx& c, Level& L, int64_t nc, Level& out) {
   hipLaunchKernelGGL(k_gal_emit, dim3(nblk(nnz)), dim3(kBlock), 0, c.st, rowidx, L.col, L.w, L.agg,
                      flag, off, nnz, keys, vals);
   LG_LAUNCH_CHECK();
-  radix_sort_pairs(keys, (uint64_t*)vals, m, digit_shifts(b, b), tmp, c.st);
+  radix_sort_pairs(keys, (uint64_t*)vals, m, pair_shifts(b), tmp, c.st, b);
   assemble(c, keys, vals, m, nc, out);
 }
 
@@ -1046,8 +1112,9 @@ void lanczos(Ctx& c, Level& L, int level, double* out) {
   reduce_dev<RED_DDOT>(q, nullptr, L.d, n, part, lz + LZ_B2, c.st);
   hipLaunchKernelGGL(k_lz_scale, dim3(nblk(n)), dim3(kBlock), 0, c.st, q, n, lz);
   for (int j = 0; j < steps; j++) {
-    LapOp<double, 1, LAP_SPMV> op{L.col, L.w, L.d, L.dinv, q, u, nullptr, nullptr, 0.0, 0.0};
-    run_rows(L.sched, L.rp, op, c.st);
+    LapOp<double, 1, LAP_SPMV> op{L.col, L.w, L.d, L.dinv, q, u, nullptr, nullptr, 0.0, 0.0, 0.0};
+    // same kernel and bytes as the solve's fp64 product (family "spmv")
+    run_rows(L.sched, L.rp, op, c.st, "spmv", 4.0 * (n + 1) + 12.0 * L.nnz + 24.0 * n);
     reduce_dev<RED_DOT>(q, u, nullptr, n, part, lz + LZ_AL + j, c.st);
     hipLaunchKernelGGL(k_lz_update, dim3(nblk(n)), dim3(kBlock), 0, c.st, u, q, qp, L.d, n, lz, j);
     reduce_dev<RED_DDOT>(u, nullptr, L.d, n, part, lz + LZ_B2, c.st);
@@ -1113,6 +1180,7 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
   c.st = st;
   c.key = seed_key(o.seed);
   c.flags = h->mem.get<int>(4);
+  c.pair = h->mem.get<int64_t>(2);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, st, (int32_t*)c.flags, (int64_t)4, 0);
   const int64_t n = g->n, nnz = g->nnz;
   h->lev.emplace_back();

@@ -680,13 +680,15 @@ struct Engine {
   void lap(const Level& L, const T* x, T* y, const T* b, T* p, T c1, T c2, T c0, const char* fam,
            int vecs) {
     Vals<T> v = vals_of<T>(L);
-    ProfScope ps(fam, st,
-                 spmm_bytes(L, K, (int)sizeof(T), vecs) + (MODE >= LAP_CHEB ? (double)sizeof(T) * L.n : 0));
+    const double bytes =
+        spmm_bytes(L, K, (int)sizeof(T), vecs) + (MODE >= LAP_CHEB ? (double)sizeof(T) * L.n : 0);
     if constexpr (use_col_split<T, K>()) {
       run_rows_col(L.sched, L.rp,
-                   LapColOp<T, K, MODE>{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2, c0}, st);
+                   LapColOp<T, K, MODE>{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2, c0}, st, fam,
+                   bytes);
     } else {
-      run_rows(L.sched, L.rp, LapOp<T, K, MODE>{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2, c0}, st);
+      run_rows(L.sched, L.rp, LapOp<T, K, MODE>{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2, c0}, st,
+               fam, bytes);
     }
   }
 
@@ -743,11 +745,19 @@ struct Engine {
       hipLaunchKernelGGL((k_cheb_zero<T, K>), dim3(vec_blocks<T, K>(n)), dim3(kBlock), 0, st, b,
                          v.dinv, cur, n, (T)(1.0 / theta));
     } else if (smooth) {
-      // steps 0 and 1 in one pass; step 0's iterate is stored only if more follow
       double rho = 1.0 / sigma;
       double rho1 = 1.0 / (2.0 * sigma - rho);
-      lap<LAP_CHEB_ZERO>(L, b, cur, b, deg > 2 ? nxt : nullptr, (T)(rho1 * rho),
-                         (T)(2.0 * rho1 / delta), (T)(1.0 / theta), "cheb", deg > 2 ? 3 : 2);
+      if constexpr (use_col_split<T, K>()) {
+        // steps 0 and 1 in one pass; step 0's iterate is stored only if more follow
+        lap<LAP_CHEB_ZERO>(L, b, cur, b, deg > 2 ? nxt : nullptr, (T)(rho1 * rho),
+                           (T)(2.0 * rho1 / delta), (T)(1.0 / theta), "cheb0", deg > 2 ? 3 : 2);
+      } else {
+        // narrow rows: store step 0's iterate, then step 1 without a D^-1 gather
+        hipLaunchKernelGGL((k_cheb_zero<T, K>), dim3(vec_blocks<T, K>(n)), dim3(kBlock), 0, st, b,
+                           v.dinv, nxt, n, (T)(1.0 / theta));
+        lap<LAP_CHEB_X1>(L, nxt, cur, b, nullptr, (T)(rho1 * rho), (T)(2.0 * rho1 / delta), T(0),
+                         "cheb0", 3);
+      }
       rho = rho1;
       for (int s = 2; s < deg; s++) {
         rho1 = 1.0 / (2.0 * sigma - rho);
@@ -778,7 +788,7 @@ struct Engine {
     }
     if (smooth) {
       // nxt keeps the previous iterate, which each further step overwrites
-      lap<LAP_CHEB_FIRST>(L, cur, nxt, b, nullptr, T(0), (T)(1.0 / theta), T(0), "cheb", 3);
+      lap<LAP_CHEB_FIRST>(L, cur, nxt, b, nullptr, T(0), (T)(1.0 / theta), T(0), "cheb1", 3);
       std::swap(cur, nxt);
       double rho = 1.0 / sigma;
       for (int s = 1; s < deg; s++) {
@@ -843,29 +853,36 @@ struct Engine {
 };
 
 // fp64 Laplacian product on level l for K columns (outer Krylov method)
-template <int K>
+// fp64 Laplacian product on level l for K columns (outer Krylov method):
+// y = L x, or y = b - L x when b is set.  TAG 1 marks the lg_spmv entry
+// point's own kernel instances.
+template <int K, int TAG = 0>
 void lap64(lg_hierarchy* h, int l, const double* x, double* y, const double* b, hipStream_t st,
            const char* fam) {
   const Level& L = h->lev[l];
-  ProfScope ps(fam, st, spmm_bytes(L, K, 8, b ? 3 : 2));
+  const double bytes = spmm_bytes(L, K, 8, b ? 3 : 2);
   if constexpr (use_col_split<double, K>()) {
     if (b)
       run_rows_col(L.sched, L.rp,
-                   LapColOp<double, K, LAP_RESID>{L.col, L.w, L.d, L.dinv, x, y, b, nullptr, 0.0, 0.0},
-                   st);
+                   LapColOp<double, K, LAP_RESID, TAG>{L.col, L.w, L.d, L.dinv, x, y, b, nullptr,
+                                                       0.0, 0.0, 0.0},
+                   st, fam, bytes);
     else
       run_rows_col(L.sched, L.rp,
-                   LapColOp<double, K, LAP_SPMV>{L.col, L.w, L.d, L.dinv, x, y, nullptr, nullptr, 0.0,
-                                                 0.0},
-                   st);
+                   LapColOp<double, K, LAP_SPMV, TAG>{L.col, L.w, L.d, L.dinv, x, y, nullptr,
+                                                      nullptr, 0.0, 0.0, 0.0},
+                   st, fam, bytes);
   } else {
     if (b)
       run_rows(L.sched, L.rp,
-               LapOp<double, K, LAP_RESID>{L.col, L.w, L.d, L.dinv, x, y, b, nullptr, 0.0, 0.0}, st);
+               LapOp<double, K, LAP_RESID, TAG>{L.col, L.w, L.d, L.dinv, x, y, b, nullptr, 0.0, 0.0,
+                                                0.0},
+               st, fam, bytes);
     else
       run_rows(L.sched, L.rp,
-               LapOp<double, K, LAP_SPMV>{L.col, L.w, L.d, L.dinv, x, y, nullptr, nullptr, 0.0, 0.0},
-               st);
+               LapOp<double, K, LAP_SPMV, TAG>{L.col, L.w, L.d, L.dinv, x, y, nullptr, nullptr, 0.0,
+                                               0.0, 0.0},
+               st, fam, bytes);
   }
 }
 
@@ -977,7 +994,7 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     for (int c = 0; c < K; c++) work[c] += active[c] > 0.0 ? cw : 0.0;
   }
   for (int it = 1; it <= max_iter && any_active(); it++) {
-    lap64<K>(h, 0, h->pp, h->pq, nullptr, st, "spmm");
+    lap64<K>(h, 0, h->pp, h->pq, nullptr, st, "spmv");
     if (flex) dot64x2(h->pp, h->pq, h->pp, h->pr, S_PQ, S_PR);
     else dot64(h->pp, h->pq, S_PQ);
     hipLaunchKernelGGL((k_alpha<K>), dim3(1), dim3(64), 0, st, sc, flex ? 1 : 0);
@@ -1112,12 +1129,12 @@ void cycle_dispatch(lg_hierarchy* h, const double* B, double* X, int k, hipStrea
 
 void spmv_dispatch(lg_hierarchy* h, int level, const double* X, double* Y, int k, hipStream_t st) {
   switch (k) {
-    case 1: lap64<1>(h, level, X, Y, nullptr, st, "spmm"); break;
-    case 2: lap64<2>(h, level, X, Y, nullptr, st, "spmm"); break;
-    case 4: lap64<4>(h, level, X, Y, nullptr, st, "spmm"); break;
-    case 8: lap64<8>(h, level, X, Y, nullptr, st, "spmm"); break;
-    case 16: lap64<16>(h, level, X, Y, nullptr, st, "spmm"); break;
-    case 32: lap64<32>(h, level, X, Y, nullptr, st, "spmm"); break;
+    case 1: lap64<1, 1>(h, level, X, Y, nullptr, st, "spmm"); break;
+    case 2: lap64<2, 1>(h, level, X, Y, nullptr, st, "spmm"); break;
+    case 4: lap64<4, 1>(h, level, X, Y, nullptr, st, "spmm"); break;
+    case 8: lap64<8, 1>(h, level, X, Y, nullptr, st, "spmm"); break;
+    case 16: lap64<16, 1>(h, level, X, Y, nullptr, st, "spmm"); break;
+    case 32: lap64<32, 1>(h, level, X, Y, nullptr, st, "spmm"); break;
     default: fail(LG_E_ARG, "lg_spmv: k must be 1, 2, 4, 8, 16 or 32");
   }
   LG_LAUNCH_CHECK();
