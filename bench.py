@@ -307,6 +307,7 @@ def main():
         lat.append((time.perf_counter() - a) * 1e3)
     lat = np.array(lat)
     stats = lg.lg_hierarchy_stats(h)
+    hier_bytes = lg.lg_hierarchy_bytes(h)
 
     # fp64 SpMV bandwidth on the finest level (algorithmic bytes), lg_spmv's own kernels
     n0 = stats[0]["n"]
@@ -361,6 +362,8 @@ def main():
         "spmv_fp64_gbs": spmv_gbs,
         "spmv_fp64_ms": sp_ms / sp_n if sp_n else None,
         "spmv_fp64_rhs": kk,
+        "hierarchy_bytes": hier_bytes,
+        "levels": [(s["type"], s["n"], s["nnz"]) for s in stats],
     }
     if lat.size:
         out["solve_only"] = {"solves_per_s": wl["k"] * 1e3 / float(lat.mean()),
