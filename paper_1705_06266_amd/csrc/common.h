@@ -30,7 +30,19 @@ typedef __int128 s128;
 namespace lg {
 
 constexpr int kBlock = 256;
-constexpr int kHubChunk = 2048;
+#ifndef LG_HUB_CHUNK
+#define LG_HUB_CHUNK 2048
+#endif
+#ifndef LG_SPLIT_DEG
+#define LG_SPLIT_DEG 4096
+#endif
+#ifndef LG_HUB_DEG
+#define LG_HUB_DEG 1024
+#endif
+#ifndef LG_PER_LANE
+#define LG_PER_LANE 4
+#endif
+constexpr int kHubChunk = LG_HUB_CHUNK;
 constexpr uint64_t kGolden = 0x9e3779b97f4a7c15ULL;
 
 // ------------------------------------------------------------------ errors
@@ -167,7 +179,9 @@ __device__ __forceinline__ T shfl_xor_any(const T& v, int mask) {
 
 // ---------------------------------------------------------- row schedule
 // Rows are grouped by degree once per matrix (a stable counting sort):
-//   class c < 7: degree <= kPerLane * 2^c, processed by 2^c lanes;
+//   class c < 7: degree <= kPerLane * 2^c; one-column kernels give such a row
+//                class_lanes(c) = 2^(c-1) lanes (up to 2 kPerLane entries
+//                each), column-split kernels 2^(c-1) lane groups;
 //   class 7:     kPerLane * 64 < degree <= hub_deg, 64 lanes striding the row;
 //   hubs:        hub_deg < degree <= kSplitDeg, one 256-thread workgroup each,
 //                dispatched first in the same launch;
@@ -178,7 +192,7 @@ __device__ __forceinline__ T shfl_xor_any(const T& v, int mask) {
 // results do not depend on scheduling.
 constexpr int kClasses = 8;
 constexpr int kPartialBytes = 512;
-constexpr int kSplitDeg = 4096;  // rows above this are split into kHubChunk-entry chunks
+constexpr int kSplitDeg = LG_SPLIT_DEG;  // rows above this are split into kHubChunk-entry chunks
 
 struct ClassTable {
   int32_t cls_start[kClasses + 1];  // row ranges of each class in perm
@@ -187,7 +201,7 @@ struct ClassTable {
 
 struct Sched {
   int64_t n = 0, nnz = 0;
-  int hub_deg = 1024;
+  int hub_deg = LG_HUB_DEG;
   int min_deg = 0, max_deg = 0;
   int32_t* perm = nullptr;  // non-hub rows grouped by class
   ClassTable ct{};
@@ -200,8 +214,13 @@ struct Sched {
   void* partial = nullptr;         // [nchunk * kPartialBytes]
 };
 
-// Target entries per lane: a lane issues this many independent gathers.
-constexpr int kPerLane = 4;
+// Degree unit of the classes (entries per lane per step of a full-width row).
+constexpr int kPerLane = LG_PER_LANE;
+
+// Lanes of a one-column row kernel for class c (see above).
+__host__ __device__ constexpr int class_lanes(int c) {
+  return c == 0 ? 1 : c < kClasses - 1 ? (1 << (c - 1)) : 64;
+}
 
 // ------------------------------------------------- profiling (HIP events)
 // Times the launches between construction and destruction when family is
@@ -394,11 +413,12 @@ __global__ __launch_bounds__(kBlock) void k_rows(Op op, const int32_t* __restric
     const int64_t p0 = ct.cls_start[c], p1 = ct.cls_start[c + 1];
     switch (c) {
       case 0: rows_class<Op, 1>(op, rp, perm, p0, p1, lb); break;
-      case 1: rows_class<Op, 2>(op, rp, perm, p0, p1, lb); break;
-      case 2: rows_class<Op, 4>(op, rp, perm, p0, p1, lb); break;
-      case 3: rows_class<Op, 8>(op, rp, perm, p0, p1, lb); break;
-      case 4: rows_class<Op, 16>(op, rp, perm, p0, p1, lb); break;
-      case 5: rows_class<Op, 32>(op, rp, perm, p0, p1, lb); break;
+      case 1: rows_class<Op, 1>(op, rp, perm, p0, p1, lb); break;
+      case 2: rows_class<Op, 2>(op, rp, perm, p0, p1, lb); break;
+      case 3: rows_class<Op, 4>(op, rp, perm, p0, p1, lb); break;
+      case 4: rows_class<Op, 8>(op, rp, perm, p0, p1, lb); break;
+      case 5: rows_class<Op, 16>(op, rp, perm, p0, p1, lb); break;
+      case 6: rows_class<Op, 32>(op, rp, perm, p0, p1, lb); break;
       default: rows_class<Op, 64>(op, rp, perm, p0, p1, lb); break;
     }
   }

@@ -509,7 +509,7 @@ void build_sched(Sched& s, const int32_t* rp, int64_t n, int64_t nnz, Arena& kee
   s.n = n;
   s.nnz = nnz;
   if (n == 0) return;
-  s.hub_deg = 1024;
+  s.hub_deg = LG_HUB_DEG;
   Arena::Mark m = tmp.mark();
   const int64_t nb = ceil_div(n, kBlock);
   const int64_t nbs = ceil_div(n, (int64_t)kBlock * kStatRows);
@@ -529,7 +529,7 @@ void build_sched(Sched& s, const int32_t* rp, int64_t n, int64_t nnz, Arena& kee
   for (int c = 0; c < kClasses; c++) {
     s.ct.cls_start[c] = (int32_t)pos;
     s.ct.blk_start[c] = (int32_t)blk;
-    const int G = c < kClasses - 1 ? (1 << c) : 64;
+    const int G = class_lanes(c);
     pos += t[ST_CLS + c];
     blk += ceil_div((int64_t)t[ST_CLS + c] * G, kBlock);
   }
