@@ -186,6 +186,68 @@ const char* lg_profile_names(void);
 const char* lg_status_str(lg_status s);
 const char* lg_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Solve server: continuous batching over a pool of graphs.  Requests (graph,
+ * right-hand sides, tolerance) may arrive at any time from any thread.  Worker
+ * threads, each with its own HIP stream, take the oldest request whose graph
+ * is idle together with every queued request for the same graph, tolerance
+ * and iteration cap (up to max_batch_rhs columns) and run them as one
+ * batched lg_solve; batches of different graphs overlap on the device.  A
+ * graph's hierarchy is built on its first request and cached; it is admitted
+ * when it fits hbm_budget after freeing the least recently used idle
+ * hierarchies (a hierarchy larger than the budget runs alone).  Each column
+ * is solved exactly as by lg_solve on a hierarchy built with
+ * max_rhs = max_batch_rhs, whatever else shares its batch.
+ * ------------------------------------------------------------------------ */
+typedef struct lg_server lg_server;
+
+typedef struct {
+  int32_t workers;        /* worker threads / HIP streams, 1..64 (default 4) */
+  int32_t max_batch_rhs;  /* columns per batched solve, 1..32 (default 32) */
+  size_t hbm_budget;      /* bytes of cached hierarchies; 0 = 3/4 of free device memory */
+  lg_setup_opts setup;    /* options of every hierarchy (max_rhs is taken from max_batch_rhs) */
+} lg_server_opts;
+
+typedef struct {
+  int64_t submitted, completed; /* requests */
+  int64_t batches;              /* batched solves run */
+  int64_t batched_columns;      /* right-hand sides solved in them */
+  int64_t setups, evictions;    /* hierarchies built and freed for room */
+  size_t resident_bytes;        /* device bytes of the cached hierarchies */
+  size_t budget_bytes;          /* the admission budget in effect */
+  int32_t resident_graphs;
+} lg_server_stats;
+
+/* Fill o with the defaults (4 workers, 32 columns, budget from free memory,
+ * the paper's setup parameters). */
+lg_status lg_server_default_opts(lg_server_opts* o);
+
+/* Start a server on the current HIP device (o may be NULL for defaults). */
+lg_status lg_server_create(const lg_server_opts* o, lg_server** out);
+
+/* Register a graph (lg_graph as for lg_setup, host or device arrays, copied
+ * to host memory during the call); *graph_id identifies it in submits.
+ * Invalid or disconnected graphs are reported by the requests on them. */
+lg_status lg_server_add_graph(lg_server* s, const lg_graph* g, int32_t* graph_id);
+
+/* Queue a solve of L X = B - mean(B) for k columns (1..max_batch_rhs).  B and
+ * X are device n x k row-major fp64 arrays owned by the caller: B must hold
+ * its values when this is called, and both must stay valid until
+ * lg_server_wait returns for *request_id.  Never blocks on the solve. */
+lg_status lg_server_submit(lg_server* s, int32_t graph_id, const double* B, double* X, int32_t k,
+                           double rtol, int32_t max_iter, int64_t* request_id);
+
+/* Block until the request is done; fills info (host, k entries, may be NULL)
+ * and *latency_ms (submit to completion, may be NULL), forgets the request
+ * and returns its status (LG_OK, LG_E_NOT_CONVERGED, or the setup error of
+ * its graph).  Each request is waited for once. */
+lg_status lg_server_wait(lg_server* s, int64_t request_id, lg_rhs_info* info, double* latency_ms);
+
+lg_status lg_server_stats_get(lg_server* s, lg_server_stats* out);
+
+/* Finish all queued requests, stop the workers and free every hierarchy. */
+void lg_server_free(lg_server* s);
+
 #ifdef __cplusplus
 }
 #endif

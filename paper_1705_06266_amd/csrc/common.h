@@ -19,6 +19,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -431,15 +432,17 @@ __global__ __launch_bounds__(kBlock) void k_rows(Op op, const int32_t* __restric
 // per kernel.
 template <typename KernelT>
 inline int64_t resident_grid(KernelT kernel) {
-  static int64_t cached = 0;
-  if (cached == 0) {
+  static std::atomic<int64_t> cached{0};  // threads that race compute the same value
+  int64_t v = cached.load(std::memory_order_relaxed);
+  if (v == 0) {
     int per_cu = 0, dev = 0, cus = 0;
     LG_HIP(hipGetDevice(&dev));
     LG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     LG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0));
-    cached = std::max<int64_t>(1, (int64_t)per_cu * cus);
+    v = std::max<int64_t>(1, (int64_t)per_cu * cus);
+    cached.store(v, std::memory_order_relaxed);
   }
-  return cached;
+  return v;
 }
 
 // fam/bytes: the kernel-timing family and algorithmic bytes of this product;

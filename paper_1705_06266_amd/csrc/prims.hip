@@ -2,6 +2,7 @@
 // a stable LSD radix sort of (key, payload) pairs, the row scheduler, the
 // device arena and the HIP-event profiler behind lg_profile_*.
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -76,6 +77,7 @@ void release_temp_arena(Arena* a) {
 namespace {
 struct Prof {
   std::mutex mu;
+  std::atomic<bool> enabled{false};  // checked without the lock on every launch
   std::string family;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
   std::vector<double> pending_bytes;
@@ -102,8 +104,9 @@ hipEvent_t take_event(Prof& p) {
 ProfScope::ProfScope(const char* family, hipStream_t s, double b, bool att)
     : on(false), attached(att), st(s), bytes(b) {
   Prof& p = prof();
-  if (p.family.empty() || p.family != family) return;
+  if (!p.enabled.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> g(p.mu);
+  if (p.family.empty() || p.family != family) return;
   a = take_event(p);
   this->b = take_event(p);
   if (!attached) LG_HIP(hipEventRecord(a, st));
@@ -125,6 +128,7 @@ extern "C" lg_status lg_profile_enable(const char* family) {
   auto& p = lg::prof();
   std::lock_guard<std::mutex> g(p.mu);
   p.family = family ? family : "";
+  p.enabled.store(!p.family.empty());
   p.launches = 0;
   p.ms = p.bytes = 0.0;
   return LG_OK;

@@ -601,6 +601,14 @@ __global__ void k_xpby_z(double* __restrict__ p, const T* __restrict__ z,
   }
 }
 
+// dst = src in the columns whose flag is set (columns never influence each other)
+template <int K>
+__global__ void k_copy_flagged(double* __restrict__ dst, const double* __restrict__ src,
+                               const double* __restrict__ flag, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < m && flag[i % K] > 0.0) dst[i] = src[i];
+}
+
 // ---- inner FCG(2) scalars of the K-cycle: [d1 a1 alpha1 zq d2 a2] x K
 template <int K>
 __global__ void k_fcg_alpha1(double* __restrict__ ks) {
@@ -1036,9 +1044,10 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
       write_slot(S_TR, zero);
     }
     if (!any_active()) break;
-    if (restart) {  // continue from the true residual with a fresh direction
-      LG_HIP(hipMemcpyAsync(h->pr, h->pt, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    if (restart) {  // those columns continue from the true residual with a fresh direction
       write_slot(S_RESTART, rflag);
+      hipLaunchKernelGGL((k_copy_flagged<K>), dim3(g), dim3(kBlock), 0, st, h->pr,
+                         (const double*)h->pt, (const double*)sl(S_RESTART), m);
     }
     const T* z = eng.precond(h->pr, !restart);
     for (int c = 0; c < K; c++) work[c] += active[c] > 0.0 ? cw : 0.0;

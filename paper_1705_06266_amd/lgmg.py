@@ -27,6 +27,8 @@ EXPORTS = [
     "lg_export_level", "lg_export_setup_data", "lg_export_coarsest", "lg_hierarchy_bytes",
     "lg_setup_ms", "lg_free", "lg_profile_enable", "lg_profile_read", "lg_profile_names",
     "lg_status_str", "lg_last_error",
+    "lg_server_default_opts", "lg_server_create", "lg_server_add_graph", "lg_server_submit",
+    "lg_server_wait", "lg_server_stats_get", "lg_server_free",
 ]
 
 
@@ -56,6 +58,18 @@ class lg_level_stats(C.Structure):
 class lg_rhs_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("rel_residual", C.c_double), ("work_units", C.c_double),
                 ("wda", C.c_double)]
+
+
+class lg_server_opts(C.Structure):
+    _fields_ = [("workers", C.c_int32), ("max_batch_rhs", C.c_int32), ("hbm_budget", C.c_size_t),
+                ("setup", lg_setup_opts)]
+
+
+class lg_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
+                ("batched_columns", C.c_int64), ("setups", C.c_int64), ("evictions", C.c_int64),
+                ("resident_bytes", C.c_size_t), ("budget_bytes", C.c_size_t),
+                ("resident_graphs", C.c_int32)]
 
 
 class LgError(RuntimeError):
@@ -94,6 +108,13 @@ def load():
         "lg_profile_names": (C.c_char_p, []),
         "lg_status_str": (C.c_char_p, [_I32]),
         "lg_last_error": (C.c_char_p, []),
+        "lg_server_default_opts": (_I32, [_P]),
+        "lg_server_create": (_I32, [_P, C.POINTER(_P)]),
+        "lg_server_add_graph": (_I32, [_P, _P, _P]),
+        "lg_server_submit": (_I32, [_P, _I32, _P, _P, _I32, _D, _I32, _P]),
+        "lg_server_wait": (_I32, [_P, _I64, _P, _P]),
+        "lg_server_stats_get": (_I32, [_P, _P]),
+        "lg_server_free": (None, [_P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -293,3 +314,86 @@ def lg_profile_read():
 
 def lg_profile_names():
     return load().lg_profile_names().decode().split(",")
+
+
+# --------------------------------------------------------------- solve server
+class Server:
+    """Continuous-batching solve server (lg_server_*).  Keeps the caller's
+    tensors of every request alive until the request has been waited for."""
+
+    def __init__(self, workers=4, max_batch_rhs=32, hbm_budget=0, **setup_overrides):
+        o = lg_server_opts()
+        _check(load().lg_server_default_opts(C.byref(o)), "lg_server_default_opts")
+        o.workers, o.max_batch_rhs, o.hbm_budget = workers, max_batch_rhs, hbm_budget
+        for k, v in setup_overrides.items():
+            setattr(o.setup, k, v)
+        self.opts = o
+        h = C.c_void_p()
+        _check(load().lg_server_create(C.byref(o), C.byref(h)), "lg_server_create")
+        self.handle = h
+        self._live = {}
+        self._n = {}
+
+    def add_graph(self, row_ptr, col, w):
+        """Register a graph (host numpy or device torch arrays); returns its id."""
+        on_device = not isinstance(row_ptr, np.ndarray)
+        if not on_device:
+            row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            w = np.ascontiguousarray(w, dtype=np.float64)
+            n, nnz = row_ptr.shape[0] - 1, col.shape[0]
+        else:
+            n, nnz = row_ptr.numel() - 1, col.numel()
+        g = lg_graph(n, nnz, _ptr(row_ptr), _ptr(col), _ptr(w), 1 if on_device else 0)
+        gid = C.c_int32()
+        _check(load().lg_server_add_graph(self.handle, C.byref(g), C.byref(gid)), "lg_server_add_graph")
+        self._n[gid.value] = n
+        return gid.value
+
+    def submit(self, graph_id, B, X=None, rtol=1e-8, max_iter=500):
+        """Queue a solve for device float64 B of shape (n, k); returns a request id.
+        B's values must be final (synchronise its stream first)."""
+        import torch
+
+        if B.dim() == 1:
+            B = B.unsqueeze(1)
+        B = B.contiguous()
+        if X is None:
+            X = torch.empty_like(B)
+        rid = C.c_int64()
+        _check(load().lg_server_submit(self.handle, graph_id, _ptr(B), _ptr(X), B.shape[1], rtol,
+                                       max_iter, C.byref(rid)), "lg_server_submit")
+        self._live[rid.value] = (B, X)
+        return rid.value
+
+    def wait(self, request_id, allow_unconverged=False):
+        """Block until the request is done: (X, infos, status, latency_ms)."""
+        B, X = self._live[request_id]
+        info = (lg_rhs_info * B.shape[1])()
+        lat = C.c_double()
+        ok = (LG_OK, LG_E_NOT_CONVERGED) if allow_unconverged else (LG_OK,)
+        try:
+            st = _check(load().lg_server_wait(self.handle, request_id, info, C.byref(lat)),
+                        "lg_server_wait", ok)
+        finally:
+            del self._live[request_id]
+        infos = [dict(iters=i.iters, rel_residual=i.rel_residual, work_units=i.work_units,
+                      wda=i.wda) for i in info]
+        return X, infos, st, lat.value
+
+    def stats(self):
+        st = lg_server_stats()
+        _check(load().lg_server_stats_get(self.handle, C.byref(st)), "lg_server_stats_get")
+        return {f: getattr(st, f) for f, _ in lg_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().lg_server_free(self.handle)
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -38,15 +38,18 @@ def test_struct_layouts_match_the_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "lgmg.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(lg_setup_opts),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(lg_setup_opts),"
         " offsetof(lg_setup_opts, seed), offsetof(lg_setup_opts, validate), sizeof(lg_graph),"
-        " sizeof(lg_level_stats), sizeof(lg_rhs_info)); return 0;}\n")
+        " sizeof(lg_level_stats), sizeof(lg_rhs_info), sizeof(lg_server_opts),"
+        " offsetof(lg_server_opts, setup), sizeof(lg_server_stats),"
+        " offsetof(lg_server_stats, resident_graphs)); return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(lg.lg_setup_opts), lg.lg_setup_opts.seed.offset,
             lg.lg_setup_opts.validate.offset, C.sizeof(lg.lg_graph), C.sizeof(lg.lg_level_stats),
-            C.sizeof(lg.lg_rhs_info)]
+            C.sizeof(lg.lg_rhs_info), C.sizeof(lg.lg_server_opts), lg.lg_server_opts.setup.offset,
+            C.sizeof(lg.lg_server_stats), lg.lg_server_stats.resident_graphs.offset]
     assert got == want
 
 
@@ -75,3 +78,13 @@ def test_argument_errors_need_no_device():
     assert lib.lg_solve(None, None, None, 1, 1e-8, 10, None, None) == lg.LG_E_ARG
     assert lg.status_str(lg.LG_E_DISCONNECTED) == "graph not connected"
     lib.lg_free(None)
+    so = lg.lg_server_opts()
+    assert lib.lg_server_default_opts(C.byref(so)) == lg.LG_OK
+    assert (so.workers, so.max_batch_rhs, so.hbm_budget) == (4, 32, 0)
+    assert so.setup.agg_iters == 10
+    so.max_batch_rhs = 33
+    srv = C.c_void_p()
+    assert lib.lg_server_create(C.byref(so), C.byref(srv)) == lg.LG_E_ARG
+    assert "max_batch_rhs" in lg.lg_last_error()
+    assert lib.lg_server_submit(None, 0, None, None, 1, 1e-8, 10, None) == lg.LG_E_ARG
+    lib.lg_server_free(None)

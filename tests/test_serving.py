@@ -1,0 +1,120 @@
+"""The continuous-batching solve server (lg_server_*): every request's result
+is the same alone and in the mix, hierarchies are admitted by the HBM budget,
+and a bad graph fails only its own requests.  All calls go through the C ABI.
+"""
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import paper_1705_06266_amd.lgmg as lg
+from gpu_util import dense_laplacian_norm, laplacian_apply, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+POOL = [
+    lambda: gg.grid2d(40, 40),
+    lambda: gg.rmat(11, 16, seed=5),
+    lambda: gg.chung_lu(5000, seed=8, max_deg=800),
+    lambda: gg.grid3d(10, 10, 10, weights="loguniform", seed=9),
+    lambda: gg.path(600),
+    lambda: gg.gnp(800, 0.01, seed=10),
+]
+
+
+def _requests(graphs, count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        gid = i % len(graphs)
+        k = int(rng.integers(1, 9))
+        out.append((gid, gg.rhs(graphs[gid].n, k, 100 + i)))
+    return out
+
+
+def _alone(graphs, max_batch_rhs):
+    """One hierarchy per graph built like the server's (max_rhs = max_batch_rhs)."""
+    return [lg.lg_setup(g.row_ptr, g.col, g.w, lg.lg_default_opts(max_rhs=max_batch_rhs))
+            for g in graphs]
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    import torch
+
+    assert torch.cuda.is_available()
+    return [mk() for mk in POOL]
+
+
+def test_results_are_the_same_alone_and_in_the_mix(graphs):
+    import torch
+
+    reqs = _requests(graphs, 36, 1)
+    srv = lg.Server(workers=3, max_batch_rhs=32)
+    gids = [srv.add_graph(g.row_ptr, g.col, g.w) for g in graphs]
+    dev = [to_dev(b) for _, b in reqs]
+    torch.cuda.synchronize()  # inputs final before the server's streams read them
+    ids = [srv.submit(gids[gid], B) for (gid, _), B in zip(reqs, dev)]
+    results = [srv.wait(i) for i in ids]
+    st = srv.stats()
+    say(f"  server stats {st}")
+    srv.close()
+    assert st["completed"] == len(reqs) and st["setups"] == len(graphs)
+    assert st["batches"] < len(reqs), "requests on one graph should share batches"
+    alone = _alone(graphs, 32)
+    for (gid, b), (X, infos, status, lat) in zip(reqs, results):
+        g = graphs[gid]
+        Xa, infa, sta = lg.lg_solve(alone[gid], to_dev(b))
+        X = X.cpu().numpy()
+        Xa = Xa.cpu().numpy()
+        assert status == lg.LG_OK and sta == lg.LG_OK and lat > 0.0
+        # columns never influence each other: bit-identical to the solo solve
+        assert np.array_equal(X, Xa), (gid, np.abs(X - Xa).max())
+        assert [i["iters"] for i in infos] == [i["iters"] for i in infa]
+        for c in range(b.shape[1]):
+            bp = b[:, c] - b[:, c].mean()
+            rel = np.linalg.norm(bp - laplacian_apply(g, X[:, c])) / np.linalg.norm(bp)
+            assert rel <= 1e-8 * 1.001
+
+
+def test_admission_by_budget_evicts_idle_hierarchies(graphs):
+    import torch
+
+    reqs = _requests(graphs, 18, 2)
+    srv = lg.Server(workers=2, max_batch_rhs=8, hbm_budget=1)  # no two hierarchies fit
+    gids = [srv.add_graph(g.row_ptr, g.col, g.w) for g in graphs]
+    dev = [to_dev(b) for _, b in reqs]
+    torch.cuda.synchronize()  # inputs final before the server's streams read them
+    ids = [srv.submit(gids[gid], B) for (gid, _), B in zip(reqs, dev)]
+    results = [srv.wait(i) for i in ids]
+    st = srv.stats()
+    say(f"  server stats {st}")
+    srv.close()
+    assert st["evictions"] > 0 and st["resident_graphs"] <= 1
+    alone = _alone(graphs, 8)
+    for (gid, b), (X, infos, status, lat) in zip(reqs, results):
+        Xa, _, _ = lg.lg_solve(alone[gid], to_dev(b))
+        assert status == lg.LG_OK
+        assert np.array_equal(X.cpu().numpy(), Xa.cpu().numpy())
+
+
+def test_a_bad_graph_fails_only_its_requests(graphs):
+    import torch
+
+    two = gg.from_edges(6, [0, 1, 3, 4], [1, 2, 4, 5])  # two components
+    srv = lg.Server(workers=2, max_batch_rhs=4)
+    good = srv.add_graph(graphs[0].row_ptr, graphs[0].col, graphs[0].w)
+    bad = srv.add_graph(two.row_ptr, two.col, two.w)
+    Bb, Bg = to_dev(gg.rhs(two.n, 2, 1)), to_dev(gg.rhs(graphs[0].n, 3, 2))
+    torch.cuda.synchronize()
+    rb = srv.submit(bad, Bb)
+    rg = srv.submit(good, Bg)
+    with pytest.raises(lg.LgError) as e:
+        srv.wait(rb)
+    assert e.value.code == lg.LG_E_DISCONNECTED
+    X, infos, status, lat = srv.wait(rg)
+    assert status == lg.LG_OK and all(i["rel_residual"] <= 1e-8 for i in infos)
+    with pytest.raises(lg.LgError) as e:
+        srv.submit(good, to_dev(gg.rhs(graphs[0].n, 5, 3)))  # more than max_batch_rhs
+    assert e.value.code == lg.LG_E_ARG
+    srv.close()
