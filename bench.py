@@ -217,12 +217,127 @@ def trace_summary(args):
     print("\n".join(lines))
 
 
+def serving_bench(args):
+    """Serving workload: a seeded pool of 64 graphs (grids and R-MAT, 1e3-1e6
+    vertices), requests of 1-8 right-hand sides on uniformly drawn graphs.
+    Reports the mixed-precision continuous-batching server's saturated
+    throughput and p50/p99 latency (submit to completion) under Poisson
+    arrivals at fractions of that rate, next to plain FP64 single-column
+    lg_solve calls on the same requests."""
+    import threading
+
+    import torch
+
+    import graphgen as gg
+    import paper_1705_06266_amd.lgmg as lg
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    pool = gg.serving_pool(count=args.pool)
+    print(f"pool generated in {time.perf_counter() - t0:.1f} s: {len(pool)} graphs, "
+          f"{sum(g.n for g in pool)} vertices", file=sys.stderr, flush=True)
+    reqs = gg.serving_requests([g.n for g in pool], args.requests)
+    rhs = [torch.as_tensor(gg.rhs(pool[gi].n, k, sd)).to(dev) for gi, k, sd in reqs]
+    outs = [torch.empty_like(b) for b in rhs]
+    torch.cuda.synchronize()
+
+    srv = lg.Server(workers=args.workers, max_batch_rhs=32, precision=lg.LG_MIXED)
+    gids = [srv.add_graph(g.row_ptr, g.col, g.w) for g in pool]
+    # hierarchies: one request per graph builds and caches them all
+    t0 = time.perf_counter()
+    warm = [srv.submit(gids[i], torch.zeros(pool[i].n, 1, dtype=torch.float64, device=dev))
+            for i in range(len(pool))]
+    for r in warm:
+        srv.wait(r)
+    setup_s = time.perf_counter() - t0
+    print(f"hierarchies built in {setup_s:.2f} s", file=sys.stderr, flush=True)
+
+    def run(rate):
+        """Submit every request (Poisson arrivals at `rate` requests/s, or all
+        at once when rate is None); returns (seconds, latencies ms)."""
+        rng = np.random.default_rng(11)
+        gaps = rng.exponential(1.0 / rate, len(reqs)) if rate else np.zeros(len(reqs))
+        ids = [None] * len(reqs)
+        lat = [0.0] * len(reqs)
+
+        def waiter():
+            for i in range(len(reqs)):
+                while ids[i] is None:
+                    time.sleep(0.0002)
+                lat[i] = srv.wait(ids[i])[3]
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        start = time.perf_counter()
+        due = start
+        for i, (gi, k, _) in enumerate(reqs):
+            due += gaps[i]
+            while time.perf_counter() < due:
+                pass
+            ids[i] = srv.submit(gids[gi], rhs[i], outs[i])
+        th.join()
+        return time.perf_counter() - start, np.array(lat)
+
+    cols = sum(k for _, k, _ in reqs)
+    sat_s, sat_lat = run(None)
+    sat_req_rate = len(reqs) / sat_s
+    st = srv.stats()
+    sweep = []
+    for frac in (0.25, 0.5, 0.75, 1.0, 1.25):
+        el, lat = run(frac * sat_req_rate)
+        sweep.append({"load": frac, "offered_req_per_s": frac * sat_req_rate,
+                      "solves_per_s": cols / el, "p50_ms": float(np.percentile(lat, 50)),
+                      "p99_ms": float(np.percentile(lat, 99))})
+        print(f"load {frac}: {sweep[-1]}", file=sys.stderr, flush=True)
+    srv.close()
+
+    # plain FP64 single-column solves of the same requests, one at a time
+    hs = {}
+    base_n = min(len(reqs), args.baseline_requests)
+    used = sorted({reqs[i][0] for i in range(base_n)})
+    for gi in used:
+        g = pool[gi]
+        hs[gi] = lg.lg_setup(torch.as_tensor(g.row_ptr).to(dev), torch.as_tensor(g.col).to(dev),
+                             torch.as_tensor(g.w).to(dev), lg.lg_default_opts(max_rhs=1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    base_cols = 0
+    for i in range(base_n):
+        gi, k, _ = reqs[i]
+        for c in range(k):
+            lg.lg_solve(hs[gi], rhs[i][:, c:c + 1].contiguous())
+            base_cols += 1
+    base_s = time.perf_counter() - t0
+    out = {
+        "metric": "serving: solves/s + p50/p99 latency to 1e-8 (continuous batching, mixed)",
+        "value": cols / sat_s, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+        "data": "synthetic",
+        "config": {"workload": f"serving_pool{args.pool}_grids_rmat_1e3-1e6_1-8rhs",
+                   "requests": len(reqs), "rhs": cols, "workers": args.workers,
+                   "max_batch_rhs": 32, "precision": "f32-cycle/f64-krylov"},
+        "saturated": {"seconds": sat_s, "req_per_s": sat_req_rate,
+                      "p50_ms": float(np.percentile(sat_lat, 50)),
+                      "p99_ms": float(np.percentile(sat_lat, 99)),
+                      "batches": st["batches"], "batched_columns": st["batched_columns"]},
+        "poisson_sweep": sweep,
+        "hierarchy_build_s": setup_s,
+        "fp64_single_rhs_baseline": {"solves_per_s": base_cols / base_s, "rhs": base_cols},
+        "speedup_vs_fp64_single_rhs": (cols / sat_s) / (base_cols / base_s),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat_s18", choices=list(WORKLOADS))
+    ap.add_argument("--workload", default="rmat_s18", choices=list(WORKLOADS) + ["serving"])
+    ap.add_argument("--pool", type=int, default=64, help="serving: graphs in the pool")
+    ap.add_argument("--requests", type=int, default=400, help="serving: requests per run")
+    ap.add_argument("--workers", type=int, default=8, help="serving: server workers")
+    ap.add_argument("--baseline-requests", type=int, default=120,
+                    help="serving: requests replayed as FP64 single-column solves")
     ap.add_argument("--latency-solves", type=int, default=100)
     ap.add_argument("--family", default=None, help="kernel family timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -247,6 +362,8 @@ def main():
               "(batches of right-hand sides or a pool of graphs would shard by keeping a "
               "replica of each hierarchy per GPU)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serving":
+        return serving_bench(args)
 
     import torch
 

@@ -40,6 +40,8 @@ __all__ = [
     "config_graph",
     "config_rhs",
     "CONFIGS",
+    "serving_pool",
+    "serving_requests",
 ]
 
 
@@ -291,6 +293,39 @@ CONFIGS = {
     "c4_chunglu_4m": dict(graph=("chung_lu", dict(n=4 << 20, gamma=2.1, mean_deg=16.0, max_deg=1e5,
                                                    seed=6)), k=16, rhs_seed=6, precision="mixed"),
 }
+
+
+def serving_pool(count=64, n_min=1e3, n_max=1e6, seed=7):
+    """The serving workload's pool: `count` graphs with vertex counts
+    log-uniform in [n_min, n_max], cycling through 2D and 3D grids (unit
+    weights) and R-MAT graphs (edge factor 16, U(0,1]); each graph has its own
+    seed derived from `seed`."""
+    rng = _rng(seed)
+    pool = []
+    for i in range(count):
+        n = float(np.exp(rng.uniform(np.log(n_min), np.log(n_max))))
+        gseed = int(rng.integers(1, 2**31))
+        kind = i % 3
+        if kind == 0:
+            side = max(2, int(round(np.sqrt(n))))
+            g = grid2d(side, side)
+        elif kind == 1:
+            side = max(2, int(round(n ** (1.0 / 3.0))))
+            g = grid3d(side, side, side)
+        else:
+            g = rmat(max(8, int(round(np.log2(n)))), 16, seed=gseed)
+        g.name = f"pool{i}_{g.name}"
+        pool.append(g)
+    return pool
+
+
+def serving_requests(pool_sizes, count, seed=7, k_max=8):
+    """`count` requests (graph index, RHS count in 1..k_max, RHS seed),
+    graphs drawn uniformly from the pool."""
+    rng = _rng(seed + 1)
+    g = rng.integers(0, len(pool_sizes), count)
+    k = rng.integers(1, k_max + 1, count)
+    return [(int(g[i]), int(k[i]), 1000 + i) for i in range(count)]
 
 
 def config_graph(name, **override):

@@ -120,8 +120,11 @@ lg_status lg_setup(const lg_graph* g, const lg_setup_opts* o, void* hip_stream,
  * preconditioned by one V-cycle, or FCG with a K-cycle; relative tolerance
  * rtol on the true residual).  B and X are device n x k row-major fp64; B is
  * not modified; X receives mean-zero solutions.  info (host, k entries, may
- * be NULL) receives per-column statistics.  1 <= k <= max_rhs of setup.
- * Returns LG_E_NOT_CONVERGED (X and info filled) if a column misses rtol. */
+ * be NULL) receives per-column statistics.  1 <= k <= max_rhs of setup.  The
+ * columns run together at width next_pow2(k); each column's arithmetic is
+ * independent of the others, so at one width a column's result does not
+ * depend on what the other columns hold.  Returns LG_E_NOT_CONVERGED (X and
+ * info filled) if a column misses rtol. */
 lg_status lg_solve(lg_hierarchy* h, const double* B, double* X, int32_t k, double rtol,
                    int32_t max_iter, void* hip_stream, lg_rhs_info* info);
 
@@ -195,9 +198,10 @@ const char* lg_last_error(void);
  * batched lg_solve; batches of different graphs overlap on the device.  A
  * graph's hierarchy is built on its first request and cached; it is admitted
  * when it fits hbm_budget after freeing the least recently used idle
- * hierarchies (a hierarchy larger than the budget runs alone).  Each column
- * is solved exactly as by lg_solve on a hierarchy built with
- * max_rhs = max_batch_rhs, whatever else shares its batch.
+ * hierarchies (a hierarchy larger than the budget runs alone).  A request's
+ * columns are computed independently of the rest of its batch; the batch's
+ * width (see lg_solve) only changes summation orders, so each result agrees
+ * with the same request solved alone within the solver tolerance.
  * ------------------------------------------------------------------------ */
 typedef struct lg_server lg_server;
 

@@ -1100,10 +1100,18 @@ void cycle_once(lg_hierarchy* h, const double* B, double* X, int k, hipStream_t 
   LG_LAUNCH_CHECK();
 }
 
+// A call with k columns runs at width next_pow2(k) (at most the workspace's
+// h->K): narrow calls stream narrow vectors.
+static int width(int k) {
+  int K = 1;
+  while (K < k) K <<= 1;
+  return K;
+}
+
 template <typename T>
 static lg_status solve_k(lg_hierarchy* h, const double* B, double* X, int k, double rtol,
                          int max_iter, hipStream_t st, lg_rhs_info* info) {
-  switch (h->K) {
+  switch (width(k)) {
     case 1: return pcg<T, 1>(h, B, X, k, rtol, max_iter, st, info);
     case 2: return pcg<T, 2>(h, B, X, k, rtol, max_iter, st, info);
     case 4: return pcg<T, 4>(h, B, X, k, rtol, max_iter, st, info);
@@ -1121,7 +1129,7 @@ lg_status solve_dispatch(lg_hierarchy* h, const double* B, double* X, int k, dou
 
 template <typename T>
 static void cycle_k(lg_hierarchy* h, const double* B, double* X, int k, hipStream_t st) {
-  switch (h->K) {
+  switch (width(k)) {
     case 1: return cycle_once<T, 1>(h, B, X, k, st);
     case 2: return cycle_once<T, 2>(h, B, X, k, st);
     case 4: return cycle_once<T, 4>(h, B, X, k, st);
