@@ -348,6 +348,8 @@ def main():
                          "traffic summary and exit (no GPU)")
     ap.add_argument("--trace-summary", default=None,
                     help="directory of a rocprofv3 --stats csv run: write the summary and exit")
+    ap.add_argument("--graphs", type=int, default=None, choices=[0, 1],
+                    help="replay the cycle as a captured HIP graph (default: the library's)")
     ap.add_argument("--command", default="", help="command line recorded in summaries")
     ap.add_argument("--bench-log", default=None, help="bench output of the profiled run (summaries)")
     args = ap.parse_args()
@@ -381,6 +383,8 @@ def main():
     B = torch.as_tensor(b_host).to(dev)
     opts = lg.lg_default_opts(max_rhs=wl["k"],
                               precision=lg.LG_MIXED if wl["precision"] == "mixed" else lg.LG_FP64)
+    if args.graphs is not None:
+        opts.graphs = args.graphs
     torch.cuda.synchronize()
 
     def step():

@@ -83,6 +83,7 @@ typedef struct {
   int32_t max_rhs;          /* largest k passed to lg_solve (1..32); sizes the solve workspace */
   int32_t keep_setup_data;  /* 1: keep strengths, test vectors, votes and elimination choices for export */
   int32_t validate;         /* 1: check symmetry, weights and connectivity on the device */
+  int32_t graphs;           /* 1: after its first use, replay the cycle as a captured HIP graph */
 } lg_setup_opts;
 
 typedef struct lg_hierarchy lg_hierarchy;

@@ -55,6 +55,7 @@ extern "C" lg_status lg_default_opts(lg_setup_opts* o) {
   o->max_rhs = 1;
   o->keep_setup_data = 0;
   o->validate = 1;
+  o->graphs = 1;
   return LG_OK;
 }
 
@@ -70,6 +71,7 @@ static const char* check_opts(const lg_setup_opts& o) {
   if (o.hash_mode != 0 && o.hash_mode != 1) return "hash_mode must be 0 or 1";
   if (o.max_levels < 1) return "max_levels must be >= 1";
   if (o.elim_max_degree < 0) return "elim_max_degree must be >= 0";
+  if (o.graphs != 0 && o.graphs != 1) return "graphs must be 0 or 1";
   return nullptr;
 }
 

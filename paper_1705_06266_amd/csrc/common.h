@@ -229,6 +229,8 @@ __host__ __device__ constexpr int class_lanes(int c) {
 // which takes start() and stop() as the events of its own dispatch
 // (hipExtLaunchKernelGGL), so the time is the kernel's alone; otherwise the
 // events are recorded on the stream around the enclosed work.
+bool prof_active();  // true while a kernel family is being timed
+
 struct ProfScope {
   ProfScope(const char* family, hipStream_t st, double bytes, bool attached = false);
   ~ProfScope();

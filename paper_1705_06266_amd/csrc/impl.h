@@ -84,7 +84,20 @@ struct lg_hierarchy {
   double* host_scal = nullptr;  // pinned mirror of scal
   double setup_ms = 0.0;
   double* lmax_dev = nullptr;
+  // The cycle captured as a HIP graph, per width log2(K) (see Engine::cycle):
+  // replayed with one launch instead of re-enqueueing every kernel.
+  struct CycleGraph {
+    hipGraphExec_t exec = nullptr;
+    const void* in = nullptr;  // the input buffer the graph reads
+    void* out = nullptr;       // the buffer holding its result
+    int uses = 0;              // eager applications so far
+  };
+  CycleGraph cycle_graph[6];
+  hipStream_t capture_stream = nullptr;
   ~lg_hierarchy() {
+    for (CycleGraph& g : cycle_graph)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
     if (host_scal) (void)hipHostFree(host_scal);
   }
 };

@@ -101,6 +101,8 @@ hipEvent_t take_event(Prof& p) {
 }
 }  // namespace
 
+bool prof_active() { return prof().enabled.load(std::memory_order_relaxed); }
+
 ProfScope::ProfScope(const char* family, hipStream_t s, double b, bool att)
     : on(false), attached(att), st(s), bytes(b) {
   Prof& p = prof();

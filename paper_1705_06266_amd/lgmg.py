@@ -46,7 +46,7 @@ class lg_setup_opts(C.Structure):
         ("cheb_hi", C.c_double), ("eig_iters", C.c_int32), ("coarsest_nnz", C.c_int64),
         ("max_levels", C.c_int32), ("cycle", C.c_int32), ("hash_mode", C.c_int32),
         ("seed", C.c_uint64), ("precision", C.c_int32), ("max_rhs", C.c_int32),
-        ("keep_setup_data", C.c_int32), ("validate", C.c_int32),
+        ("keep_setup_data", C.c_int32), ("validate", C.c_int32), ("graphs", C.c_int32),
     ]
 
 

@@ -237,3 +237,29 @@ def test_every_level_is_a_laplacian(built):
     for l, s in enumerate(lg.lg_hierarchy_stats(h)):
         rp, col, w, d, mp = lg.lg_export_level(h, l)
         check_laplacian_level(rp, col, w, d)
+
+
+@pytest.mark.parametrize("precision,cycle", [(lg.LG_FP64, 1), (lg.LG_MIXED, 1), (lg.LG_FP64, 2)])
+@pytest.mark.parametrize("name", ["grid3d_12_loguniform", "rmat_s12"])
+def test_graph_replays_match_eager_cycles(built, name, precision, cycle):
+    """The cycle replayed as a captured HIP graph computes exactly what the
+    eager launches compute: several solves (each replaying the graph every
+    iteration) with unrelated eager work and synchronisations in between."""
+    import torch
+
+    g = CASES[name]()
+    say(f"[case] {name} graphs vs eager, precision {precision}, cycle {cycle}")
+    hg = gpu_setup(g, max_rhs=4, precision=precision, cycle=cycle, graphs=1)
+    he = gpu_setup(g, max_rhs=4, precision=precision, cycle=cycle, graphs=0)
+    B = to_dev(gg.rhs(g.n, 3, 31))
+    Xe, infe, _ = lg.lg_solve(he, B)
+    Xe = Xe.cpu().numpy()
+    x = torch.randn(g.n, 2, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for rep in range(4):
+        Xg, infg, _ = lg.lg_solve(hg, B)
+        assert np.array_equal(Xg.cpu().numpy(), Xe), rep
+        assert [i["iters"] for i in infg] == [i["iters"] for i in infe]
+        lg.lg_spmv(hg, 0, x, y)  # eager work on the same hierarchy between replays
+        (y * 2.0).sum().item()
+        torch.cuda.synchronize()
