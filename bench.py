@@ -350,6 +350,8 @@ def main():
                     help="directory of a rocprofv3 --stats csv run: write the summary and exit")
     ap.add_argument("--graphs", type=int, default=None, choices=[0, 1],
                     help="replay the cycle as a captured HIP graph (default: the library's)")
+    ap.add_argument("--autotune", type=int, default=None, choices=[0, 1],
+                    help="time row-lane shifts per level at setup (default: the library's)")
     ap.add_argument("--command", default="", help="command line recorded in summaries")
     ap.add_argument("--bench-log", default=None, help="bench output of the profiled run (summaries)")
     args = ap.parse_args()
@@ -385,6 +387,8 @@ def main():
                               precision=lg.LG_MIXED if wl["precision"] == "mixed" else lg.LG_FP64)
     if args.graphs is not None:
         opts.graphs = args.graphs
+    if args.autotune is not None:
+        opts.autotune = args.autotune
     torch.cuda.synchronize()
 
     def step():
@@ -484,7 +488,7 @@ def main():
         "spmv_fp64_ms": sp_ms / sp_n if sp_n else None,
         "spmv_fp64_rhs": kk,
         "hierarchy_bytes": hier_bytes,
-        "levels": [(s["type"], s["n"], s["nnz"]) for s in stats],
+        "levels": [(s["type"], s["n"], s["nnz"], s["lane_shift"], s["col_shift"]) for s in stats],
     }
     if lat.size:
         out["solve_only"] = {"solves_per_s": wl["k"] * 1e3 / float(lat.mean()),

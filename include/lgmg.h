@@ -84,6 +84,8 @@ typedef struct {
   int32_t keep_setup_data;  /* 1: keep strengths, test vectors, votes and elimination choices for export */
   int32_t validate;         /* 1: check symmetry, weights and connectivity on the device */
   int32_t graphs;           /* 1: after its first use, replay the cycle as a captured HIP graph */
+  int32_t autotune;         /* 1: choose lanes per row of each large level by timing (cached per
+                               structure; summation order, hence rounding, follows the choice) */
 } lg_setup_opts;
 
 typedef struct lg_hierarchy lg_hierarchy;
@@ -95,6 +97,7 @@ typedef struct {
   int64_t nc;      /* vertices on the next level (0 for the coarsest) */
   double lmax;     /* lambda_max estimate of D^-1 L (aggregation levels) */
   int64_t n_hub;   /* rows split across workgroups by the row scheduler */
+  int32_t lane_shift, col_shift; /* row lanes 2^(class - shift) in use (set by the autotuner) */
 } lg_level_stats;
 
 typedef struct {

@@ -56,6 +56,7 @@ extern "C" lg_status lg_default_opts(lg_setup_opts* o) {
   o->keep_setup_data = 0;
   o->validate = 1;
   o->graphs = 1;
+  o->autotune = 1;
   return LG_OK;
 }
 
@@ -72,6 +73,7 @@ static const char* check_opts(const lg_setup_opts& o) {
   if (o.max_levels < 1) return "max_levels must be >= 1";
   if (o.elim_max_degree < 0) return "elim_max_degree must be >= 0";
   if (o.graphs != 0 && o.graphs != 1) return "graphs must be 0 or 1";
+  if (o.autotune != 0 && o.autotune != 1) return "autotune must be 0 or 1";
   return nullptr;
 }
 
@@ -99,6 +101,7 @@ extern "C" lg_status lg_setup(const lg_graph* g, const lg_setup_opts* o, void* h
   LG_HIP(hipGetDevice(&h->device));
   lg::setup_hierarchy(h, g, st);
   lg::alloc_solve_workspace(h, st);
+  if (opts.autotune) lg::autotune(h, st);
   LG_HIP(hipStreamSynchronize(st));
   h->setup_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -166,6 +169,8 @@ extern "C" lg_status lg_hierarchy_stats(const lg_hierarchy* h, lg_level_stats* o
     out[l].nc = L.nc;
     out[l].lmax = L.lmax;
     out[l].n_hub = L.sched.nhub + L.sched.nsplit;
+    out[l].lane_shift = L.sched.lane_shift;
+    out[l].col_shift = L.sched.col_shift;
   }
   return LG_OK;
 }

@@ -213,14 +213,17 @@ struct Sched {
   int32_t* split_cptr = nullptr;   // [nsplit + 1] first chunk of each split row
   int32_t* chunk_split = nullptr;  // [nchunk] split row of each chunk
   void* partial = nullptr;         // [nchunk * kPartialBytes]
+  // lanes (one-column kernels) or lane groups (column-split kernels) of a
+  // class-c row: 2^(c - shift), chosen per matrix by the autotuner
+  int lane_shift = 1, col_shift = 1;
 };
 
 // Degree unit of the classes (entries per lane per step of a full-width row).
 constexpr int kPerLane = LG_PER_LANE;
 
-// Lanes of a one-column row kernel for class c (see above).
-__host__ __device__ constexpr int class_lanes(int c) {
-  return c == 0 ? 1 : c < kClasses - 1 ? (1 << (c - 1)) : 64;
+// Lanes of a one-column row kernel for class c (see above) at a given shift.
+__host__ __device__ constexpr int class_lanes(int c, int shift = 1) {
+  return c >= kClasses - 1 ? 64 : (1 << (c > shift ? c - shift : 0));
 }
 
 // ------------------------------------------------- profiling (HIP events)
@@ -391,7 +394,8 @@ __global__ __launch_bounds__(kBlock) void k_rows(Op op, const int32_t* __restric
                                                  int64_t nchunk, const int32_t* __restrict__ split_rows,
                                                  const int32_t* __restrict__ split_cptr,
                                                  const int32_t* __restrict__ chunk_split,
-                                                 typename Op::Acc* __restrict__ partial) {
+                                                 typename Op::Acc* __restrict__ partial,
+                                                 int shift) {
   int64_t b = blockIdx.x;
   if (b < nchunk) {
     split_chunk(op, rp, split_rows, split_cptr, chunk_split, partial, b);
@@ -414,14 +418,13 @@ __global__ __launch_bounds__(kBlock) void k_rows(Op op, const int32_t* __restric
     for (int k = 1; k < kClasses; k++) c += (q >= ct.blk_start[k]) ? 1 : 0;
     const int64_t lb = q - ct.blk_start[c];
     const int64_t p0 = ct.cls_start[c], p1 = ct.cls_start[c + 1];
-    switch (c) {
-      case 0: rows_class<Op, 1>(op, rp, perm, p0, p1, lb); break;
+    switch (class_lanes(c, shift)) {
       case 1: rows_class<Op, 1>(op, rp, perm, p0, p1, lb); break;
       case 2: rows_class<Op, 2>(op, rp, perm, p0, p1, lb); break;
-      case 3: rows_class<Op, 4>(op, rp, perm, p0, p1, lb); break;
-      case 4: rows_class<Op, 8>(op, rp, perm, p0, p1, lb); break;
-      case 5: rows_class<Op, 16>(op, rp, perm, p0, p1, lb); break;
-      case 6: rows_class<Op, 32>(op, rp, perm, p0, p1, lb); break;
+      case 4: rows_class<Op, 4>(op, rp, perm, p0, p1, lb); break;
+      case 8: rows_class<Op, 8>(op, rp, perm, p0, p1, lb); break;
+      case 16: rows_class<Op, 16>(op, rp, perm, p0, p1, lb); break;
+      case 32: rows_class<Op, 32>(op, rp, perm, p0, p1, lb); break;
       default: rows_class<Op, 64>(op, rp, perm, p0, p1, lb); break;
     }
   }
@@ -455,17 +458,24 @@ void run_rows(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st,
   static_assert(sizeof(typename Op::Acc) <= kPartialBytes, "accumulator larger than a partial slot");
   static_assert(sizeof(typename Op::Acc) % 4 == 0, "accumulator size must be a multiple of 4");
   if (s.n == 0) return;
-  const int64_t total = s.ct.blk_start[kClasses];
+  ClassTable ct = s.ct;
+  int64_t total = 0;
+  for (int c = 0; c < kClasses; c++) {
+    ct.blk_start[c] = (int32_t)total;
+    total += ceil_div((int64_t)(s.ct.cls_start[c + 1] - s.ct.cls_start[c]) * class_lanes(c, s.lane_shift),
+                      (int64_t)kBlock);
+  }
+  ct.blk_start[kClasses] = (int32_t)total;
   const int64_t blocks =
       round_up8(s.nchunk + s.nhub) + round_up8(std::min<int64_t>(total, resident_grid(k_rows<Op>)));
   if (blocks == 0) return;
   {
     ProfScope ps(fam, st, bytes, true);
     hipExtLaunchKernelGGL((k_rows<Op>), dim3((unsigned)blocks), dim3(kBlock), 0, st, ps.start(),
-                          ps.stop(), 0, op, rp, (const int32_t*)s.perm, s.ct, s.nhub,
+                          ps.stop(), 0, op, rp, (const int32_t*)s.perm, ct, s.nhub,
                           (const int32_t*)s.hub_rows, s.nchunk, (const int32_t*)s.split_rows,
                           (const int32_t*)s.split_cptr, (const int32_t*)s.chunk_split,
-                          reinterpret_cast<typename Op::Acc*>(s.partial));
+                          reinterpret_cast<typename Op::Acc*>(s.partial), s.lane_shift);
   }
   LG_LAUNCH_CHECK();
   if (s.nsplit) {
@@ -558,7 +568,8 @@ __global__ __launch_bounds__(kBlock) void k_rows_col(Op op, const int32_t* __res
                                                      const int32_t* __restrict__ split_rows,
                                                      const int32_t* __restrict__ split_cptr,
                                                      const int32_t* __restrict__ chunk_split,
-                                                     typename Op::Acc* __restrict__ partial) {
+                                                     typename Op::Acc* __restrict__ partial,
+                                                     int shift) {
   constexpr int L = Op::kL;
   int64_t b = blockIdx.x;
   if (b < nchunk) {
@@ -585,15 +596,14 @@ __global__ __launch_bounds__(kBlock) void k_rows_col(Op op, const int32_t* __res
   constexpr int MM = 64 / L;  // most groups a row may span inside one wavefront
   for_class_blocks(ct, b, slots, [&](int c, int64_t lb) {
     const int64_t p0 = ct.cls_start[c], p1 = ct.cls_start[c + 1];
-    switch (c) {
-      case 0: col_rows<Op, 1>(op, rp, perm, p0, p1, lb); break;
+    switch (c >= kClasses - 1 ? 0 : min(class_lanes(c, shift), MM)) {
       case 1: col_rows<Op, 1>(op, rp, perm, p0, p1, lb); break;
       case 2: col_rows<Op, (2 < MM ? 2 : MM)>(op, rp, perm, p0, p1, lb); break;
-      case 3: col_rows<Op, (4 < MM ? 4 : MM)>(op, rp, perm, p0, p1, lb); break;
-      case 4: col_rows<Op, (8 < MM ? 8 : MM)>(op, rp, perm, p0, p1, lb); break;
-      case 5: col_rows<Op, (16 < MM ? 16 : MM)>(op, rp, perm, p0, p1, lb); break;
-      case 6: col_rows<Op, (32 < MM ? 32 : MM)>(op, rp, perm, p0, p1, lb); break;
-      default: {  // one workgroup per row
+      case 4: col_rows<Op, (4 < MM ? 4 : MM)>(op, rp, perm, p0, p1, lb); break;
+      case 8: col_rows<Op, (8 < MM ? 8 : MM)>(op, rp, perm, p0, p1, lb); break;
+      case 16: col_rows<Op, (16 < MM ? 16 : MM)>(op, rp, perm, p0, p1, lb); break;
+      case 32: col_rows<Op, (32 < MM ? 32 : MM)>(op, rp, perm, p0, p1, lb); break;
+      default: {  // one workgroup per row (class 7)
         const int64_t row = perm[p0 + lb];
         const typename Op::Acc t = col_block_reduce(op, row, rp[row], rp[row + 1]);
         if (threadIdx.x < L) op.finish(row, t, (int)threadIdx.x);
@@ -630,7 +640,7 @@ void run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_t s
   for (int c = 0; c < kClasses; c++) {
     ct.blk_start[c] = (int32_t)blk;
     const int64_t rows = s.ct.cls_start[c + 1] - s.ct.cls_start[c];
-    const int64_t M = std::min<int64_t>(c == 0 ? 1 : (int64_t)1 << (c - 1), 64 / L);
+    const int64_t M = std::min<int64_t>(class_lanes(c, s.col_shift), 64 / L);
     blk += c == kClasses - 1 ? rows : ceil_div(rows * L * M, kBlock);
   }
   ct.blk_start[kClasses] = (int32_t)blk;
@@ -643,7 +653,7 @@ void run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_t s
                           ps.stop(), 0, op, rp, (const int32_t*)s.perm, ct, s.nhub,
                           (const int32_t*)s.hub_rows, s.nchunk, (const int32_t*)s.split_rows,
                           (const int32_t*)s.split_cptr, (const int32_t*)s.chunk_split,
-                          reinterpret_cast<typename Op::Acc*>(s.partial));
+                          reinterpret_cast<typename Op::Acc*>(s.partial), s.col_shift);
   }
   LG_LAUNCH_CHECK();
   if (s.nsplit) {

@@ -118,4 +118,5 @@ lg_status solve_dispatch(lg_hierarchy* h, const double* B, double* X, int k, dou
                          int max_iter, hipStream_t st, lg_rhs_info* info);
 void cycle_dispatch(lg_hierarchy* h, const double* B, double* X, int k, hipStream_t st);
 void spmv_dispatch(lg_hierarchy* h, int level, const double* X, double* Y, int k, hipStream_t st);
+void autotune(lg_hierarchy* h, hipStream_t st);
 }  // namespace lg

@@ -535,7 +535,7 @@ void build_sched(Sched& s, const int32_t* rp, int64_t n, int64_t nnz, Arena& kee
   for (int c = 0; c < kClasses; c++) {
     s.ct.cls_start[c] = (int32_t)pos;
     s.ct.blk_start[c] = (int32_t)blk;
-    const int G = class_lanes(c);
+    const int G = class_lanes(c, s.lane_shift);
     pos += t[ST_CLS + c];
     blk += ceil_div((int64_t)t[ST_CLS + c] * G, kBlock);
   }

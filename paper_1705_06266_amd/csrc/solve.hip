@@ -9,6 +9,8 @@
 // and residuals, and the coarsest dense solve stay in fp64).
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "impl.h"
@@ -1199,6 +1201,101 @@ void spmv_dispatch(lg_hierarchy* h, int level, const double* X, double* Y, int k
     default: fail(LG_E_ARG, "lg_spmv: k must be 1, 2, 4, 8, 16 or 32");
   }
   LG_LAUNCH_CHECK();
+}
+
+// ----------------------------------------------------------- autotuner
+// Lanes (one-column kernels) or lane groups (column-split kernels) per row of
+// each degree class are 2^(c - shift); the best shift depends on the degree
+// distribution, the width and the precision.  For every level whose product
+// is large enough to matter, the tuner times that level's dominant product
+// (the smoother-shaped residual at the cycle's precision on an aggregation
+// level, the CG's fp64 product on the finest elimination level) for each
+// candidate shift and keeps the fastest.  Choices are cached for the process
+// by the level's structure, precision and width, so hierarchies of the same
+// graph (and repeated setups) reuse them without timing again.
+namespace {
+constexpr int64_t kTuneMinNnz = (int64_t)1 << 18;
+constexpr int kTuneShifts[] = {0, 1, 2};
+std::mutex g_tune_mu;
+std::map<std::vector<int64_t>, int> g_tune;
+}  // namespace
+
+template <typename T, int K>
+static void autotune_k(lg_hierarchy* h, hipStream_t st) {
+  Engine<T, K> eng{h, st};
+  hipEvent_t e0, e1;
+  LG_HIP(hipEventCreate(&e0));
+  LG_HIP(hipEventCreate(&e1));
+  const int nl = (int)h->lev.size();
+  for (int l = 0; l + 1 < nl; l++) {
+    Level& L = h->lev[l];
+    const bool agg = L.type == LG_LEVEL_AGG;
+    if (L.nnz < kTuneMinNnz || (!agg && l != 0)) continue;
+    const bool col = agg ? use_col_split<T, K>() : use_col_split<double, K>();
+    int& shift = col ? L.sched.col_shift : L.sched.lane_shift;
+    const std::vector<int64_t> key{L.n, L.nnz, L.sched.min_deg, L.sched.max_deg, L.sched.nhub,
+                                   L.sched.nsplit, agg ? (int64_t)sizeof(T) : 8, K, col ? 1 : 0};
+    {
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) {
+        shift = it->second;
+        continue;
+      }
+    }
+    auto product = [&]() {
+      if (agg)
+        eng.template lap<LAP_RESID>(L, (const T*)L.vx, (T*)L.vr, (const T*)L.vb, nullptr, T(0), T(0),
+                                    T(0), "", 3);
+      else
+        lap64<K>(h, 0, h->pp, h->pq, nullptr, st, "");
+    };
+    const int64_t m = L.n * K;
+    if (agg) {
+      hipLaunchKernelGGL((k_fill<T>), dim3(nblk(m)), dim3(kBlock), 0, st, (T*)L.vx, m, T(0));
+      hipLaunchKernelGGL((k_fill<T>), dim3(nblk(m)), dim3(kBlock), 0, st, (T*)L.vb, m, T(0));
+    } else {
+      hipLaunchKernelGGL((k_fill<double>), dim3(nblk(m)), dim3(kBlock), 0, st, h->pp, m, 0.0);
+    }
+    int best = shift;
+    float best_ms = 0.0f;
+    for (int cand : kTuneShifts) {
+      shift = cand;
+      product();  // warm-up at this shift
+      LG_HIP(hipEventRecord(e0, st));
+      for (int r = 0; r < 3; r++) product();
+      LG_HIP(hipEventRecord(e1, st));
+      LG_HIP(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      LG_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (cand == kTuneShifts[0] || ms < best_ms) {
+        best_ms = ms;
+        best = cand;
+      }
+    }
+    shift = best;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[key] = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+template <typename T>
+static void autotune_t(lg_hierarchy* h, hipStream_t st) {
+  switch (h->K) {
+    case 1: return autotune_k<T, 1>(h, st);
+    case 2: return autotune_k<T, 2>(h, st);
+    case 4: return autotune_k<T, 4>(h, st);
+    case 8: return autotune_k<T, 8>(h, st);
+    case 16: return autotune_k<T, 16>(h, st);
+    default: return autotune_k<T, 32>(h, st);
+  }
+}
+
+void autotune(lg_hierarchy* h, hipStream_t st) {
+  if (h->opts.precision == LG_MIXED) autotune_t<float>(h, st);
+  else autotune_t<double>(h, st);
 }
 
 // ----------------------------------------------------------- workspace
