@@ -86,6 +86,8 @@ typedef struct {
   int32_t graphs;           /* 1: after its first use, replay the cycle as a captured HIP graph */
   int32_t autotune;         /* 1: choose lanes per row of each large level by timing (cached per
                                structure; summation order, hence rounding, follows the choice) */
+  int32_t elim_passes;      /* elimination passes before each aggregation, 1..16 (1: Section 3.4;
+                               more repeat it on its own result while it removes enough) */
 } lg_setup_opts;
 
 typedef struct lg_hierarchy lg_hierarchy;

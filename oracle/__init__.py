@@ -52,6 +52,7 @@ class Opts(C.Structure):
         ("cycle", C.c_int32),
         ("hash_mode", C.c_int32),
         ("seed", C.c_uint64),
+        ("elim_passes", C.c_int32),
     ]
 
 

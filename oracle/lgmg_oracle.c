@@ -60,6 +60,7 @@ void lgo_default_opts(lgo_opts* o) {
   o->cycle = 1;
   o->hash_mode = 0;
   o->seed = 12345;
+  o->elim_passes = 1;  /* one pass, as the paper applies; more repeat it on the result */
 }
 
 /* ---------------------------------------------------------------- RNG ---- */
@@ -856,7 +857,10 @@ int lgo_setup(int64_t n, const int64_t* rp, const int32_t* col, const double* w,
     olevel* cur = &h->lev[l];
     int64_t nl = cur->A.n;
     if (nl + cur->A.nnz <= o->coarsest_nnz || l + 1 >= o->max_levels || l + 2 >= MAXLEV) break;
-    if (o->elim_enable) {
+    /* Section 3.4's elimination, repeated on its own result while it still
+       removes more than the minimum fraction (elim_passes > 1) */
+    int stop = 0;
+    for (int pass = 0; o->elim_enable && pass < o->elim_passes; pass++) {
       int32_t* z = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)nl);
       uint8_t* F = (uint8_t*)xmalloc((size_t)nl);
       int64_t nf = lgo_elim_select(nl, cur->A.rp, cur->A.col, o->elim_max_degree, o->hash_mode,
@@ -891,13 +895,17 @@ int lgo_setup(int64_t n, const int64_t* rp, const int32_t* col, const double* w,
         l++;
         cur = &h->lev[l];
         nl = cur->A.n;
-        if (nl + cur->A.nnz <= o->coarsest_nnz || l + 1 >= o->max_levels || l + 2 >= MAXLEV)
+        if (nl + cur->A.nnz <= o->coarsest_nnz || l + 1 >= o->max_levels || l + 2 >= MAXLEV) {
+          stop = 1;
           break;
+        }
       } else {
         free(z);
         free(F);
+        break;
       }
     }
+    if (stop) break;
     /* aggregation level */
     cur->X = (double*)xmalloc(sizeof(double) * 4 * (size_t)nl);
     cur->S = (double*)xmalloc(sizeof(double) * (size_t)(cur->A.nnz ? cur->A.nnz : 1));

@@ -41,6 +41,7 @@ typedef struct {
   int32_t cycle;              /* 1 = V-cycle inside CG, 2 = K-cycle inside FCG */
   int32_t hash_mode;          /* 0 = mixed hash of the id, 1 = identity (test hook) */
   uint64_t seed;              /* seed of the counter-based generator */
+  int32_t elim_passes;        /* elimination passes before each aggregation (1: Section 3.4) */
 } lgo_opts;
 
 void lgo_default_opts(lgo_opts* o);

@@ -57,6 +57,7 @@ extern "C" lg_status lg_default_opts(lg_setup_opts* o) {
   o->validate = 1;
   o->graphs = 1;
   o->autotune = 1;
+  o->elim_passes = 1;
   return LG_OK;
 }
 
@@ -74,6 +75,7 @@ static const char* check_opts(const lg_setup_opts& o) {
   if (o.elim_max_degree < 0) return "elim_max_degree must be >= 0";
   if (o.graphs != 0 && o.graphs != 1) return "graphs must be 0 or 1";
   if (o.autotune != 0 && o.autotune != 1) return "autotune must be 0 or 1";
+  if (o.elim_passes < 1 || o.elim_passes > 16) return "elim_passes must be in 1..16";
   return nullptr;
 }
 

@@ -1240,22 +1240,28 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
                            (l + 2 >= kMaxLevelCap);
     if (stop_here) break;
     Arena::Mark lm = c.tmp.mark();
-    if (o.elim_enable) {
+    // Section 3.4's elimination, repeated on its own result while it still
+    // removes more than the minimum fraction (elim_passes > 1)
+    bool stop = false;
+    for (int pass = 0; o.elim_enable && pass < o.elim_passes; pass++) {
       ElimChoice ch = elim_select(c, *L);
-      if ((double)ch.nf > o.elim_min_fraction * (double)L->n) {
-        h->lev.emplace_back();
-        L = &h->lev[l];
-        build_elim(c, *L, ch, h->lev[l + 1]);
-        check_flags(c);
+      if (!((double)ch.nf > o.elim_min_fraction * (double)L->n)) {
         c.tmp.rewind(lm);
-        l++;
-        L = &h->lev[l];
-        if ((L->n + L->nnz <= o.coarsest_nnz) || (l + 1 >= o.max_levels) ||
-            (l + 2 >= kMaxLevelCap))
-          break;
+        break;
       }
+      h->lev.emplace_back();
+      L = &h->lev[l];
+      build_elim(c, *L, ch, h->lev[l + 1]);
+      check_flags(c);
       c.tmp.rewind(lm);
+      l++;
+      L = &h->lev[l];
+      if ((L->n + L->nnz <= o.coarsest_nnz) || (l + 1 >= o.max_levels) || (l + 2 >= kMaxLevelCap)) {
+        stop = true;
+        break;
+      }
     }
+    if (stop) break;
     // aggregation level
     double* X = o.keep_setup_data ? h->mem.get<double>(4 * L->n) : c.tmp.get<double>(4 * L->n);
     double* S = o.keep_setup_data ? h->mem.get<double>(L->nnz) : c.tmp.get<double>(L->nnz);

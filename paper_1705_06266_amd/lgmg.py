@@ -47,7 +47,7 @@ class lg_setup_opts(C.Structure):
         ("max_levels", C.c_int32), ("cycle", C.c_int32), ("hash_mode", C.c_int32),
         ("seed", C.c_uint64), ("precision", C.c_int32), ("max_rhs", C.c_int32),
         ("keep_setup_data", C.c_int32), ("validate", C.c_int32), ("graphs", C.c_int32),
-        ("autotune", C.c_int32),
+        ("autotune", C.c_int32), ("elim_passes", C.c_int32),
     ]
 
 

@@ -263,3 +263,19 @@ def test_graph_replays_match_eager_cycles(built, name, precision, cycle):
         lg.lg_spmv(hg, 0, x, y)  # eager work on the same hierarchy between replays
         (y * 2.0).sum().item()
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name", ["path_333", "chunglu_30k_hubs", "grid2d_64x64", "rmat_s12"])
+def test_repeated_elimination_matches(built, name):
+    """Repeated elimination passes (elim_passes > 1): hierarchy bit for bit,
+    solve to the fp64 bar."""
+    g, hg, ho = _pair(name, elim_passes=4)
+    sg = compare_hierarchies(hg, ho, setup_data=True)
+    say(f"  levels={[(s['type'], s['n']) for s in sg]}")
+    b = gg.rhs(g.n, 1, 13)[:, 0]
+    X, info, st = lg.lg_solve(hg, to_dev(b[:, None]), rtol=1e-8, max_iter=300)
+    xo, sto, ito, relo, _ = ho.solve(b, 1e-8, 300)
+    xg = X.cpu().numpy()[:, 0]
+    assert st == 0 and sto == 0 and abs(info[0]["iters"] - ito) <= 1
+    diff = dense_laplacian_norm(g, xg - xo) / dense_laplacian_norm(g, xo)
+    assert diff <= 1e-6

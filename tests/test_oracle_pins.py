@@ -557,6 +557,52 @@ def test_elimination_level_with_exact_coarse_solve_is_exact():
     assert st == 0 and it == 1
 
 
+def test_repeated_elimination_keeps_series_resistance_on_a_path():
+    # Eliminating vertices of a unit-weight path only deletes leaves or merges
+    # series edges: a coarse edge between the surviving original vertices u < v
+    # has weight 1/(v - u), the series resistance of the fine edges between them.
+    n = 257
+    g = gg.path(n)
+    h = oracle.Hierarchy(g, oracle.default_opts(elim_passes=6, elim_min_fraction=0.0,
+                                                coarsest_nnz=3))
+    lv = h.levels()
+    elim = [l for l, L in enumerate(lv) if L.type == oracle.ELIM]
+    assert elim[:6] == list(range(6)), [L.type for L in lv]
+    sizes = [lv[l].n for l in range(7)]
+    assert all(a > b for a, b in zip(sizes, sizes[1:]))
+    orig = np.arange(n)
+    for l in range(6):  # original vertex behind each kept vertex
+        cidx = h.map(l)
+        kept = np.flatnonzero(cidx >= 0)
+        new = np.empty(lv[l].nc, dtype=np.int64)
+        new[cidx[kept]] = orig[kept]
+        orig = new
+    assert np.all(np.diff(orig) > 0)
+    gc, dc = h.csr(6)
+    rows = np.repeat(np.arange(gc.n), np.diff(gc.row_ptr))
+    assert np.all(np.diff(gc.row_ptr) <= 2)  # still a path, between consecutive survivors
+    assert np.all(np.abs(rows - gc.col) == 1)
+    span = np.abs(orig[rows] - orig[gc.col]).astype(np.float64)
+    assert np.allclose(gc.w * span, 1.0, rtol=1e-12, atol=0)
+
+
+def test_repeated_elimination_with_exact_coarse_solve_is_exact():
+    # elimination levels are exact Schur complements: with passes repeated
+    # until the dense coarsest level, one cycle is L^+ and CG stops after one step
+    g = gg.path(60, w=np.linspace(1.0, 3.0, 59))
+    h = oracle.Hierarchy(g, oracle.default_opts(elim_passes=16, coarsest_nnz=60))
+    lv = h.levels()
+    assert [L.type for L in lv[:-1]] == [oracle.ELIM] * (len(lv) - 1) and len(lv) >= 3
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(g.n)
+    b -= b.mean()
+    L = dense_L(g)
+    x = h.cycle(b)
+    assert np.linalg.norm(L @ x - b) <= 1e-12 * np.linalg.norm(b)
+    x, st, it, rel, work = h.solve(b, 1e-8)
+    assert st == 0 and it == 1
+
+
 def test_wda_within_the_papers_range_on_the_2d_grid():
     # context only: the paper's V-cycle WDA on its test set spans roughly 3 to 100
     g = gg.grid2d(64, 64)
