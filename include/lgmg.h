@@ -134,6 +134,18 @@ lg_status lg_setup(const lg_graph* g, const lg_setup_opts* o, void* hip_stream,
 lg_status lg_solve(lg_hierarchy* h, const double* B, double* X, int32_t k, double rtol,
                    int32_t max_iter, void* hip_stream, lg_rhs_info* info);
 
+/* The nev smallest nonzero eigenvalues of L (ascending, host lambda[nev])
+ * and unit eigenvectors (device X, n x nev row-major, mean zero) -- the
+ * Fiedler vector first (Section 2.1: spectral partitioning and drawing).
+ * Block inverse subspace iteration on the mean-zero space, each block solved
+ * with lg_solve's preconditioned CG; stops when every pair has
+ * ||L x - lambda x|| <= tol * lambda (resid, host nev, may be NULL) or after
+ * max_iter blocks (*iters, may be NULL).  The block is next_pow2(nev + 1)
+ * columns: 1 <= nev <= 7 and that block at most max_rhs of setup.  Returns
+ * LG_E_NOT_CONVERGED (outputs filled) if a pair misses tol. */
+lg_status lg_eigs(lg_hierarchy* h, int32_t nev, double tol, int32_t max_iter, double* X,
+                  double* lambda, int32_t* iters, double* resid, void* hip_stream);
+
 /* One application of the preconditioner (Algorithm 1 from the finest level
  * with zero initial guess; V- or K-cycle and precision as in setup):
  * X = M B for device n x k fp64 arrays.  No projection.  The columns of B

@@ -416,3 +416,17 @@ class Hierarchy:
         st = lib().lgo_solve(self._h, _ptr(b), _ptr(x), rtol, max_iter, C.byref(it), C.byref(rel),
                              C.byref(work))
         return x, int(st), it.value, rel.value, work.value
+
+
+def eigs_dense(g, nev):
+    """The nev smallest nonzero eigenvalues of L = D - A of a connected graph,
+    ascending, with unit eigenvectors (columns): the definition itself, from
+    the dense matrix (Section 2.1's eigensystem; its first vector is the
+    Fiedler vector).  Small graphs only."""
+    n = g.n
+    rows = np.repeat(np.arange(n), np.diff(g.row_ptr))
+    L = np.zeros((n, n))
+    np.add.at(L, (rows, g.col), -g.w)
+    L[np.arange(n), np.arange(n)] = np.bincount(rows, weights=g.w, minlength=n)
+    lam, V = np.linalg.eigh(L)
+    return lam[1:nev + 1], V[:, 1:nev + 1]

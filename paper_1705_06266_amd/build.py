@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblgmg.so")
-SOURCES = ["prims.hip", "setup.hip", "solve.hip", "capi.hip", "server.hip"]
+SOURCES = ["prims.hip", "setup.hip", "solve.hip", "capi.hip", "server.hip", "eigen.hip"]
 HEADERS = ["common.h", "impl.h", "ops.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

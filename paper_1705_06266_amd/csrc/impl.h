@@ -119,4 +119,6 @@ lg_status solve_dispatch(lg_hierarchy* h, const double* B, double* X, int k, dou
 void cycle_dispatch(lg_hierarchy* h, const double* B, double* X, int k, hipStream_t st);
 void spmv_dispatch(lg_hierarchy* h, int level, const double* X, double* Y, int k, hipStream_t st);
 void autotune(lg_hierarchy* h, hipStream_t st);
+lg_status eigs_dispatch(lg_hierarchy* h, int nev, double tol, int max_iter, double* X,
+                        double* lambda, int* iters, double* resid, hipStream_t st);
 }  // namespace lg

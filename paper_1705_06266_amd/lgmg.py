@@ -23,7 +23,7 @@ LG_CYCLE_V, LG_CYCLE_K = 1, 2
 LG_FP64, LG_MIXED = 0, 1
 
 EXPORTS = [
-    "lg_default_opts", "lg_setup", "lg_solve", "lg_cycle", "lg_spmv", "lg_hierarchy_stats",
+    "lg_default_opts", "lg_setup", "lg_solve", "lg_eigs", "lg_cycle", "lg_spmv", "lg_hierarchy_stats",
     "lg_export_level", "lg_export_setup_data", "lg_export_coarsest", "lg_hierarchy_bytes",
     "lg_setup_ms", "lg_free", "lg_profile_enable", "lg_profile_read", "lg_profile_names",
     "lg_status_str", "lg_last_error",
@@ -97,6 +97,7 @@ def load():
         "lg_setup": (_I32, [_P, _P, _P, C.POINTER(_P)]),
         "lg_solve": (_I32, [_P, _P, _P, _I32, _D, _I32, _P, _P]),
         "lg_cycle": (_I32, [_P, _P, _P, _I32, _P]),
+        "lg_eigs": (_I32, [_P, _I32, _D, _I32, _P, _P, _P, _P, _P]),
         "lg_spmv": (_I32, [_P, _I32, _P, _P, _I32, _P]),
         "lg_hierarchy_stats": (_I32, [_P, _P, _I32, _P]),
         "lg_export_level": (_I32, [_P, _I32, _P, _P, _P, _P, _P]),
@@ -225,6 +226,21 @@ def lg_solve(h, B, X=None, rtol=1e-8, max_iter=500, stream=None, allow_unconverg
     infos = [dict(iters=i.iters, rel_residual=i.rel_residual, work_units=i.work_units, wda=i.wda)
              for i in info]
     return X, infos, st
+
+
+def lg_eigs(h, nev=1, tol=1e-8, max_iter=200, stream=None, allow_unconverged=False):
+    """The nev smallest nonzero eigenpairs of L: (lambda, X, iters, resid, status)
+    with lambda a numpy array and X a device float64 tensor of shape (n, nev)."""
+    import torch
+
+    X = torch.empty((h.n, nev), dtype=torch.float64, device=torch.device("cuda", torch.cuda.current_device()))
+    lam = np.zeros(nev)
+    res = np.zeros(nev)
+    it = C.c_int32()
+    ok = (LG_OK, LG_E_NOT_CONVERGED) if allow_unconverged else (LG_OK,)
+    st = _check(load().lg_eigs(h.handle, nev, tol, max_iter, _ptr(X), _ptr(lam), C.byref(it),
+                               _ptr(res), _stream(stream)), "lg_eigs", ok)
+    return lam, X, it.value, res, st
 
 
 def lg_cycle(h, B, X=None, stream=None):

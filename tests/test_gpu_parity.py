@@ -279,3 +279,30 @@ def test_repeated_elimination_matches(built, name):
     assert st == 0 and sto == 0 and abs(info[0]["iters"] - ito) <= 1
     diff = dense_laplacian_norm(g, xg - xo) / dense_laplacian_norm(g, xo)
     assert diff <= 1e-6
+
+
+@pytest.mark.parametrize("name,nev", [("grid2d_64x64", 3), ("path_333", 2), ("cycle_64", 2),
+                                      ("gnp_700", 1), ("grid3d_12_loguniform", 3)])
+def test_eigs_match_the_dense_eigendecomposition(built, name, nev):
+    """lg_eigs: the nev smallest nonzero eigenpairs.  Bar: each returned pair
+    has ||L x - lambda x|| <= tol * lambda (checked here on the host), the
+    eigenvalues equal the dense ones to 1e-9 relative, and where the spectrum
+    has a gap after the nev-th value the returned subspace is the exact one."""
+    g = CASES[name]()
+    say(f"[case] {name} eigs nev={nev}")
+    h = gpu_setup(g, max_rhs=8)
+    tol = 1e-8
+    lam, X, it, res, st = lg.lg_eigs(h, nev, tol=tol, max_iter=500)
+    lam_o, V = oracle.eigs_dense(g, nev + 1)
+    say(f"  iterations {it}, lambda {lam}, dense {lam_o[:nev]}")
+    assert st == lg.LG_OK
+    X = X.cpu().numpy()
+    for i in range(nev):
+        x = X[:, i]
+        assert abs(np.linalg.norm(x) - 1.0) <= 1e-10 and abs(x.sum()) <= 1e-8 * np.sqrt(g.n)
+        r = np.linalg.norm(laplacian_apply(g, x) - lam[i] * x)
+        assert r <= tol * lam[i] * 1.001
+    assert np.allclose(lam, lam_o[:nev], rtol=1e-9, atol=0)
+    if lam_o[nev] - lam_o[nev - 1] > 1e-3 * lam_o[nev]:
+        s = np.linalg.svd(V[:, :nev].T @ X, compute_uv=False)
+        assert s.min() >= 1.0 - 1e-8

@@ -611,3 +611,31 @@ def test_wda_within_the_papers_range_on_the_2d_grid():
     x, st, it, rel, work = h.solve(b)
     wda = -work / math.log10(rel)
     assert st == 0 and 3 < wda < 100
+
+
+# ---- eigenpairs (the definition computed densely; pinned to closed forms)
+def test_eigs_dense_path_closed_form_and_fiedler_vector():
+    n = 40
+    lam, V = oracle.eigs_dense(gg.path(n), 3)
+    k = np.arange(1, 4)
+    assert np.allclose(lam, 2.0 - 2.0 * np.cos(np.pi * k / n), rtol=0, atol=1e-12)
+    u = np.cos(np.pi * (np.arange(n) + 0.5) / n)
+    assert abs(abs(V[:, 0] @ u) / np.linalg.norm(u) - 1.0) <= 1e-10
+
+
+def test_eigs_dense_even_cycle_has_double_eigenvalues():
+    n = 30
+    lam, V = oracle.eigs_dense(gg.cycle(n), 4)
+    want = 2.0 - 2.0 * np.cos(2.0 * np.pi * np.array([1, 1, 2, 2]) / n)
+    assert np.allclose(lam, want, rtol=0, atol=1e-12)
+
+
+def test_eigs_dense_grid_is_a_sum_of_path_spectra():
+    a, b = 7, 5
+    lam, V = oracle.eigs_dense(gg.grid2d(a, b), 6)
+    pa = 2.0 - 2.0 * np.cos(np.pi * np.arange(a) / a)
+    pb = 2.0 - 2.0 * np.cos(np.pi * np.arange(b) / b)
+    want = np.sort((pa[:, None] + pb[None, :]).ravel())[1:7]
+    assert np.allclose(lam, want, rtol=0, atol=1e-12)
+    assert np.allclose(V.T @ V, np.eye(6), atol=1e-12)
+    assert np.allclose(V.sum(axis=0), 0.0, atol=1e-10)  # orthogonal to the constant
