@@ -362,7 +362,7 @@ def main():
         return trace_summary(args)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(batches of right-hand sides or a pool of graphs would shard by keeping a "
               "replica of each hierarchy per GPU)", file=sys.stderr)
         sys.exit(2)

@@ -346,7 +346,14 @@ def test_filter_keeps_strength_equal_to_threshold():
 
 
 def test_path_hand_trace():
-    # traced by hand in the design doc: seeds 1 and 3, aggregates {0,1,2} and {3,4}
+    # Hand trace (all strengths 1, so every edge passes the filter and ties go
+    # to the smaller index).  While all are Undecided, 0 votes for 1, 1 for 0,
+    # 2 for 1, 3 for 2 and 4 for 3: votes grow by (1, 2, 1, 1, 0) per iteration,
+    # so after iteration 4 vertex 1 has 8 votes and becomes a Seed.  Iteration 5:
+    # 0 and 2 join Seed 1; 3 votes for 2 (still Undecided at the iteration's
+    # start), 4 for 3.  Iterations 6-8: 3 and 4 vote for each other, 3 reaches 8
+    # votes after iteration 8 and becomes a Seed; 4 joins it in iteration 9.
+    # Final votes (4, 8, 5, 8, 3), aggregates {0, 1, 2} and {3, 4}.
     g = gg.path(5)
     nc, agg, state, idx, votes = oracle.aggregate(g, _uniform_S(g), oracle.default_opts())
     assert nc == 2
