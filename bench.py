@@ -352,6 +352,8 @@ def main():
                     help="replay the cycle as a captured HIP graph (default: the library's)")
     ap.add_argument("--autotune", type=int, default=None, choices=[0, 1],
                     help="time row-lane shifts per level at setup (default: the library's)")
+    ap.add_argument("--merge-path", type=int, default=None, choices=[0, 1, 2],
+                    help="one-column products: 0 class rows, 1 tuner's choice, 2 merge path")
     ap.add_argument("--command", default="", help="command line recorded in summaries")
     ap.add_argument("--bench-log", default=None, help="bench output of the profiled run (summaries)")
     args = ap.parse_args()
@@ -389,6 +391,8 @@ def main():
         opts.graphs = args.graphs
     if args.autotune is not None:
         opts.autotune = args.autotune
+    if args.merge_path is not None:
+        opts.merge_path = args.merge_path
     torch.cuda.synchronize()
 
     def step():
@@ -488,7 +492,8 @@ def main():
         "spmv_fp64_ms": sp_ms / sp_n if sp_n else None,
         "spmv_fp64_rhs": kk,
         "hierarchy_bytes": hier_bytes,
-        "levels": [(s["type"], s["n"], s["nnz"], s["lane_shift"], s["col_shift"]) for s in stats],
+        "levels": [(s["type"], s["n"], s["nnz"], s["lane_shift"], s["col_shift"], s["merge"])
+                   for s in stats],
     }
     if lat.size:
         out["solve_only"] = {"solves_per_s": wl["k"] * 1e3 / float(lat.mean()),

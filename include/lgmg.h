@@ -88,6 +88,8 @@ typedef struct {
                                structure; summation order, hence rounding, follows the choice) */
   int32_t elim_passes;      /* elimination passes before each aggregation, 1..16 (1: Section 3.4;
                                more repeat it on its own result while it removes enough) */
+  int32_t merge_path;       /* one-column Laplacian products: 0 degree-class rows only, 1 the
+                               autotuner may pick a merge-path traversal per level, 2 always */
 } lg_setup_opts;
 
 typedef struct lg_hierarchy lg_hierarchy;
@@ -100,6 +102,7 @@ typedef struct {
   double lmax;     /* lambda_max estimate of D^-1 L (aggregation levels) */
   int64_t n_hub;   /* rows split across workgroups by the row scheduler */
   int32_t lane_shift, col_shift; /* row lanes 2^(class - shift) in use (set by the autotuner) */
+  int32_t merge;                 /* 1: one-column products use the merge-path traversal */
 } lg_level_stats;
 
 typedef struct {

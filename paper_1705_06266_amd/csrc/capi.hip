@@ -58,6 +58,7 @@ extern "C" lg_status lg_default_opts(lg_setup_opts* o) {
   o->graphs = 1;
   o->autotune = 1;
   o->elim_passes = 1;
+  o->merge_path = 1;
   return LG_OK;
 }
 
@@ -76,6 +77,7 @@ static const char* check_opts(const lg_setup_opts& o) {
   if (o.graphs != 0 && o.graphs != 1) return "graphs must be 0 or 1";
   if (o.autotune != 0 && o.autotune != 1) return "autotune must be 0 or 1";
   if (o.elim_passes < 1 || o.elim_passes > 16) return "elim_passes must be in 1..16";
+  if (o.merge_path < 0 || o.merge_path > 2) return "merge_path must be 0, 1 or 2";
   return nullptr;
 }
 
@@ -103,6 +105,8 @@ extern "C" lg_status lg_setup(const lg_graph* g, const lg_setup_opts* o, void* h
   LG_HIP(hipGetDevice(&h->device));
   lg::setup_hierarchy(h, g, st);
   lg::alloc_solve_workspace(h, st);
+  if (opts.merge_path == 2)
+    for (auto& L : h->lev) L.sched.merge = true;
   if (opts.autotune) lg::autotune(h, st);
   LG_HIP(hipStreamSynchronize(st));
   h->setup_ms =
@@ -184,6 +188,7 @@ extern "C" lg_status lg_hierarchy_stats(const lg_hierarchy* h, lg_level_stats* o
     out[l].n_hub = L.sched.nhub + L.sched.nsplit;
     out[l].lane_shift = L.sched.lane_shift;
     out[l].col_shift = L.sched.col_shift;
+    out[l].merge = L.sched.merge ? 1 : 0;
   }
   return LG_OK;
 }

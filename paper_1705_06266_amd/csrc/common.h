@@ -216,7 +216,20 @@ struct Sched {
   // lanes (one-column kernels) or lane groups (column-split kernels) of a
   // class-c row: 2^(c - shift), chosen per matrix by the autotuner
   int lane_shift = 1, col_shift = 1;
+  // merge-path tiles for one-column Laplacian products (see k_merge_rows):
+  // tile_row[t] = rows whose end marker precedes merged item t * kMergeTile
+  int64_t ntile = 0;
+  int32_t* tile_row = nullptr;   // [ntile + 1]
+  int32_t* carry_row = nullptr;  // [ntile] row cut by the tile's end, or -1
+  double* carry_val = nullptr;   // [ntile] its partial sum in the tile
+  bool merge = false;            // one-column Laplacian products use the merge path
 };
+
+// Merge path: the rows' entries and end markers form one list of n + nnz
+// items (row r's marker sits at rp[r+1] + r); a workgroup takes kMergeTile
+// consecutive items, whatever the degrees.
+constexpr int kMergeIPT = 8;
+constexpr int64_t kMergeTile = (int64_t)kBlock * kMergeIPT;
 
 // Degree unit of the classes (entries per lane per step of a full-width row).
 constexpr int kPerLane = LG_PER_LANE;
@@ -662,6 +675,127 @@ void run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_t s
                        (const typename Op::Acc*)s.partial, s.nsplit);
     LG_LAUNCH_CHECK();
   }
+}
+
+// ------------------------------------------------------------ merge path
+// One-column products over a fixed share of the merged list per workgroup
+// (Merrill & Garland's merge-based CSR traversal): the tile's products
+// w_e x_col(e) are staged in LDS by coalesced loads, each thread walks
+// kMergeIPT items and finishes the rows whose entries it saw entirely; rows
+// cut between threads get the earlier threads' partial sums from a segmented
+// scan; a row cut by the tile's end is finished by its last tile and the
+// earlier tiles' partials are added by k_merge_fix, through the epilogue's
+// slope (every Laplacian epilogue is affine in the row sum).  All partitions
+// and orders are fixed, so results are deterministic.
+// Op: Val, term(e), slope(row), finish(row, acc, 0, 1), identity().
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_merge_rows(Op op, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ tile_row,
+                                                       int64_t n, int64_t nnz,
+                                                       int32_t* __restrict__ carry_row,
+                                                       double* __restrict__ carry_val) {
+  using T = typename Op::Val;
+  __shared__ T prod[kMergeTile];
+  __shared__ int32_t mpos[kMergeTile];
+  __shared__ T sv[2][kBlock];
+  __shared__ int32_t sf[2][kBlock];
+  const int64_t t = blockIdx.x;
+  const int64_t d0 = t * kMergeTile, d1 = min(d0 + kMergeTile, n + nnz);
+  const int64_t i0 = tile_row[t], i1 = tile_row[t + 1];
+  const int64_t j0 = d0 - i0, j1 = d1 - i1;
+  for (int64_t e = j0 + threadIdx.x; e < j1; e += kBlock) prod[e - j0] = op.term((int)e);
+  for (int64_t r = i0 + threadIdx.x; r < i1; r += kBlock) mpos[r - i0] = (int32_t)(rp[r + 1] + r - d0);
+  __syncthreads();
+  // this thread's items [dk, dk1) and its starting row: markers before dk
+  const int rel0 = (int)min((int64_t)threadIdx.x * kMergeIPT, d1 - d0);
+  const int rel1 = (int)min((int64_t)rel0 + kMergeIPT, d1 - d0);
+  int lo = 0, hi = (int)(i1 - i0);
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (mpos[mid] < rel0) lo = mid + 1;
+    else hi = mid;
+  }
+  int i = lo;                      // row index within the tile
+  int j = rel0 - lo;               // entry index within the tile (items = rows + entries)
+  const int first = i;
+  T run = T(0), first_sum = T(0);
+  bool ended = false;
+  typename Op::Acc acc;
+  for (int pos = rel0; pos < rel1; pos++) {
+    if (i < (int)(i1 - i0) && mpos[i] == pos) {  // row i ends here
+      if (!ended) {
+        first_sum = run;
+        ended = true;
+      } else {  // started and ended inside this thread: complete
+        acc = op.identity();
+        acc.v[0] = run;
+        op.finish(i0 + i, acc, 0, 1);
+      }
+      run = T(0);
+      i++;
+    } else {
+      run += prod[j];
+      j++;
+    }
+  }
+  // segmented inclusive scan of the threads' trailing partials, keyed by row
+  const int k = threadIdx.x;
+  int buf = 0;
+  sv[0][k] = run;
+  sf[0][k] = i;  // the row the trailing partial belongs to
+  __syncthreads();
+  for (int o = 1; o < kBlock; o <<= 1) {
+    T v = sv[buf][k];
+    if (k >= o && sf[buf][k - o] == sf[buf][k]) v += sv[buf][k - o];
+    sv[buf ^ 1][k] = v;
+    sf[buf ^ 1][k] = sf[buf][k];
+    buf ^= 1;
+    __syncthreads();
+  }
+  // rows whose entries began in earlier threads of this tile
+  if (ended) {
+    const T carry_in = (k > 0 && sf[buf][k - 1] == first) ? sv[buf][k - 1] : T(0);
+    acc = op.identity();
+    acc.v[0] = first_sum + carry_in;
+    op.finish(i0 + first, acc, 0, 1);
+  }
+  if (k == kBlock - 1) {
+    const bool cut = i1 < n;  // row i1 continues into the next tile
+    carry_row[t] = cut ? (int32_t)i1 : -1;
+    carry_val[t] = cut ? (double)sv[buf][k] : 0.0;
+  }
+}
+
+// Rows cut by tile ends: add the earlier tiles' partials (in tile order) to
+// the row the following tile finished.
+template <class Op>
+__global__ void k_merge_fix(Op op, const int32_t* __restrict__ carry_row,
+                            const double* __restrict__ carry_val, int64_t ntile) {
+  using T = typename Op::Val;
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= ntile) return;
+  const int32_t r = carry_row[t];
+  if (r < 0 || (t > 0 && carry_row[t - 1] == r)) return;
+  double s = 0.0;
+  for (int64_t u = t; u < ntile && carry_row[u] == r; u++) s += carry_val[u];
+  op.add_to_row(r, (T)s);
+}
+
+template <class Op>
+void run_merge(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st,
+               const char* fam = "", double bytes = 0.0) {
+  if (s.n == 0 || s.ntile == 0) return;
+  {
+    ProfScope ps(fam, st, bytes, true);
+    hipExtLaunchKernelGGL((k_merge_rows<Op>), dim3((unsigned)s.ntile), dim3(kBlock), 0, st,
+                          ps.start(), ps.stop(), 0, op, rp, (const int32_t*)s.tile_row, s.n, s.nnz,
+                          s.carry_row, s.carry_val);
+  }
+  LG_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_merge_fix<Op>), dim3((unsigned)ceil_div(s.ntile, (int64_t)kBlock)),
+                     dim3(kBlock), 0, st, op, (const int32_t*)s.carry_row,
+                     (const double*)s.carry_val, s.ntile);
+  LG_LAUNCH_CHECK();
 }
 
 // ------------------------------------------------------------- memory

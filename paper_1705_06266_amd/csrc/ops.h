@@ -65,6 +65,19 @@ struct LapOp {
 #pragma unroll
     for (int c = 0; c < K; c++) a.v[c] += o.v[c];
   }
+
+  // merge-path interface (one column): an entry's term of the row sum, and
+  // the epilogue's slope d y_row / d(row sum) for partial sums added late
+  using Val = T;
+  __device__ __forceinline__ T term(int e) const {
+    const int j = col[e];
+    return MODE == LAP_CHEB_ZERO ? w[e] * ((dinv[j] * x[j]) * c0) : w[e] * x[j];
+  }
+  __device__ __forceinline__ T slope(int64_t row) const {
+    return MODE == LAP_SPMV ? T(-1) : MODE == LAP_RESID ? T(1) : c2 * dinv[row];
+  }
+  __device__ __forceinline__ void add_to_row(int64_t row, T s) const { y[row] += slope(row) * s; }
+
   __device__ __forceinline__ void finish(int64_t row, const Acc& a, int lane, int G) const {
     const T di = d[row];
 #pragma unroll

@@ -509,6 +509,22 @@ void read_dev(void* host, const void* dev, size_t bytes, hipStream_t st) {
   memcpy(host, pinned, bytes);
 }
 
+// tile_row[t] = rows whose end marker (at rp[r+1] + r) precedes merged item
+// min(t * kMergeTile, n + nnz), by binary search (the positions increase).
+__global__ void k_merge_split(const int32_t* __restrict__ rp, int64_t n, int64_t nnz,
+                              int64_t ntile, int32_t* __restrict__ tile_row) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t > ntile) return;
+  const int64_t d = min(t * kMergeTile, n + nnz);
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)rp[mid + 1] + mid < d) lo = mid + 1;
+    else hi = mid;
+  }
+  tile_row[t] = (int32_t)lo;
+}
+
 void build_sched(Sched& s, const int32_t* rp, int64_t n, int64_t nnz, Arena& keep, Arena& tmp,
                  hipStream_t st) {
   s = Sched();
@@ -575,6 +591,14 @@ void build_sched(Sched& s, const int32_t* rp, int64_t n, int64_t nnz, Arena& kee
       LG_LAUNCH_CHECK();
     }
   }
+  // merge-path tiles
+  s.ntile = ceil_div(n + nnz, kMergeTile);
+  s.tile_row = keep.get<int32_t>(s.ntile + 1);
+  s.carry_row = keep.get<int32_t>(s.ntile);
+  s.carry_val = keep.get<double>(s.ntile);
+  hipLaunchKernelGGL(k_merge_split, dim3((unsigned)ceil_div(s.ntile + 1, kBlock)), dim3(kBlock), 0, st,
+                     rp, n, nnz, s.ntile, s.tile_row);
+  LG_LAUNCH_CHECK();
   tmp.rewind(m);
 }
 

@@ -703,8 +703,14 @@ struct Engine {
                    LapColOp<T, K, MODE>{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2, c0}, st, fam,
                    bytes);
     } else {
-      run_rows(L.sched, L.rp, LapOp<T, K, MODE>{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2, c0}, st,
-               fam, bytes);
+      const LapOp<T, K, MODE> op{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2, c0};
+      if constexpr (K == 1) {
+        if (L.sched.merge) {
+          run_merge(L.sched, L.rp, op, st, fam, bytes);
+          return;
+        }
+      }
+      run_rows(L.sched, L.rp, op, st, fam, bytes);
     }
   }
 
@@ -927,16 +933,20 @@ void lap64(lg_hierarchy* h, int l, const double* x, double* y, const double* b, 
                                                       nullptr, 0.0, 0.0, 0.0},
                    st, fam, bytes);
   } else {
+    auto go = [&](const auto& op) {
+      if constexpr (K == 1) {
+        if (L.sched.merge) {
+          run_merge(L.sched, L.rp, op, st, fam, bytes);
+          return;
+        }
+      }
+      run_rows(L.sched, L.rp, op, st, fam, bytes);
+    };
     if (b)
-      run_rows(L.sched, L.rp,
-               LapOp<double, K, LAP_RESID, TAG>{L.col, L.w, L.d, L.dinv, x, y, b, nullptr, 0.0, 0.0,
-                                                0.0},
-               st, fam, bytes);
+      go(LapOp<double, K, LAP_RESID, TAG>{L.col, L.w, L.d, L.dinv, x, y, b, nullptr, 0.0, 0.0, 0.0});
     else
-      run_rows(L.sched, L.rp,
-               LapOp<double, K, LAP_SPMV, TAG>{L.col, L.w, L.d, L.dinv, x, y, nullptr, nullptr, 0.0,
-                                               0.0, 0.0},
-               st, fam, bytes);
+      go(LapOp<double, K, LAP_SPMV, TAG>{L.col, L.w, L.d, L.dinv, x, y, nullptr, nullptr, 0.0, 0.0,
+                                         0.0});
   }
 }
 
@@ -1233,13 +1243,17 @@ static void autotune_k(lg_hierarchy* h, hipStream_t st) {
     if (L.nnz < kTuneMinNnz || (!agg && l != 0)) continue;
     const bool col = agg ? use_col_split<T, K>() : use_col_split<double, K>();
     int& shift = col ? L.sched.col_shift : L.sched.lane_shift;
+    // candidates: the class-binned kernels at shifts 0, 1, 2, and (one column) the merge path
+    const bool try_merge = K == 1 && h->opts.merge_path == 1;
     const std::vector<int64_t> key{L.n, L.nnz, L.sched.min_deg, L.sched.max_deg, L.sched.nhub,
-                                   L.sched.nsplit, agg ? (int64_t)sizeof(T) : 8, K, col ? 1 : 0};
+                                   L.sched.nsplit, agg ? (int64_t)sizeof(T) : 8, K, col ? 1 : 0,
+                                   h->opts.merge_path};
     {
       std::lock_guard<std::mutex> g(g_tune_mu);
       auto it = g_tune.find(key);
       if (it != g_tune.end()) {
-        shift = it->second;
+        L.sched.merge = it->second < 0;
+        if (it->second >= 0) shift = it->second;
         continue;
       }
     }
@@ -1259,8 +1273,11 @@ static void autotune_k(lg_hierarchy* h, hipStream_t st) {
     }
     int best = shift;
     float best_ms = 0.0f;
-    for (int cand : kTuneShifts) {
-      shift = cand;
+    const int ncand = (int)(sizeof(kTuneShifts) / sizeof(int)) + (try_merge ? 1 : 0);
+    for (int ci = 0; ci < ncand; ci++) {
+      const int cand = ci < (int)(sizeof(kTuneShifts) / sizeof(int)) ? kTuneShifts[ci] : -1;
+      L.sched.merge = cand < 0;
+      if (cand >= 0) shift = cand;
       product();  // warm-up at this shift
       LG_HIP(hipEventRecord(e0, st));
       for (int r = 0; r < 3; r++) product();
@@ -1268,12 +1285,13 @@ static void autotune_k(lg_hierarchy* h, hipStream_t st) {
       LG_HIP(hipEventSynchronize(e1));
       float ms = 0.0f;
       LG_HIP(hipEventElapsedTime(&ms, e0, e1));
-      if (cand == kTuneShifts[0] || ms < best_ms) {
+      if (ci == 0 || ms < best_ms) {
         best_ms = ms;
         best = cand;
       }
     }
-    shift = best;
+    L.sched.merge = best < 0;
+    if (best >= 0) shift = best;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune[key] = best;
   }

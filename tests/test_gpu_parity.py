@@ -306,3 +306,40 @@ def test_eigs_match_the_dense_eigendecomposition(built, name, nev):
     if lam_o[nev] - lam_o[nev - 1] > 1e-3 * lam_o[nev]:
         s = np.linalg.svd(V[:, :nev].T @ X, compute_uv=False)
         assert s.min() >= 1.0 - 1e-8
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_merge_path_products_cycles_and_solves(built, name):
+    """One-column products through the merge-path traversal (merge_path=2):
+    every level's L x, one cycle and the fp64 solve against the oracle, a
+    mixed-precision solve to the residual target."""
+    g = CASES[name]()
+    say(f"[case] {name} merge path")
+    h = gpu_setup(g, merge_path=2)
+    ho = oracle.Hierarchy(g, oracle_opts(h.opts))
+    rng = np.random.default_rng(3)
+    for l, s in enumerate(lg.lg_hierarchy_stats(h)):
+        x = rng.standard_normal((s["n"], 1))
+        y = torch_empty(s["n"])
+        lg.lg_spmv(h, l, to_dev(x), y)
+        yo = ho.spmv(l, x[:, 0])
+        assert np.abs(y.cpu().numpy()[:, 0] - yo).max() <= 1e-12 * (np.abs(yo).max() + 1e-300), l
+    b = gg.rhs(g.n, 1, 7)[:, 0]
+    b -= b.mean()
+    xc = lg.lg_cycle(h, to_dev(b[:, None])).cpu().numpy()[:, 0]
+    xco = ho.cycle(b)
+    assert np.linalg.norm(xc - xco) <= 1e-10 * np.linalg.norm(xco)
+    X, info, st = lg.lg_solve(h, to_dev(b[:, None]), rtol=1e-8, max_iter=300)
+    xo, sto, ito, relo, _ = ho.solve(b, 1e-8, 300)
+    assert st == 0 and abs(info[0]["iters"] - ito) <= 1
+    diff = dense_laplacian_norm(g, X.cpu().numpy()[:, 0] - xo) / dense_laplacian_norm(g, xo)
+    assert diff <= 1e-6
+    hm = gpu_setup(g, merge_path=2, precision=lg.LG_MIXED)
+    Xm, infm, stm = lg.lg_solve(hm, to_dev(b[:, None]), rtol=1e-8, max_iter=300)
+    assert stm == 0 and infm[0]["rel_residual"] <= 1e-8
+
+
+def torch_empty(n):
+    import torch
+
+    return torch.empty((n, 1), dtype=torch.float64, device="cuda:0")
