@@ -88,8 +88,9 @@ typedef struct {
                                structure; summation order, hence rounding, follows the choice) */
   int32_t elim_passes;      /* elimination passes before each aggregation, 1..16 (1: Section 3.4;
                                more repeat it on its own result while it removes enough) */
-  int32_t merge_path;       /* one-column Laplacian products: 0 degree-class rows only, 1 the
-                               autotuner may pick a merge-path traversal per level, 2 always */
+  int32_t merge_path;       /* one-column Laplacian products: 0 degree-class rows only (default),
+                               1 the autotuner may pick a merge-path traversal per level, 2 every
+                               level uses it (the autotuner then leaves one-column levels alone) */
 } lg_setup_opts;
 
 typedef struct lg_hierarchy lg_hierarchy;

@@ -58,7 +58,7 @@ extern "C" lg_status lg_default_opts(lg_setup_opts* o) {
   o->graphs = 1;
   o->autotune = 1;
   o->elim_passes = 1;
-  o->merge_path = 1;
+  o->merge_path = 0;
   return LG_OK;
 }
 

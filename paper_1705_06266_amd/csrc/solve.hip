@@ -1242,6 +1242,7 @@ static void autotune_k(lg_hierarchy* h, hipStream_t st) {
     const bool agg = L.type == LG_LEVEL_AGG;
     if (L.nnz < kTuneMinNnz || (!agg && l != 0)) continue;
     const bool col = agg ? use_col_split<T, K>() : use_col_split<double, K>();
+    if (K == 1 && h->opts.merge_path == 2) continue;  // one-column products forced to the merge path
     int& shift = col ? L.sched.col_shift : L.sched.lane_shift;
     // candidates: the class-binned kernels at shifts 0, 1, 2, and (one column) the merge path
     const bool try_merge = K == 1 && h->opts.merge_path == 1;

@@ -316,6 +316,7 @@ def test_merge_path_products_cycles_and_solves(built, name):
     g = CASES[name]()
     say(f"[case] {name} merge path")
     h = gpu_setup(g, merge_path=2)
+    assert all(s["merge"] == 1 for s in lg.lg_hierarchy_stats(h))
     ho = oracle.Hierarchy(g, oracle_opts(h.opts))
     rng = np.random.default_rng(3)
     for l, s in enumerate(lg.lg_hierarchy_stats(h)):
