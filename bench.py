@@ -159,7 +159,7 @@ def pmc_summary(args):
              f"reads {f_['calibration_kib']:.0f} KiB -> scale {f_['scale']:.4f} -> "
              f"{f_['bytes_per_launch'] / 1e6:.2f} MB read per dispatch",
              f"WRITE_SIZE {w_['kib_per_launch_raw']:.1f} KiB/dispatch; calibration copy of 512 MiB "
-             f"reads {w_['calibration_kib']:.0f} KiB -> scale {w_['scale']:.4f} -> "
+             f"writes {w_['calibration_kib']:.0f} KiB -> scale {w_['scale']:.4f} -> "
              f"{w_['bytes_per_launch'] / 1e6:.2f} MB written per dispatch",
              f"HBM traffic {rec['hbm_bytes_per_launch'] / 1e6:.2f} MB per dispatch",
              "", "json: " + json.dumps(rec)]
@@ -202,14 +202,21 @@ def trace_summary(args):
     if target:
         lines.append(f"roofline kernel {wl['kernel']}: {int(target['Calls'])} calls, "
                      f"average {float(target['AverageNs']) / 1e3:.2f} us (rocprofv3)")
-    if args.bench_log:
-        with open(args.bench_log) as f:
+    logs = [("same run under the profiler", args.bench_log),
+            ("default run without the profiler", args.plain_log)]
+    for what, log in logs:
+        if not log:
+            continue
+        with open(log) as f:
             rec = json.loads([ln for ln in f if ln.startswith("{")][-1])
         r = rec["roofline"]
-        lines.append(f"same run, HIP events in bench.py over the timed steps: {r['launches']} launches, "
+        lines.append(f"{what}, HIP events in bench.py over the timed steps: {r['launches']} launches, "
                      f"average {r['avg_launch_ms'] * 1e3:.2f} us, "
                      f"{r['algorithmic_bytes_per_launch'] / 1e6:.2f} MB algorithmic per launch, "
                      f"{r['achieved']:.0f} GB/s")
+    if args.bench_log and args.plain_log:
+        lines.append("(kernel tracing adds time to the events that bracket each dispatch; the "
+                     "kernel's own duration is the rocprofv3 figure, which the unprofiled events match)")
     os.makedirs(PROFILES, exist_ok=True)
     path = os.path.join(PROFILES, f"{wl['family']}_{args.workload}_kernel_stats.txt")
     with open(path, "w") as f:
@@ -356,6 +363,7 @@ def main():
                     help="one-column products: 0 class rows, 1 tuner's choice, 2 merge path")
     ap.add_argument("--command", default="", help="command line recorded in summaries")
     ap.add_argument("--bench-log", default=None, help="bench output of the profiled run (summaries)")
+    ap.add_argument("--plain-log", default=None, help="bench output of a run without the profiler (summaries)")
     args = ap.parse_args()
 
     if args.pmc_summary:
