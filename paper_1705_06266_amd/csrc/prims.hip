@@ -170,25 +170,76 @@ extern "C" const char* lg_profile_names(void) {
 namespace lg {
 
 // ------------------------------------------------------------------- scan
+// Reduce-then-scan over tiles of kScanTile items; each thread owns kScanIPT
+// consecutive items, moved with 16-byte vector loads and stores when the
+// buffers are 16-byte aligned.  Pass 1 writes tile sums, the sums are scanned
+// (recursively), pass 2 writes out[i] = tile offset + in-tile prefix.
 constexpr int kScanIPT = 8;
 constexpr int kScanTile = kBlock * kScanIPT;
 
 template <typename TI>
-__global__ __launch_bounds__(kBlock) void k_scan_tiles(const TI* __restrict__ in,
-                                                       int64_t* __restrict__ out,
-                                                       int64_t* __restrict__ sums, int64_t n,
-                                                       int64_t* __restrict__ total) {
-  __shared__ int64_t wsum[kBlock / 64];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  int64_t v[kScanIPT];
+__device__ __forceinline__ void scan_load8(const TI* __restrict__ in, int64_t i0, int64_t n,
+                                           bool vec, int64_t v[kScanIPT]) {
+  if (vec && i0 + kScanIPT <= n) {
+    if constexpr (sizeof(TI) == 4) {
+      const int4* p = reinterpret_cast<const int4*>(in + i0);
+      const int4 a = p[0], b = p[1];
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+      v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+      const longlong2* p = reinterpret_cast<const longlong2*>(in + i0);
+#pragma unroll
+      for (int k = 0; k < kScanIPT / 2; k++) {
+        const longlong2 a = p[k];
+        v[2 * k] = a.x;
+        v[2 * k + 1] = a.y;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanIPT; k++) v[k] = i0 + k < n ? (int64_t)in[i0 + k] : 0;
+  }
+}
+
+// Block-wide sum of one value per thread (valid in every thread).
+__device__ __forceinline__ int64_t block_sum_i64(int64_t x, int64_t* wsum) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  if (lane == 0) wsum[w] = x;
+  __syncthreads();
   int64_t s = 0;
 #pragma unroll
-  for (int k = 0; k < kScanIPT; k++) {
-    const int64_t i = base + (int64_t)t * kScanIPT + k;
-    v[k] = i < n ? (int64_t)in[i] : 0;
-    s += v[k];
-  }
+  for (int k = 0; k < kBlock / 64; k++) s += wsum[k];
+  return s;
+}
+
+template <typename TI>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const TI* __restrict__ in, int64_t n,
+                                                        bool vec, int64_t* __restrict__ sums) {
+  __shared__ int64_t wsum[kBlock / 64];
+  int64_t v[kScanIPT];
+  scan_load8(in, (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIPT, n, vec, v);
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanIPT; k++) s += v[k];
+  s = block_sum_i64(s, wsum);
+  if (threadIdx.x == 0) sums[blockIdx.x] = s;
+}
+
+// offs == nullptr: a single tile.  The last tile also writes out[n], the total.
+template <typename TI>
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const TI* __restrict__ in,
+                                                       int64_t* __restrict__ out, int64_t n,
+                                                       bool vec, const int64_t* __restrict__ offs) {
+  __shared__ int64_t wsum[kBlock / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * kScanTile + (int64_t)t * kScanIPT;
+  int64_t v[kScanIPT];
+  scan_load8(in, i0, n, vec, v);
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanIPT; k++) s += v[k];
   int64_t x = s;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -197,27 +248,27 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const TI* __restrict__ in
   }
   if (lane == 63) wsum[w] = x;
   __syncthreads();
-  int64_t wpre = 0;
-  for (int k = 0; k < w; k++) wpre += wsum[k];
-  int64_t run = wpre + x - s;
+  int64_t run = offs ? offs[blockIdx.x] : 0;
+  for (int k = 0; k < w; k++) run += wsum[k];
+  run += x - s;
+  int64_t r[kScanIPT];
 #pragma unroll
   for (int k = 0; k < kScanIPT; k++) {
-    const int64_t i = base + (int64_t)t * kScanIPT + k;
-    if (i < n) out[i] = run;
+    r[k] = run;
     run += v[k];
   }
-  if (t == kBlock - 1) {
-    sums[blockIdx.x] = wpre + x;
-    if (total) *total = wpre + x;  // single-tile scan: the tile sum is the total
+  if (vec && i0 + kScanIPT <= n) {
+    longlong2* p = reinterpret_cast<longlong2*>(out + i0);
+#pragma unroll
+    for (int k = 0; k < kScanIPT / 2; k++) p[k] = make_longlong2(r[2 * k], r[2 * k + 1]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanIPT; k++)
+      if (i0 + k < n) out[i0 + k] = r[k];
   }
+  if (blockIdx.x == gridDim.x - 1 && t == kBlock - 1) out[n] = run;
 }
 
-// out[i] += offset of its tile for i < n; out[n] = total (offs[nb]).
-__global__ void k_scan_add(int64_t* __restrict__ out, const int64_t* __restrict__ offs, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) out[i] += offs[i / kScanTile];
-  else if (i == n) out[n] = offs[(n + kScanTile - 1) / kScanTile];
-}
 __global__ void k_zero_i64(int64_t* dst) { *dst = 0; }
 
 template <typename TI>
@@ -227,15 +278,19 @@ static void scan_core(const TI* in, int64_t* out, int64_t n, Arena& tmp, hipStre
     return;
   }
   const int64_t nb = ceil_div(n, kScanTile);
-  int64_t* sums = tmp.get<int64_t>(nb);
-  hipLaunchKernelGGL((k_scan_tiles<TI>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, out, sums, n,
-                     nb == 1 ? out + n : (int64_t*)nullptr);
+  const bool vec = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+  const int64_t* offs = nullptr;
   if (nb > 1) {
-    int64_t* offs = tmp.get<int64_t>(nb + 1);
-    scan_core<int64_t>(sums, offs, nb, tmp, st);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)ceil_div(n + 1, kBlock)), dim3(kBlock), 0, st, out,
-                       offs, n);
+    int64_t* sums = tmp.get<int64_t>(nb);
+    int64_t* o = tmp.get<int64_t>(nb + 1);
+    hipLaunchKernelGGL((k_scan_reduce<TI>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, vec,
+                       sums);
+    LG_LAUNCH_CHECK();
+    scan_core<int64_t>(sums, o, nb, tmp, st);
+    offs = o;
   }
+  hipLaunchKernelGGL((k_scan_tiles<TI>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, out, n, vec,
+                     offs);
   LG_LAUNCH_CHECK();
 }
 
@@ -266,8 +321,16 @@ int64_t scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, Arena& tmp, 
 }
 
 // ------------------------------------------------------------- radix sort
-constexpr int kRadixIPT = 16;
+constexpr int kRadixIPT = 8;
 constexpr int kRadixTile = kBlock * kRadixIPT;
+constexpr int kBlockSortMax = 2 * kRadixTile;  // sorted by one workgroup in LDS
+constexpr int kBlockSortRounds = kBlockSortMax / kBlock;
+constexpr int kMaxDigits = 8;
+
+struct RadixShifts {
+  int count;
+  int s[kMaxDigits];
+};
 
 // Digit of a key.  pack > 0: the key holds a pair (hi << 32 | lo) with
 // hi, lo < 2^pack, and digits are taken from the contiguous (hi << pack | lo),
@@ -275,6 +338,55 @@ constexpr int kRadixTile = kBlock * kRadixIPT;
 __device__ __forceinline__ int radix_digit(uint64_t key, int shift, int pack) {
   if (pack) key = ((key >> 32) << pack) | (key & 0xffffffffULL);
   return (int)((key >> shift) & 255);
+}
+
+// Exclusive prefix sum of one int per thread over a kBlock-thread workgroup.
+__device__ __forceinline__ int block_excl_scan(int v, int* wtot) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wtot[w] = x;
+  __syncthreads();
+  int pre = 0;
+  for (int k = 0; k < w; k++) pre += wtot[k];
+  __syncthreads();
+  return pre + x - v;
+}
+
+// One round of a stable counting sort: the workgroup's threads hold one item
+// each, in index order.  Returns the item's position run[d] + (items of
+// earlier waves with digit d) + (earlier lanes of this wave with digit d) and
+// advances run[] past the round's items.
+__device__ __forceinline__ int radix_round(bool valid, int d, int* run, int (*wc)[256]) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; k++) wc[k][t] = 0;
+  __syncthreads();
+  const uint64_t lt = (lane == 0) ? 0ULL : ((~0ULL) >> (64 - lane));
+  uint64_t peers = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; b++) {
+    const int bit = (d >> b) & 1;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  if (valid && (int)(__ffsll((unsigned long long)peers) - 1) == lane) wc[w][d] = __popcll(peers);
+  __syncthreads();
+  int pos = 0;
+  if (valid) {
+    pos = run[d] + __popcll(peers & lt);
+    for (int k = 0; k < w; k++) pos += wc[k][d];
+  }
+  __syncthreads();
+  int add = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; k++) add += wc[k][t];
+  run[t] += add;
+  return pos;
 }
 
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n,
@@ -285,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t* __restric
   cnt[t] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kRadixTile;
-#pragma unroll 4
+#pragma unroll
   for (int r = 0; r < kRadixIPT; r++) {
     const int64_t i = base + (int64_t)r * kBlock + t;
     if (i < n) atomicAdd(&cnt[radix_digit(keys[i], shift, pack)], 1);
@@ -294,22 +406,28 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t* __restric
   hist[(int64_t)t * nb + blockIdx.x] = cnt[t];
 }
 
-// Stable scatter: items are visited in (round, thread) order, which is their
-// index order inside the tile; equal digits keep that order.
+// Stable scatter of one tile.  The tile is first ordered by digit in LDS
+// (items ranked in index order), then written out so that consecutive threads
+// store consecutive positions of a digit's output range.  offs is the
+// exclusive scan of the digit-major histogram (256 * nb + 1 entries).
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     const uint64_t* __restrict__ kin, const uint64_t* __restrict__ vin, uint64_t* __restrict__ kout,
     uint64_t* __restrict__ vout, int64_t n, int shift, int pack, const int64_t* __restrict__ offs,
     int64_t nb) {
-  __shared__ int64_t run[256];
+  __shared__ uint64_t sk[kRadixTile], sv[kRadixTile];
+  __shared__ int64_t gbase[256];
+  __shared__ int run[256];
   __shared__ int wc[kBlock / 64][256];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  run[t] = offs[(int64_t)t * nb + blockIdx.x];
-  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
-  const uint64_t lt = (lane == 0) ? 0ULL : ((~0ULL) >> (64 - lane));
+  __shared__ int wtot[kBlock / 64];
+  const int t = threadIdx.x;
+  const int64_t b = blockIdx.x, base = b * kRadixTile;
+  const int64_t o0 = offs[(int64_t)t * nb + b];
+  const int c = (int)(offs[(int64_t)t * nb + b + 1] - o0);
+  const int ex = block_excl_scan(c, wtot);
+  run[t] = ex;
+  gbase[t] = o0 - ex;
+  // radix_round's first barrier publishes run[]
   for (int r = 0; r < kRadixIPT; r++) {
-#pragma unroll
-    for (int k = 0; k < kBlock / 64; k++) wc[k][t] = 0;
-    __syncthreads();
     const int64_t i = base + (int64_t)r * kBlock + t;
     const bool valid = i < n;
     uint64_t key = 0, val = 0;
@@ -319,28 +437,65 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
       val = vin[i];
       d = radix_digit(key, shift, pack);
     }
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; b++) {
-      const int bit = (d >> b) & 1;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
-    }
-    const int rank = __popcll(peers & lt);
-    if (valid && (int)(__ffsll((unsigned long long)peers) - 1) == lane) wc[w][d] = __popcll(peers);
-    __syncthreads();
+    const int pos = radix_round(valid, d, run, wc);
     if (valid) {
-      int64_t pos = run[d] + rank;
-      for (int k = 0; k < w; k++) pos += wc[k][d];
-      kout[pos] = key;
-      vout[pos] = val;
+      sk[pos] = key;
+      sv[pos] = val;
+    }
+  }
+  __syncthreads();
+  const int cnt = (int)min((int64_t)kRadixTile, n - base);
+  for (int j = t; j < cnt; j += kBlock) {
+    const uint64_t key = sk[j];
+    const int64_t pos = gbase[radix_digit(key, shift, pack)] + j;
+    kout[pos] = key;
+    vout[pos] = sv[j];
+  }
+}
+
+// All digit passes of a sort of n <= kBlockSortMax pairs in one workgroup.
+__global__ __launch_bounds__(kBlock) void k_radix_block_sort(uint64_t* __restrict__ keys,
+                                                             uint64_t* __restrict__ vals, int n,
+                                                             RadixShifts sh, int pack) {
+  __shared__ uint64_t sk[kBlockSortMax], sv[kBlockSortMax];
+  __shared__ int cnt[256], run[256];
+  __shared__ int wc[kBlock / 64][256];
+  __shared__ int wtot[kBlock / 64];
+  const int t = threadIdx.x;
+  for (int j = t; j < n; j += kBlock) {
+    sk[j] = keys[j];
+    sv[j] = vals[j];
+  }
+  for (int p = 0; p < sh.count; p++) {
+    const int shift = sh.s[p];
+    cnt[t] = 0;
+    __syncthreads();
+    for (int j = t; j < n; j += kBlock) atomicAdd(&cnt[radix_digit(sk[j], shift, pack)], 1);
+    __syncthreads();
+    run[t] = block_excl_scan(cnt[t], wtot);
+    uint64_t k[kBlockSortRounds], v[kBlockSortRounds];
+#pragma unroll
+    for (int r = 0; r < kBlockSortRounds; r++) {
+      const int j = r * kBlock + t;
+      k[r] = j < n ? sk[j] : 0;
+      v[r] = j < n ? sv[j] : 0;
+    }
+    // radix_round's first barrier orders these reads before the writes below
+#pragma unroll
+    for (int r = 0; r < kBlockSortRounds; r++) {
+      const bool valid = r * kBlock + t < n;
+      const int d = valid ? radix_digit(k[r], shift, pack) : 0;
+      const int pos = radix_round(valid, d, run, wc);
+      if (valid) {
+        sk[pos] = k[r];
+        sv[pos] = v[r];
+      }
     }
     __syncthreads();
-    int add = 0;
-#pragma unroll
-    for (int k = 0; k < kBlock / 64; k++) add += wc[k][t];
-    run[t] += add;
-    __syncthreads();
+  }
+  for (int j = t; j < n; j += kBlock) {
+    keys[j] = sk[j];
+    vals[j] = sv[j];
   }
 }
 
@@ -367,6 +522,15 @@ void radix_sort_pairs(uint64_t* keys, uint64_t* vals, int64_t n, const std::vect
                       Arena& tmp, hipStream_t st, int pack) {
   if (n <= 1 || shifts.empty()) return;
   ProfScope prof_scope("radix", st, (double)n * 32.0 * shifts.size());
+  if (n <= kBlockSortMax && (int)shifts.size() <= kMaxDigits) {
+    RadixShifts sh{};
+    sh.count = (int)shifts.size();
+    for (int k = 0; k < sh.count; k++) sh.s[k] = shifts[k];
+    hipLaunchKernelGGL(k_radix_block_sort, dim3(1), dim3(kBlock), 0, st, keys, vals, (int)n, sh,
+                       pack);
+    LG_LAUNCH_CHECK();
+    return;
+  }
   Arena::Mark m = tmp.mark();
   const int64_t nb = ceil_div(n, kRadixTile);
   uint64_t* k2 = tmp.get<uint64_t>(n);

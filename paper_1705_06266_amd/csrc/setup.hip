@@ -44,12 +44,21 @@ struct NoAcc {
 
 // Section 2.1: weights positive, undirected (w_ij = w_ji), no self-loops;
 // plus the CSR rules (columns in range, strictly increasing).  One thread per
-// stored entry, so a hub row costs no more than its entries.
+// stored entry.  Symmetry: of the two entries (i, j) and (j, i) of a pair only
+// the one whose partner lies in the shorter row (ties by index) searches for
+// it, and counts itself.  With strictly increasing rows and no self-loops the
+// searching entries map one-to-one onto distinct non-searching partners, so
+// the matrix is symmetric iff every search succeeds with an equal weight and
+// exactly half of the entries search (k_validate_pairs).
+constexpr int kValidateSlots = 64;
+
 __global__ void k_validate(const int32_t* __restrict__ rowidx, const int32_t* __restrict__ rp,
                            const int32_t* __restrict__ col, const double* __restrict__ w,
-                           int64_t n, int64_t nnz, int* __restrict__ flags) {
+                           int64_t n, int64_t nnz, int* __restrict__ flags,
+                           unsigned long long* __restrict__ searched) {
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   int f = 0;
+  bool srch = false;
   if (e < nnz) {
     const int row = rowidx[e];
     const int j = col[e];
@@ -57,26 +66,44 @@ __global__ void k_validate(const int32_t* __restrict__ rowidx, const int32_t* __
       f = F_COL;
     } else {
       if (j == row) f |= F_LOOP;
-      if (e > rp[row] && col[e - 1] >= j) f |= F_ORDER;
+      const int r0 = rp[row];
+      if (e > r0 && col[e - 1] >= j) f |= F_ORDER;
       const double we = w[e];
       if (!(we > 0.0) || !__builtin_isfinite(we)) f |= F_WEIGHT;
-      int lo = rp[j], hi = rp[j + 1] - 1, found = -1;
-      while (lo <= hi) {
-        const int mid = lo + ((hi - lo) >> 1);
-        const int c = col[mid];
-        if (c == row) {
-          found = mid;
-          break;
+      int lo = rp[j], hi = rp[j + 1] - 1;
+      const int dj = hi + 1 - lo, di = rp[row + 1] - r0;
+      srch = dj < di || (dj == di && j < row);
+      if (srch) {
+        int found = -1;
+        while (lo <= hi) {
+          const int mid = lo + ((hi - lo) >> 1);
+          const int c = col[mid];
+          if (c == row) {
+            found = mid;
+            break;
+          }
+          if (c < row) lo = mid + 1;
+          else hi = mid - 1;
         }
-        if (c < row) lo = mid + 1;
-        else hi = mid - 1;
+        if (found < 0 || w[found] != we) f |= F_ASYM;
       }
-      if (found < 0 || w[found] != we) f |= F_ASYM;
     }
   }
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) f |= __shfl_xor(f, m);
-  if ((threadIdx.x & 63) == 0 && f) atomicOr(flags, f);
+  const unsigned long long cnt = __popcll(__ballot(srch));
+  if ((threadIdx.x & 63) == 0) {
+    if (f) atomicOr(flags, f);
+    if (cnt) atomicAdd(&searched[(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) % kValidateSlots], cnt);
+  }
+}
+
+__global__ void k_validate_pairs(const unsigned long long* __restrict__ searched, int64_t nnz,
+                                 int* __restrict__ flags) {
+  unsigned long long v = threadIdx.x < kValidateSlots ? searched[threadIdx.x] : 0ULL;
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+  if (threadIdx.x == 0 && 2 * v != (unsigned long long)nnz) atomicOr(flags, F_ASYM);
 }
 
 // ------------------------------------------------------------ connectivity
@@ -1210,9 +1237,14 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
   if (o.validate && nnz) {
     Arena::Mark m = c.tmp.mark();
     int32_t* rowidx = c.tmp.get<int32_t>(nnz);
+    unsigned long long* searched = c.tmp.get<unsigned long long>(kValidateSlots);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, st, (int32_t*)searched,
+                       (int64_t)(2 * kValidateSlots), 0);
     run_rows(L0->sched, L0->rp, RowIdxOp{rowidx}, st);
     hipLaunchKernelGGL(k_validate, dim3(nblk(nnz)), dim3(kBlock), 0, st, rowidx, L0->rp, L0->col,
-                       L0->w, n, nnz, c.flags);
+                       L0->w, n, nnz, c.flags, searched);
+    hipLaunchKernelGGL(k_validate_pairs, dim3(1), dim3(64), 0, st, (const unsigned long long*)searched,
+                       nnz, c.flags);
     LG_LAUNCH_CHECK();
     check_flags(c);
     c.tmp.rewind(m);
