@@ -21,7 +21,7 @@ FLAGS = [
     # never emit packed-fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
-]
+] + os.environ.get("LGMG_HIPCC_FLAGS", "").split()
 
 
 def sources():

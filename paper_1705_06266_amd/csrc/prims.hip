@@ -295,11 +295,9 @@ static void scan_core(const TI* in, int64_t* out, int64_t n, Arena& tmp, hipStre
 }
 
 int64_t read_i64(const int64_t* dev, hipStream_t st) {
-  static thread_local int64_t* pinned = nullptr;
-  if (!pinned) LG_HIP(hipHostMalloc((void**)&pinned, sizeof(int64_t), hipHostMallocDefault));
-  LG_HIP(hipMemcpyAsync(pinned, dev, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  LG_HIP(hipStreamSynchronize(st));
-  return *pinned;
+  int64_t v = 0;
+  read_dev(&v, dev, sizeof(v), st);
+  return v;
 }
 
 int64_t scan_i64(const int64_t* in, int64_t* out, int64_t n, Arena& tmp, hipStream_t st,
@@ -664,13 +662,59 @@ __global__ void k_zero_i32n(int32_t* p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
+// Small device values the host needs (sizes, flags, convergence scalars) are
+// read through a mailbox: a one-workgroup kernel copies them into
+// fine-grained (coherent) pinned host memory, makes them visible system-wide
+// and then writes a sequence number there, which the host polls.  This skips
+// the copy-engine round trip and the stream-synchronisation wake-up.  Each
+// host thread owns one mailbox (kept until the process ends).
+constexpr int kMailHeader = 16;     // 32-bit words before the data
+constexpr size_t kMailBytes = 65536;  // largest read
+
+__global__ void k_mail(const uint32_t* __restrict__ src, int words, uint32_t* __restrict__ box,
+                       uint32_t seq) {
+  for (int i = threadIdx.x; i < words; i += blockDim.x) box[kMailHeader + i] = src[i];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(box, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 void read_dev(void* host, const void* dev, size_t bytes, hipStream_t st) {
-  static thread_local char* pinned = nullptr;
-  if (!pinned) LG_HIP(hipHostMalloc((void**)&pinned, 4096, hipHostMallocDefault));
-  if (bytes > 4096) fail(LG_E_ARG, "read_dev: too large");
-  LG_HIP(hipMemcpyAsync(pinned, dev, bytes, hipMemcpyDeviceToHost, st));
-  LG_HIP(hipStreamSynchronize(st));
-  memcpy(host, pinned, bytes);
+  if (bytes == 0) return;
+  if (bytes > kMailBytes) fail(LG_E_ARG, "read_dev: too large");
+  if ((bytes & 3) || (reinterpret_cast<uintptr_t>(dev) & 3)) {
+    static thread_local char* pinned = nullptr;
+    if (!pinned) LG_HIP(hipHostMalloc((void**)&pinned, kMailBytes, hipHostMallocDefault));
+    LG_HIP(hipMemcpyAsync(pinned, dev, bytes, hipMemcpyDeviceToHost, st));
+    LG_HIP(hipStreamSynchronize(st));
+    memcpy(host, pinned, bytes);
+    return;
+  }
+  static thread_local uint32_t* box = nullptr;
+  static thread_local uint32_t* box_dev = nullptr;
+  static thread_local uint32_t seq = 0;
+  if (!box) {
+    LG_HIP(hipHostMalloc((void**)&box, kMailHeader * 4 + kMailBytes,
+                         hipHostMallocCoherent | hipHostMallocMapped | hipHostMallocPortable));
+    LG_HIP(hipHostGetDevicePointer((void**)&box_dev, box, 0));
+    __atomic_store_n(box, 0u, __ATOMIC_RELAXED);
+  }
+  if (++seq == 0) seq = 1;  // 0 is the initial value
+  hipLaunchKernelGGL(k_mail, dim3(1), dim3(kBlock), 0, st, (const uint32_t*)dev, (int)(bytes / 4),
+                     box_dev, seq);
+  LG_LAUNCH_CHECK();
+  for (uint64_t spin = 1; __atomic_load_n(box, __ATOMIC_ACQUIRE) != seq; spin++) {
+    if (spin % 1024) continue;
+    const hipError_t e = hipStreamQuery(st);
+    if (e == hipErrorNotReady) continue;
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(LG_E_HIP, std::string("HIP error: ") + hipGetErrorString(e));
+    }
+    if (__atomic_load_n(box, __ATOMIC_ACQUIRE) != seq)
+      fail(LG_E_HIP, "device read: the stream finished without publishing the value");
+  }
+  memcpy(host, box + kMailHeader, bytes);
 }
 
 // tile_row[t] = rows whose end marker (at rp[r+1] + r) precedes merged item

@@ -839,11 +839,30 @@ __global__ void k_copy_f64(const double* __restrict__ in, double* __restrict__ o
 // ===================================================================== host
 namespace {
 
+// A second stream for work that only reads finished levels (Lanczos), so it
+// fills the gaps of the level construction.  Its destructor waits for it, so
+// an error thrown mid-setup cannot release memory the stream still reads.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t ready = nullptr, done = nullptr;
+  SideStream() = default;
+  SideStream(const SideStream&) = delete;
+  SideStream& operator=(const SideStream&) = delete;
+  ~SideStream() {
+    if (s) (void)hipStreamSynchronize(s);
+    if (ready) (void)hipEventDestroy(ready);
+    if (done) (void)hipEventDestroy(done);
+  }
+};
+
 struct Ctx {
   lg_hierarchy* h;
   hipStream_t st;
   TempArena lease;
   Arena& tmp = *lease.a;
+  TempArena side_lease;  // side-stream temporaries, kept until setup ends
+  Arena& side_tmp = *side_lease.a;
+  SideStream side;  // declared after the arenas: joined before they are released
   int* flags = nullptr;  // device error flags
   int64_t* pair = nullptr;  // two device words for reading totals back together
   uint64_t key = 0;
@@ -851,8 +870,7 @@ struct Ctx {
 
 void check_flags(Ctx& c) {
   int f = 0;
-  LG_HIP(hipMemcpyAsync(&f, c.flags, sizeof(int), hipMemcpyDeviceToHost, c.st));
-  LG_HIP(hipStreamSynchronize(c.st));
+  read_dev(&f, c.flags, sizeof(int), c.st);
   if (f & F_ROWPTR) fail(LG_E_GRAPH, "row pointers are not a valid CSR offset array");
   if (f & F_COL) fail(LG_E_GRAPH, "column index out of range");
   if (f & F_LOOP) fail(LG_E_GRAPH, "self-loop (diagonal entry) in the adjacency");
@@ -1118,9 +1136,14 @@ void galerkin(Ctx& c, Level& L, int64_t nc, Level& out) {
 }
 
 // lambda_max(D^-1 L) by eig_iters Lanczos steps in the D inner product.
+// Runs on the side stream after the work queued so far on the main stream;
+// setup_hierarchy joins the streams before reading the results.
 void lanczos(Ctx& c, Level& L, int level, double* out) {
   const lg_setup_opts& o = c.h->opts;
-  Arena& tmp = c.tmp;
+  const hipStream_t st = c.side.s;
+  LG_HIP(hipEventRecord(c.side.ready, c.st));
+  LG_HIP(hipStreamWaitEvent(st, c.side.ready, 0));
+  Arena& tmp = c.side_tmp;
   const int64_t n = L.n;
   double* q = tmp.get<double>(n);
   double* qp = tmp.get<double>(n);
@@ -1128,27 +1151,27 @@ void lanczos(Ctx& c, Level& L, int level, double* out) {
   double* lz = tmp.get<double>(LZ_SIZE);
   double* part = tmp.get<double>(kRedBlocks);
   const int steps = std::min(o.eig_iters, 64);
-  hipLaunchKernelGGL(k_lz_init_scalars, dim3(1), dim3(64), 0, c.st, lz);
+  hipLaunchKernelGGL(k_lz_init_scalars, dim3(1), dim3(64), 0, st, lz);
   if (n < 2 || steps < 1) {
-    hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(64), 0, c.st, lz, out);
+    hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(64), 0, st, lz, out);
     return;
   }
-  hipLaunchKernelGGL(k_lz_start, dim3(nblk(n)), dim3(kBlock), 0, c.st, q, qp, n, c.key, level);
-  reduce_dev<RED_SUM>(q, nullptr, nullptr, n, part, lz + LZ_SUM, c.st);
-  hipLaunchKernelGGL(k_lz_center, dim3(nblk(n)), dim3(kBlock), 0, c.st, q, n, lz);
-  reduce_dev<RED_DDOT>(q, nullptr, L.d, n, part, lz + LZ_B2, c.st);
-  hipLaunchKernelGGL(k_lz_scale, dim3(nblk(n)), dim3(kBlock), 0, c.st, q, n, lz);
+  hipLaunchKernelGGL(k_lz_start, dim3(nblk(n)), dim3(kBlock), 0, st, q, qp, n, c.key, level);
+  reduce_dev<RED_SUM>(q, nullptr, nullptr, n, part, lz + LZ_SUM, st);
+  hipLaunchKernelGGL(k_lz_center, dim3(nblk(n)), dim3(kBlock), 0, st, q, n, lz);
+  reduce_dev<RED_DDOT>(q, nullptr, L.d, n, part, lz + LZ_B2, st);
+  hipLaunchKernelGGL(k_lz_scale, dim3(nblk(n)), dim3(kBlock), 0, st, q, n, lz);
   for (int j = 0; j < steps; j++) {
     LapOp<double, 1, LAP_SPMV> op{L.col, L.w, L.d, L.dinv, q, u, nullptr, nullptr, 0.0, 0.0, 0.0};
     // same kernel and bytes as the solve's fp64 product (family "spmv")
-    run_rows(L.sched, L.rp, op, c.st, "spmv", 4.0 * (n + 1) + 12.0 * L.nnz + 24.0 * n);
-    reduce_dev<RED_DOT>(q, u, nullptr, n, part, lz + LZ_AL + j, c.st);
-    hipLaunchKernelGGL(k_lz_update, dim3(nblk(n)), dim3(kBlock), 0, c.st, u, q, qp, L.d, n, lz, j);
-    reduce_dev<RED_DDOT>(u, nullptr, L.d, n, part, lz + LZ_B2, c.st);
-    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(1), 0, c.st, lz, j, steps);
-    hipLaunchKernelGGL(k_lz_next, dim3(nblk(n)), dim3(kBlock), 0, c.st, u, q, qp, n, lz, j);
+    run_rows(L.sched, L.rp, op, st, "spmv", 4.0 * (n + 1) + 12.0 * L.nnz + 24.0 * n);
+    reduce_dev<RED_DOT>(q, u, nullptr, n, part, lz + LZ_AL + j, st);
+    hipLaunchKernelGGL(k_lz_update, dim3(nblk(n)), dim3(kBlock), 0, st, u, q, qp, L.d, n, lz, j);
+    reduce_dev<RED_DDOT>(u, nullptr, L.d, n, part, lz + LZ_B2, st);
+    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(1), 0, st, lz, j, steps);
+    hipLaunchKernelGGL(k_lz_next, dim3(nblk(n)), dim3(kBlock), 0, st, u, q, qp, n, lz, j);
   }
-  hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(64), 0, c.st, lz, out);
+  hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(64), 0, st, lz, out);
   LG_LAUNCH_CHECK();
 }
 
@@ -1208,6 +1231,10 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
   c.key = seed_key(o.seed);
   c.flags = h->mem.get<int>(4);
   c.pair = h->mem.get<int64_t>(2);
+  if (!h->capture_stream) LG_HIP(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+  c.side.s = h->capture_stream;
+  LG_HIP(hipEventCreateWithFlags(&c.side.ready, hipEventDisableTiming));
+  LG_HIP(hipEventCreateWithFlags(&c.side.done, hipEventDisableTiming));
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, st, (int32_t*)c.flags, (int64_t)4, 0);
   const int64_t n = g->n, nnz = g->nnz;
   h->lev.emplace_back();
@@ -1258,8 +1285,7 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
     double* tot = c.tmp.get<double>(1);
     reduce_dev<RED_SUM>(L0->d, nullptr, nullptr, n, part, tot, st);
     double total = 0.0;
-    LG_HIP(hipMemcpyAsync(&total, tot, sizeof(double), hipMemcpyDeviceToHost, st));
-    LG_HIP(hipStreamSynchronize(st));
+    read_dev(&total, tot, sizeof(double), st);
     if (!(total < 0x1p62)) fail(LG_E_RANGE, "total edge weight must be below 2^62");
     c.tmp.rewind(m);
   }
@@ -1328,9 +1354,10 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
   coarsest(c, h->lev[l]);
   if (o.precision == LG_MIXED)
     for (int i = 0; i < l; i++) make_f32(c, h->lev[i]);
+  LG_HIP(hipEventRecord(c.side.done, c.side.s));
+  LG_HIP(hipStreamWaitEvent(st, c.side.done, 0));
   std::vector<double> lm(l + 1, 0.0);
-  LG_HIP(hipMemcpyAsync(lm.data(), h->lmax_dev, sizeof(double) * (l + 1), hipMemcpyDeviceToHost, st));
-  LG_HIP(hipStreamSynchronize(st));
+  read_dev(lm.data(), h->lmax_dev, sizeof(double) * (l + 1), st);
   for (int i = 0; i <= l; i++) h->lev[i].lmax = h->lev[i].type == LG_LEVEL_AGG ? lm[i] : 0.0;
   check_flags(c);
 }

@@ -984,8 +984,7 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
   double* hs = h->host_scal;
   auto sl = [&](int slot) { return sc + slot * K; };
   auto read_scal = [&]() {
-    LG_HIP(hipMemcpyAsync(hs, sc, sizeof(double) * S_COUNT * K, hipMemcpyDeviceToHost, st));
-    LG_HIP(hipStreamSynchronize(st));
+    read_dev(hs, sc, sizeof(double) * S_COUNT * K, st);
   };
   auto write_slot = [&](int slot, const std::vector<double>& v) {
     for (int c = 0; c < K; c++) hs[slot * K + c] = v[c];
