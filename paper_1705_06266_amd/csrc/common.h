@@ -43,6 +43,9 @@ constexpr int kBlock = 256;
 #ifndef LG_PER_LANE
 #define LG_PER_LANE 4
 #endif
+#ifndef LG_XSUM_UNROLL
+#define LG_XSUM_UNROLL 1
+#endif
 constexpr int kHubChunk = LG_HUB_CHUNK;
 constexpr uint64_t kGolden = 0x9e3779b97f4a7c15ULL;
 
@@ -96,43 +99,33 @@ constexpr int kLanczosStream = 64;
 // fp64 term is rounded to the nearest multiple of 2^-64 (ties to even), the
 // 128-bit integers are added (wrapping; associative, hence order free) and the
 // total is rounded once to the nearest fp64 (ties to even).
+//
+// The conversion is branch-free (both shift directions are formed and one is
+// selected), so the lanes of a wave never diverge on the magnitudes of their
+// terms.
 __device__ __forceinline__ u128 xs_term(double v, int& bad) {
   const uint64_t bits = (uint64_t)__double_as_longlong(v);
   const uint64_t mag = bits & 0x7fffffffffffffffULL;
   const int ex = (int)(mag >> 52);
-  uint64_t m = mag & 0x000fffffffffffffULL;
-  if (ex == 0x7ff) {
-    bad = 1;
-    return 0;
-  }
-  int e = ex;
-  if (e == 0) {
-    if (m == 0) return 0;
-    e = 1;
-  } else {
-    m |= 0x0010000000000000ULL;
-  }
-  // |v| = m * 2^(e-1075); times 2^64 -> m * 2^(e-1011)
-  const int sh = e - 1011;
-  u128 r;
-  if (sh >= 0) {
-    if (sh > 73) {  // |v| * 2^64 >= 2^126
-      bad = 1;
-      return 0;
-    }
-    r = (u128)m << sh;
-  } else {
-    const int rs = -sh;
-    if (rs > 54) {
-      r = 0;  // below half a unit of 2^-64
-    } else {
-      uint64_t q = m >> rs;
-      const uint64_t rem = m & ((1ULL << rs) - 1);
-      const uint64_t half = 1ULL << (rs - 1);
-      if (rem > half || (rem == half && (q & 1))) q++;
-      r = q;
-    }
-  }
+  const uint64_t frac = mag & 0x000fffffffffffffULL;
+  const uint64_t m = ex ? (frac | 0x0010000000000000ULL) : frac;
+  // |v| * 2^64 = m * 2^sh
+  const int sh = (ex ? ex : 1) - 1011;
+  const bool inval = (ex == 0x7ff) | (sh > 73);  // not finite, or |v| * 2^64 >= 2^126
+  bad |= inval;
+  // sh >= 0: exact left shift of the 53-bit significand
+  const int ls = sh < 0 ? 0 : (sh > 73 ? 73 : sh);
+  const uint64_t lo_l = ls >= 64 ? 0 : (m << (ls & 63));
+  const uint64_t hi_l = ls >= 64 ? (m << ((ls - 64) & 63)) : (ls == 0 ? 0 : (m >> ((64 - ls) & 63)));
+  // sh < 0: right shift, rounded to nearest, ties to even (shifts past 54 give 0)
+  const int rs = sh >= 0 ? 1 : (sh < -63 ? 63 : -sh);
+  const uint64_t q = m >> rs;
+  const uint64_t rem = m & ((1ULL << rs) - 1);
+  const uint64_t half = 1ULL << (rs - 1);
+  const uint64_t qr = q + (uint64_t)((rem > half) | ((rem == half) & (q & 1)));
+  const uint64_t lo = inval ? 0 : (sh >= 0 ? lo_l : qr);
+  const uint64_t hi = inval ? 0 : (sh >= 0 ? hi_l : 0);
+  const u128 r = ((u128)hi << 64) | lo;
   return (bits >> 63) ? (u128)0 - r : r;
 }
 
@@ -268,21 +261,37 @@ __host__ __device__ inline int degree_class(int d, int hub_deg) {
 }
 
 // Whole-row reduction by one workgroup; the epilogue runs on thread 0.
+// Entries a lane loads ahead in the row loops: Op::kUnroll if the op sets it
+// (ops with wide accumulators trade it for occupancy), else 4.
+template <class Op, class = void>
+struct op_unroll {
+  static constexpr int value = 4;
+};
+template <class Op>
+struct op_unroll<Op, std::void_t<decltype(Op::kUnroll)>> {
+  static constexpr int value = Op::kUnroll;
+};
+
+// op.accum over the entries e, e + step, ... below end.
+template <class Op>
+__device__ __forceinline__ void accum_strided(const Op& op, typename Op::Acc& acc, int64_t row,
+                                              int e, int end, int step) {
+  constexpr int U = op_unroll<Op>::value;
+  for (; e + (U - 1) * step < end; e += U * step) {
+#pragma unroll
+    for (int u = 0; u < U; u++) op.accum(acc, row, e + u * step);
+  }
+  if constexpr (U > 1)
+    for (; e < end; e += step) op.accum(acc, row, e);
+}
+
 template <class Op>
 __device__ __forceinline__ void block_row(const Op& op, const int32_t* __restrict__ rp,
                                           int64_t row) {
   using Acc = typename Op::Acc;
   Acc acc = op.identity();
   if (op.active(row)) {
-    const int end = rp[row + 1];
-    int e = rp[row] + (int)threadIdx.x;
-    for (; e + 3 * kBlock < end; e += 4 * kBlock) {
-      op.accum(acc, row, e);
-      op.accum(acc, row, e + kBlock);
-      op.accum(acc, row, e + 2 * kBlock);
-      op.accum(acc, row, e + 3 * kBlock);
-    }
-    for (; e < end; e += kBlock) op.accum(acc, row, e);
+    accum_strided(op, acc, row, rp[row] + (int)threadIdx.x, rp[row + 1], kBlock);
   }
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) op.combine(acc, shfl_xor_any(acc, m));
@@ -308,15 +317,7 @@ __device__ __forceinline__ void rows_class(const Op& op, const int32_t* __restri
   const int64_t row = perm[pos];
   typename Op::Acc acc = op.identity();
   if (op.active(row)) {
-    const int end = rp[row + 1];
-    int e = rp[row] + lane;
-    for (; e + 3 * G < end; e += 4 * G) {
-      op.accum(acc, row, e);
-      op.accum(acc, row, e + G);
-      op.accum(acc, row, e + 2 * G);
-      op.accum(acc, row, e + 3 * G);
-    }
-    for (; e < end; e += G) op.accum(acc, row, e);
+    accum_strided(op, acc, row, rp[row] + lane, rp[row + 1], G);
 #pragma unroll
     for (int m = G / 2; m > 0; m >>= 1) op.combine(acc, shfl_xor_any(acc, m));
   }
@@ -338,14 +339,7 @@ __device__ __forceinline__ void split_chunk(const Op& op, const int32_t* __restr
   const int end = min(rp[row + 1], beg + kHubChunk);
   Acc acc = op.identity();
   if (op.active(row)) {
-    int e = beg + (int)threadIdx.x;
-    for (; e + 3 * kBlock < end; e += 4 * kBlock) {
-      op.accum(acc, row, e);
-      op.accum(acc, row, e + kBlock);
-      op.accum(acc, row, e + 2 * kBlock);
-      op.accum(acc, row, e + 3 * kBlock);
-    }
-    for (; e < end; e += kBlock) op.accum(acc, row, e);
+    accum_strided(op, acc, row, beg + (int)threadIdx.x, end, kBlock);
   }
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) op.combine(acc, shfl_xor_any(acc, m));

@@ -398,6 +398,7 @@ struct X4Acc {
 // Y_i = (1 - omega) X_i + omega * (exact sum_j w_ij X_j) / d_i.
 struct JacobiOp {
   using Acc = X4Acc;
+  static constexpr int kUnroll = LG_XSUM_UNROLL;
   const int32_t* __restrict__ col;
   const double* __restrict__ w;
   const double* __restrict__ d;

@@ -679,7 +679,7 @@ inline Vals<float> vals_of<float>(const Level& L) {
 template <typename T>
 inline int dot_blocks(int64_t m) {
   const int64_t vecs = ceil_div(m, 16 / (int64_t)sizeof(T));
-  return (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, ceil_div(vecs, (int64_t)kBlock * 4)));
+  return (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, ceil_div(vecs, (int64_t)kBlock)));
 }
 
 inline double spmm_bytes(const Level& L, int K, int s, int vecs) {
