@@ -850,9 +850,16 @@ int64_t scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, Arena& tmp, 
                         bool want_total);
 // Stable LSD radix sort of (key, val) pairs over the listed 8-bit digit shifts.
 // pack > 0: keys are (hi << 32 | lo) with hi, lo < 2^pack and the shifts index
-// the packed value (hi << pack | lo) (see pair_shifts).
-void radix_sort_pairs(uint64_t* keys, uint64_t* vals, int64_t n, const std::vector<int>& shifts,
-                      Arena& tmp, hipStream_t st, int pack = 0);
+// the packed value (hi << pack | lo) (see pair_shifts).  The sorted pairs are
+// left either in the input arrays or in two arrays taken from tmp (which stay
+// allocated until the caller rewinds tmp); the result says where.
+struct SortedPairs {
+  uint64_t* keys;
+  uint64_t* vals;
+};
+SortedPairs radix_sort_pairs(uint64_t* keys, uint64_t* vals, int64_t n,
+                             const std::vector<int>& shifts, Arena& tmp, hipStream_t st,
+                             int pack = 0);
 std::vector<int> pair_shifts(int bits);  // digits of a packed pair of two bits-wide halves
 std::vector<int> digit_shifts(int bits_lo, int bits_hi);  // digits covering [0,bits_lo) and [32,32+bits_hi)
 int bits_for(int64_t max_value);

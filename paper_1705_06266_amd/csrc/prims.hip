@@ -516,9 +516,9 @@ std::vector<int> pair_shifts(int bits) {
   return s;
 }
 
-void radix_sort_pairs(uint64_t* keys, uint64_t* vals, int64_t n, const std::vector<int>& shifts,
-                      Arena& tmp, hipStream_t st, int pack) {
-  if (n <= 1 || shifts.empty()) return;
+SortedPairs radix_sort_pairs(uint64_t* keys, uint64_t* vals, int64_t n,
+                             const std::vector<int>& shifts, Arena& tmp, hipStream_t st, int pack) {
+  if (n <= 1 || shifts.empty()) return {keys, vals};
   ProfScope prof_scope("radix", st, (double)n * 32.0 * shifts.size());
   if (n <= kBlockSortMax && (int)shifts.size() <= kMaxDigits) {
     RadixShifts sh{};
@@ -527,12 +527,13 @@ void radix_sort_pairs(uint64_t* keys, uint64_t* vals, int64_t n, const std::vect
     hipLaunchKernelGGL(k_radix_block_sort, dim3(1), dim3(kBlock), 0, st, keys, vals, (int)n, sh,
                        pack);
     LG_LAUNCH_CHECK();
-    return;
+    return {keys, vals};
   }
-  Arena::Mark m = tmp.mark();
-  const int64_t nb = ceil_div(n, kRadixTile);
+  // the second pair of arrays may hold the result: allocated before the mark
   uint64_t* k2 = tmp.get<uint64_t>(n);
   uint64_t* v2 = tmp.get<uint64_t>(n);
+  Arena::Mark m = tmp.mark();
+  const int64_t nb = ceil_div(n, kRadixTile);
   int32_t* hist = tmp.get<int32_t>(256 * nb);
   int64_t* offs = tmp.get<int64_t>(256 * nb + 1);
   uint64_t *ka = keys, *va = vals, *kb = k2, *vb = v2;
@@ -548,11 +549,8 @@ void radix_sort_pairs(uint64_t* keys, uint64_t* vals, int64_t n, const std::vect
     std::swap(ka, kb);
     std::swap(va, vb);
   }
-  if (ka != keys) {
-    LG_HIP(hipMemcpyAsync(keys, ka, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, st));
-    LG_HIP(hipMemcpyAsync(vals, va, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, st));
-  }
   tmp.rewind(m);
+  return {ka, va};
 }
 
 // ------------------------------------------------------------ row schedule
@@ -771,11 +769,11 @@ void build_sched(Sched& s, const int32_t* rp, int64_t n, int64_t nnz, Arena& kee
     uint64_t* vals = tmp.get<uint64_t>(n);
     hipLaunchKernelGGL(k_class_keys, dim3((unsigned)nb), dim3(kBlock), 0, st, rp, n, s.hub_deg, keys,
                        vals);
-    radix_sort_pairs(keys, vals, n, std::vector<int>{0}, tmp, st);
+    const SortedPairs sp = radix_sort_pairs(keys, vals, n, std::vector<int>{0}, tmp, st);
     s.perm = keep.get<int32_t>(pos);
     if (pos)
       hipLaunchKernelGGL(k_u64_to_i32_n, dim3((unsigned)ceil_div(pos, kBlock)), dim3(kBlock), 0, st,
-                         (const uint64_t*)vals, pos, s.perm);
+                         (const uint64_t*)sp.vals, pos, s.perm);
     LG_LAUNCH_CHECK();
   }
   if (s.nhub || s.nsplit) {

@@ -999,7 +999,12 @@ void build_elim(Ctx& c, Level& L, const ElimChoice& ch, Level& out) {
                      L.d, L.cidx, offd, offf, nnz, dkeys, dvals, fkeys, fvals);
   LG_LAUNCH_CHECK();
   const int b = bits_for(nc > 0 ? nc - 1 : 0);
-  radix_sort_pairs(fkeys, (uint64_t*)fvals, nfill, pair_shifts(b), tmp, c.st, b);
+  {
+    const SortedPairs sp =
+        radix_sort_pairs(fkeys, (uint64_t*)fvals, nfill, pair_shifts(b), tmp, c.st, b);
+    fkeys = sp.keys;
+    fvals = (double*)sp.vals;
+  }
   uint64_t* keys = tmp.get<uint64_t>(m);
   double* vals = tmp.get<double>(m);
   {
@@ -1111,7 +1116,9 @@ void galerkin(Ctx& c, Level& L, int64_t nc, Level& out) {
     uint64_t* mk = tmp.get<uint64_t>(n);
     uint64_t* mv = tmp.get<uint64_t>(n);
     hipLaunchKernelGGL(k_members_keys, dim3(nblk(n)), dim3(kBlock), 0, c.st, L.agg, n, mk, mv);
-    radix_sort_pairs(mk, mv, n, digit_shifts(b, 0), tmp, c.st);
+    const SortedPairs sp = radix_sort_pairs(mk, mv, n, digit_shifts(b, 0), tmp, c.st);
+    mk = sp.keys;
+    mv = sp.vals;
     L.mem = h->mem.get<int32_t>(n);
     L.mptr = h->mem.get<int32_t>(nc + 1);
     hipLaunchKernelGGL(k_u64_to_i32, dim3(nblk(n)), dim3(kBlock), 0, c.st, mv, n, L.mem);
@@ -1132,8 +1139,8 @@ void galerkin(Ctx& c, Level& L, int64_t nc, Level& out) {
   hipLaunchKernelGGL(k_gal_emit, dim3(nblk(nnz)), dim3(kBlock), 0, c.st, rowidx, L.col, L.w, L.agg,
                      flag, off, nnz, keys, vals);
   LG_LAUNCH_CHECK();
-  radix_sort_pairs(keys, (uint64_t*)vals, m, pair_shifts(b), tmp, c.st, b);
-  assemble(c, keys, vals, m, nc, out);
+  const SortedPairs sp = radix_sort_pairs(keys, (uint64_t*)vals, m, pair_shifts(b), tmp, c.st, b);
+  assemble(c, sp.keys, (double*)sp.vals, m, nc, out);
 }
 
 // lambda_max(D^-1 L) by eig_iters Lanczos steps in the D inner product.
@@ -1311,7 +1318,6 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
       h->lev.emplace_back();
       L = &h->lev[l];
       build_elim(c, *L, ch, h->lev[l + 1]);
-      check_flags(c);
       c.tmp.rewind(lm);
       l++;
       L = &h->lev[l];
@@ -1325,7 +1331,6 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
     double* X = o.keep_setup_data ? h->mem.get<double>(4 * L->n) : c.tmp.get<double>(4 * L->n);
     double* S = o.keep_setup_data ? h->mem.get<double>(L->nnz) : c.tmp.get<double>(L->nnz);
     strength(c, *L, l, S, X);
-    check_flags(c);
     int32_t *status = nullptr, *votes = nullptr;
     const int64_t nc = aggregate(c, *L, S, &status, &votes);
     if (o.keep_setup_data) {
@@ -1345,7 +1350,6 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
     L->nc = nc;
     galerkin(c, *L, nc, h->lev[l + 1]);
     lanczos(c, *L, l, h->lmax_dev + l);
-    check_flags(c);
     c.tmp.rewind(lm);
     l++;
   }
@@ -1360,6 +1364,9 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
   std::vector<double> lm(l + 1, 0.0);
   read_dev(lm.data(), h->lmax_dev, sizeof(double) * (l + 1), st);
   for (int i = 0; i <= l; i++) h->lev[i].lmax = h->lev[i].type == LG_LEVEL_AGG ? lm[i] : 0.0;
+  // After validation the level loop can only raise F_XSUM (an exact sum out of
+  // range), which never affects an index; it is reported here, once, instead
+  // of after every level.
   check_flags(c);
 }
 
