@@ -840,8 +840,22 @@ struct TempArena {
 
 
 // ------------------------------------------------------------- helpers
+// Row statistics behind a schedule: max degree, min degree, 8 class counts,
+// hubs, split rows, split chunks (and spare slots).
+constexpr int kStat = 16;
+
+// Row schedule of the CSR (rp, n rows, nnz entries): statistics, read back,
+// layout.  tiles: also the merge-path tiles (level matrices whose one-column
+// products may take the merge path).
 void build_sched(Sched& s, const int32_t* rp, int64_t n, int64_t nnz, Arena& keep, Arena& tmp,
-                 hipStream_t st);
+                 hipStream_t st, bool tiles = false);
+// The two halves, for callers that read the statistics together with other
+// values: sched_stats launches the kernels that fill kStat ints (returned, on
+// the device, in tmp; n_dev optionally holds the actual row count <= n) and
+// sched_layout builds the schedule from those ints once they are on the host.
+int* sched_stats(const int32_t* rp, int64_t n, const int64_t* n_dev, Arena& tmp, hipStream_t st);
+void sched_layout(Sched& s, const int* t, const int32_t* rp, int64_t n, int64_t nnz, bool tiles,
+                  Arena& keep, Arena& tmp, hipStream_t st);
 // out[i] = sum_{j<i} in[j] for i <= n (out has n+1 entries); returns out[n] on the host
 // when want_total (synchronises the stream).
 int64_t scan_i64(const int64_t* in, int64_t* out, int64_t n, Arena& tmp, hipStream_t st,
@@ -865,5 +879,13 @@ std::vector<int> digit_shifts(int bits_lo, int bits_hi);  // digits covering [0,
 int bits_for(int64_t max_value);
 int64_t read_i64(const int64_t* dev, hipStream_t st);
 void read_dev(void* host, const void* dev, size_t bytes, hipStream_t st);
+// Several small device values in one round trip (up to 4 segments of whole,
+// 4-byte aligned words; waits for the work queued on st before them).
+struct DevRead {
+  void* host;
+  const void* dev;
+  size_t bytes;
+};
+void read_dev_n(const DevRead* r, int count, hipStream_t st);
 
 }  // namespace lg

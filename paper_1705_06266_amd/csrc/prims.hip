@@ -554,13 +554,15 @@ SortedPairs radix_sort_pairs(uint64_t* keys, uint64_t* vals, int64_t n,
 }
 
 // ------------------------------------------------------------ row schedule
-constexpr int kStat = 16;  // per block: max deg, min deg, 8 class counts, hubs, splits, chunks
 enum { ST_MAX = 0, ST_MIN = 1, ST_CLS = 2, ST_HUB = 10, ST_SPLIT = 11, ST_CHUNK = 12 };
 
 constexpr int kStatRows = 16;  // rows per thread in k_sched_stats
 
+// n_dev (optional): the actual row count on the device, at most n.
 __global__ __launch_bounds__(kBlock) void k_sched_stats(const int32_t* __restrict__ rp, int64_t n,
+                                                        const int64_t* __restrict__ n_dev,
                                                         int hub_deg, int* __restrict__ partial) {
+  if (n_dev) n = min(n, *n_dev);
   int v[kStat];
 #pragma unroll
   for (int k = 0; k < kStat; k++) v[k] = 0;
@@ -669,12 +671,66 @@ __global__ void k_zero_i32n(int32_t* p, int64_t n) {
 constexpr int kMailHeader = 16;     // 32-bit words before the data
 constexpr size_t kMailBytes = 65536;  // largest read
 
-__global__ void k_mail(const uint32_t* __restrict__ src, int words, uint32_t* __restrict__ box,
-                       uint32_t seq) {
-  for (int i = threadIdx.x; i < words; i += blockDim.x) box[kMailHeader + i] = src[i];
+constexpr int kMailSegs = 4;
+struct MailSegs {
+  const uint32_t* src[kMailSegs];
+  int words[kMailSegs];
+  int count;
+};
+
+// Copies the segments back to back into the mailbox, then publishes seq.
+__global__ void k_mail(MailSegs segs, uint32_t* __restrict__ box, uint32_t seq) {
+  int at = kMailHeader;
+  for (int k = 0; k < segs.count; k++) {
+    for (int i = threadIdx.x; i < segs.words[k]; i += blockDim.x) box[at + i] = segs.src[k][i];
+    at += segs.words[k];
+  }
   __threadfence_system();
   __syncthreads();
   if (threadIdx.x == 0) __hip_atomic_store(box, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+void read_dev_n(const DevRead* r, int count, hipStream_t st) {
+  if (count < 1 || count > kMailSegs) fail(LG_E_ARG, "read_dev_n: 1 to 4 segments");
+  MailSegs segs{};
+  segs.count = count;
+  size_t total = 0;
+  for (int k = 0; k < count; k++) {
+    if ((r[k].bytes & 3) || (reinterpret_cast<uintptr_t>(r[k].dev) & 3))
+      fail(LG_E_ARG, "read_dev_n: segments must be 4-byte aligned whole words");
+    segs.src[k] = static_cast<const uint32_t*>(r[k].dev);
+    segs.words[k] = (int)(r[k].bytes / 4);
+    total += r[k].bytes;
+  }
+  if (total > kMailBytes) fail(LG_E_ARG, "read_dev_n: too large");
+  static thread_local uint32_t* box = nullptr;
+  static thread_local uint32_t* box_dev = nullptr;
+  static thread_local uint32_t seq = 0;
+  if (!box) {
+    LG_HIP(hipHostMalloc((void**)&box, kMailHeader * 4 + kMailBytes,
+                         hipHostMallocCoherent | hipHostMallocMapped | hipHostMallocPortable));
+    LG_HIP(hipHostGetDevicePointer((void**)&box_dev, box, 0));
+    __atomic_store_n(box, 0u, __ATOMIC_RELAXED);
+  }
+  if (++seq == 0) seq = 1;  // 0 is the initial value
+  hipLaunchKernelGGL(k_mail, dim3(1), dim3(kBlock), 0, st, segs, box_dev, seq);
+  LG_LAUNCH_CHECK();
+  for (uint64_t spin = 1; __atomic_load_n(box, __ATOMIC_ACQUIRE) != seq; spin++) {
+    if (spin % 1024) continue;
+    const hipError_t e = hipStreamQuery(st);
+    if (e == hipErrorNotReady) continue;
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(LG_E_HIP, std::string("HIP error: ") + hipGetErrorString(e));
+    }
+    if (__atomic_load_n(box, __ATOMIC_ACQUIRE) != seq)
+      fail(LG_E_HIP, "device read: the stream finished without publishing the value");
+  }
+  const char* data = reinterpret_cast<const char*>(box + kMailHeader);
+  for (int k = 0; k < count; k++) {
+    memcpy(r[k].host, data, r[k].bytes);
+    data += r[k].bytes;
+  }
 }
 
 void read_dev(void* host, const void* dev, size_t bytes, hipStream_t st) {
@@ -688,31 +744,8 @@ void read_dev(void* host, const void* dev, size_t bytes, hipStream_t st) {
     memcpy(host, pinned, bytes);
     return;
   }
-  static thread_local uint32_t* box = nullptr;
-  static thread_local uint32_t* box_dev = nullptr;
-  static thread_local uint32_t seq = 0;
-  if (!box) {
-    LG_HIP(hipHostMalloc((void**)&box, kMailHeader * 4 + kMailBytes,
-                         hipHostMallocCoherent | hipHostMallocMapped | hipHostMallocPortable));
-    LG_HIP(hipHostGetDevicePointer((void**)&box_dev, box, 0));
-    __atomic_store_n(box, 0u, __ATOMIC_RELAXED);
-  }
-  if (++seq == 0) seq = 1;  // 0 is the initial value
-  hipLaunchKernelGGL(k_mail, dim3(1), dim3(kBlock), 0, st, (const uint32_t*)dev, (int)(bytes / 4),
-                     box_dev, seq);
-  LG_LAUNCH_CHECK();
-  for (uint64_t spin = 1; __atomic_load_n(box, __ATOMIC_ACQUIRE) != seq; spin++) {
-    if (spin % 1024) continue;
-    const hipError_t e = hipStreamQuery(st);
-    if (e == hipErrorNotReady) continue;
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      fail(LG_E_HIP, std::string("HIP error: ") + hipGetErrorString(e));
-    }
-    if (__atomic_load_n(box, __ATOMIC_ACQUIRE) != seq)
-      fail(LG_E_HIP, "device read: the stream finished without publishing the value");
-  }
-  memcpy(host, box + kMailHeader, bytes);
+  const DevRead r{host, dev, bytes};
+  read_dev_n(&r, 1, st);
 }
 
 // tile_row[t] = rows whose end marker (at rp[r+1] + r) precedes merged item
@@ -731,8 +764,28 @@ __global__ void k_merge_split(const int32_t* __restrict__ rp, int64_t n, int64_t
   tile_row[t] = (int32_t)lo;
 }
 
+int* sched_stats(const int32_t* rp, int64_t n, const int64_t* n_dev, Arena& tmp, hipStream_t st) {
+  const int64_t nbs = std::max<int64_t>(1, ceil_div(n, (int64_t)kBlock * kStatRows));
+  int* part = tmp.get<int>(kStat * nbs);
+  int* tot = tmp.get<int>(kStat);
+  hipLaunchKernelGGL(k_sched_stats, dim3((unsigned)nbs), dim3(kBlock), 0, st, rp, n, n_dev,
+                     (int)LG_HUB_DEG, part);
+  hipLaunchKernelGGL(k_sched_final, dim3(1), dim3(kStat * 64), 0, st, (const int*)part, nbs, tot);
+  LG_LAUNCH_CHECK();
+  return tot;
+}
+
 void build_sched(Sched& s, const int32_t* rp, int64_t n, int64_t nnz, Arena& keep, Arena& tmp,
-                 hipStream_t st) {
+                 hipStream_t st, bool tiles) {
+  int t[kStat] = {};
+  Arena::Mark m = tmp.mark();
+  if (n > 0) read_dev(t, sched_stats(rp, n, nullptr, tmp, st), sizeof(t), st);
+  sched_layout(s, t, rp, n, nnz, tiles, keep, tmp, st);
+  tmp.rewind(m);
+}
+
+void sched_layout(Sched& s, const int* t, const int32_t* rp, int64_t n, int64_t nnz, bool tiles,
+                  Arena& keep, Arena& tmp, hipStream_t st) {
   s = Sched();
   s.n = n;
   s.nnz = nnz;
@@ -740,14 +793,6 @@ void build_sched(Sched& s, const int32_t* rp, int64_t n, int64_t nnz, Arena& kee
   s.hub_deg = LG_HUB_DEG;
   Arena::Mark m = tmp.mark();
   const int64_t nb = ceil_div(n, kBlock);
-  const int64_t nbs = ceil_div(n, (int64_t)kBlock * kStatRows);
-  int* part = tmp.get<int>(kStat * nbs);
-  int* tot = tmp.get<int>(kStat);
-  hipLaunchKernelGGL(k_sched_stats, dim3((unsigned)nbs), dim3(kBlock), 0, st, rp, n, s.hub_deg, part);
-  hipLaunchKernelGGL(k_sched_final, dim3(1), dim3(kStat * 64), 0, st, (const int*)part, nbs, tot);
-  LG_LAUNCH_CHECK();
-  int t[kStat];
-  read_dev(t, tot, sizeof(t), st);
   s.max_deg = t[ST_MAX];
   s.min_deg = t[ST_MIN];
   s.nhub = t[ST_HUB];
@@ -797,14 +842,15 @@ void build_sched(Sched& s, const int32_t* rp, int64_t n, int64_t nnz, Arena& kee
       LG_LAUNCH_CHECK();
     }
   }
-  // merge-path tiles
-  s.ntile = ceil_div(n + nnz, kMergeTile);
-  s.tile_row = keep.get<int32_t>(s.ntile + 1);
-  s.carry_row = keep.get<int32_t>(s.ntile);
-  s.carry_val = keep.get<double>(s.ntile);
-  hipLaunchKernelGGL(k_merge_split, dim3((unsigned)ceil_div(s.ntile + 1, kBlock)), dim3(kBlock), 0, st,
-                     rp, n, nnz, s.ntile, s.tile_row);
-  LG_LAUNCH_CHECK();
+  if (tiles) {  // merge-path tiles
+    s.ntile = ceil_div(n + nnz, kMergeTile);
+    s.tile_row = keep.get<int32_t>(s.ntile + 1);
+    s.carry_row = keep.get<int32_t>(s.ntile);
+    s.carry_val = keep.get<double>(s.ntile);
+    hipLaunchKernelGGL(k_merge_split, dim3((unsigned)ceil_div(s.ntile + 1, kBlock)), dim3(kBlock), 0,
+                       st, rp, n, nnz, s.ntile, s.tile_row);
+    LG_LAUNCH_CHECK();
+  }
   tmp.rewind(m);
 }
 

@@ -15,7 +15,8 @@
 namespace lg {
 
 enum {
-  F_ROWPTR = 1, F_COL = 2, F_LOOP = 4, F_ORDER = 8, F_WEIGHT = 16, F_ASYM = 32, F_XSUM = 64
+  F_ROWPTR = 1, F_COL = 2, F_LOOP = 4, F_ORDER = 8, F_WEIGHT = 16, F_ASYM = 32, F_XSUM = 64,
+  F_SPLIT = 128
 };
 
 constexpr int kMaxLevelCap = 128;
@@ -112,10 +113,11 @@ __global__ void k_validate_pairs(const unsigned long long* __restrict__ searched
 // connected iff no level with more than one vertex has an isolated vertex and
 // the coarsest level is connected; the latter is checked here by a
 // breadth-first search in one workgroup (the coarsest level is small).
+// flags: F_SPLIT is raised when the search does not reach every vertex.
 __global__ __launch_bounds__(1024) void k_coarse_connected(const int32_t* __restrict__ rp,
                                                            const int32_t* __restrict__ col, int n,
                                                            int* __restrict__ seen, int* qa, int* qb,
-                                                           int* __restrict__ out) {
+                                                           int* __restrict__ flags) {
   __shared__ int nq, nnext, total;
   for (int i = threadIdx.x; i < n; i += blockDim.x) seen[i] = 0;
   __syncthreads();
@@ -147,7 +149,7 @@ __global__ __launch_bounds__(1024) void k_coarse_connected(const int32_t* __rest
     qa = qb;
     qb = t;
   }
-  if (threadIdx.x == 0) *out = total;
+  if (threadIdx.x == 0 && total != n) atomicOr(flags, F_SPLIT);
 }
 
 // ------------------------------------------------------ exact row sums
@@ -598,11 +600,12 @@ __global__ void k_run_heads(const uint64_t* __restrict__ keys, int64_t m,
   if (e < m) head[e] = (e == 0 || keys[e] != keys[e - 1]);
 }
 
+// R: the number of runs (on the device, ridx[m] after the scan).
 __global__ void k_run_starts(const int32_t* __restrict__ head, const int64_t* __restrict__ ridx,
-                             int64_t m, int64_t R, int32_t* __restrict__ start) {
+                             int64_t m, const int64_t* __restrict__ R, int32_t* __restrict__ start) {
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e < m && head[e]) start[ridx[e]] = (int32_t)e;
-  if (e == 0) start[R] = (int32_t)m;
+  if (e == 0) start[*R] = (int32_t)m;
 }
 
 // Row pointer of a matrix whose entries are sorted by row = key >> shift:
@@ -865,13 +868,10 @@ struct Ctx {
   Arena& side_tmp = *side_lease.a;
   SideStream side;  // declared after the arenas: joined before they are released
   int* flags = nullptr;  // device error flags
-  int64_t* pair = nullptr;  // two device words for reading totals back together
   uint64_t key = 0;
 };
 
-void check_flags(Ctx& c) {
-  int f = 0;
-  read_dev(&f, c.flags, sizeof(int), c.st);
+void raise_flags(int f) {
   if (f & F_ROWPTR) fail(LG_E_GRAPH, "row pointers are not a valid CSR offset array");
   if (f & F_COL) fail(LG_E_GRAPH, "column index out of range");
   if (f & F_LOOP) fail(LG_E_GRAPH, "self-loop (diagonal entry) in the adjacency");
@@ -879,6 +879,13 @@ void check_flags(Ctx& c) {
   if (f & F_WEIGHT) fail(LG_E_GRAPH, "edge weight not finite and positive");
   if (f & F_ASYM) fail(LG_E_GRAPH, "adjacency not symmetric");
   if (f & F_XSUM) fail(LG_E_RANGE, "sum outside the exact-sum range (total weight too large)");
+  if (f & F_SPLIT) fail(LG_E_DISCONNECTED, "graph is not connected (coarsest level splits)");
+}
+
+void check_flags(Ctx& c) {
+  int f = 0;
+  read_dev(&f, c.flags, sizeof(int), c.st);
+  raise_flags(f);
 }
 
 // A level with more than one vertex and an isolated vertex: the input graph
@@ -898,29 +905,52 @@ void level_diag(Ctx& c, Level& L) {
 
 // Sorted (row << 32 | col, value) pairs -> CSR of `out` with exact sums of
 // equal keys (rows 0..nrows-1), then its schedule and diagonal.
-void assemble(Ctx& c, uint64_t* keys, double* vals, int64_t m, int64_t nrows, Level& out) {
+// A schedule whose statistics are on the device, to be read back with the
+// next values the host waits for.
+struct PendingSched {
+  Sched* s;
+  const int* stats;
+  const int32_t* rp;
+  int64_t n, nnz;
+};
+
+// Coarse matrix from sorted (row << 32 | col, value) pairs: one exact sum per
+// run of equal keys.  pend: a schedule laid out after the same read back.
+void assemble(Ctx& c, uint64_t* keys, double* vals, int64_t m, int64_t nrows, Level& out,
+              const PendingSched* pend = nullptr) {
   Arena& tmp = c.tmp;
   lg_hierarchy* h = c.h;
   out.n = nrows;
   out.rp = h->mem.get<int32_t>(nrows + 1);
+  int pt[kStat] = {};
   if (m == 0) {
     hipLaunchKernelGGL(k_fill_i32, dim3(nblk(nrows + 1)), dim3(kBlock), 0, c.st, out.rp,
                        nrows + 1, 0);
     out.nnz = 0;
     out.col = h->mem.get<int32_t>(1);
     out.w = h->mem.get<double>(1);
+    if (pend && pend->n) read_dev(pt, pend->stats, sizeof(pt), c.st);
   } else {
     int32_t* head = tmp.get<int32_t>(m);
     int64_t* ridx = tmp.get<int64_t>(m + 1);
     hipLaunchKernelGGL(k_run_heads, dim3(nblk(m)), dim3(kBlock), 0, c.st, keys, m, head);
-    const int64_t R = scan_i32_to_i64(head, ridx, m, tmp, c.st, true);
-    int32_t* start = tmp.get<int32_t>(R + 1);
-    hipLaunchKernelGGL(k_run_starts, dim3(nblk(m)), dim3(kBlock), 0, c.st, head, ridx, m, R, start);
+    scan_i32_to_i64(head, ridx, m, tmp, c.st, false);
+    // the runs are the rows of a CSR over the pairs; R <= m is still on the device
+    int32_t* start = tmp.get<int32_t>(m + 1);
+    hipLaunchKernelGGL(k_run_starts, dim3(nblk(m)), dim3(kBlock), 0, c.st, head, ridx, m,
+                       (const int64_t*)(ridx + m), start);
+    const int* rstats = sched_stats(start, m, ridx + m, tmp, c.st);
+    int64_t R = 0;
+    int rt[kStat];
+    DevRead rd[3] = {{&R, ridx + m, sizeof(R)}, {rt, rstats, sizeof(rt)}, {pt, nullptr, 0}};
+    int nread = 2;
+    if (pend && pend->n) rd[nread++] = {pt, pend->stats, sizeof(pt)};
+    read_dev_n(rd, nread, c.st);
     out.nnz = R;
     out.col = h->mem.get<int32_t>(R);
     out.w = h->mem.get<double>(R);
     Sched rs;
-    build_sched(rs, start, R, m, tmp, tmp, c.st);
+    sched_layout(rs, rt, start, R, m, false, tmp, tmp, c.st);
     {
       ProfScope ps("galerkin_reduce", c.st, (double)m * 16.0 + (double)R * 12.0);
       run_rows(rs, start, RunXsumOp{vals, keys, start, out.col, out.w, c.flags}, c.st);
@@ -929,7 +959,8 @@ void assemble(Ctx& c, uint64_t* keys, double* vals, int64_t m, int64_t nrows, Le
                        nrows, out.rp);
     LG_LAUNCH_CHECK();
   }
-  build_sched(out.sched, out.rp, out.n, out.nnz, h->mem, tmp, c.st);
+  if (pend) sched_layout(*pend->s, pt, pend->rp, pend->n, pend->nnz, false, h->mem, tmp, c.st);
+  build_sched(out.sched, out.rp, out.n, out.nnz, h->mem, tmp, c.st, h->opts.merge_path != 0);
   check_isolated(out);
   level_diag(c, out);
 }
@@ -984,13 +1015,18 @@ void build_elim(Ctx& c, Level& L, const ElimChoice& ch, Level& out) {
                      L.cidx, nnz, dcnt, fcnt, ptflag);
   int64_t* offd = tmp.get<int64_t>(nnz + 1);
   int64_t* offf = tmp.get<int64_t>(nnz + 1);
+  int64_t* off2 = tmp.get<int64_t>(nnz + 1);
   scan_i32_to_i64(dcnt, offd, nnz, tmp, c.st, false);
   scan_i32_to_i64(fcnt, offf, nnz, tmp, c.st, false);
-  int64_t tot[2];
-  LG_HIP(hipMemcpyAsync(c.pair, offd + nnz, sizeof(int64_t), hipMemcpyDeviceToDevice, c.st));
-  LG_HIP(hipMemcpyAsync(c.pair + 1, offf + nnz, sizeof(int64_t), hipMemcpyDeviceToDevice, c.st));
-  read_dev(tot, c.pair, sizeof(tot), c.st);  // both totals, one synchronisation
-  const int64_t na = tot[0], nfill = tot[1], m = na + nfill;
+  scan_i32_to_i64(ptflag, off2, nnz, tmp, c.st, false);
+  int64_t na = 0, nfill = 0, npt = 0;
+  {
+    const DevRead rd[3] = {{&na, offd + nnz, sizeof(na)},
+                           {&nfill, offf + nnz, sizeof(nfill)},
+                           {&npt, off2 + nnz, sizeof(npt)}};
+    read_dev_n(rd, 3, c.st);  // all three totals, one round trip
+  }
+  const int64_t m = na + nfill;
   uint64_t* dkeys = tmp.get<uint64_t>(na);
   double* dvals = tmp.get<double>(na);
   uint64_t* fkeys = tmp.get<uint64_t>(nfill);
@@ -1026,8 +1062,6 @@ void build_elim(Ctx& c, Level& L, const ElimChoice& ch, Level& out) {
     tmp.rewind(mm);
   }
   // transfer data: F-part of P^T
-  int64_t* off2 = tmp.get<int64_t>(nnz + 1);
-  const int64_t npt = scan_i32_to_i64(ptflag, off2, nnz, tmp, c.st, true);
   L.ptrp = h->mem.get<int32_t>(nc + 1);
   L.ptf = h->mem.get<int32_t>(npt);
   L.ptc = h->mem.get<double>(npt);
@@ -1036,9 +1070,10 @@ void build_elim(Ctx& c, Level& L, const ElimChoice& ch, Level& out) {
   hipLaunchKernelGGL(k_pt_rowptr, dim3(nblk(n)), dim3(kBlock), 0, c.st, L.rp, L.cidx, off2, n, npt,
                      nc, L.ptrp);
   LG_LAUNCH_CHECK();
-  build_sched(L.ptsched, L.ptrp, nc, npt, h->mem, tmp, c.st);
+  const PendingSched pend{&L.ptsched, nc ? sched_stats(L.ptrp, nc, nullptr, tmp, c.st) : nullptr,
+                          L.ptrp, nc, npt};
   L.nnzP = nc + npt;  // each eliminated vertex's entries appear once in P^T
-  assemble(c, keys, vals, m, nc, out);
+  assemble(c, keys, vals, m, nc, out, &pend);
 }
 
 // Section 3.5: four smoothed test vectors and the normalised affinity S.
@@ -1125,15 +1160,23 @@ void galerkin(Ctx& c, Level& L, int64_t nc, Level& out) {
     hipLaunchKernelGGL(k_rowptr_sorted, dim3(nblk(n)), dim3(kBlock), 0, c.st, mk,
                        (const int32_t*)nullptr, n, 0, nc, L.mptr);
     LG_LAUNCH_CHECK();
-    build_sched(L.msched, L.mptr, nc, n, h->mem, tmp, c.st);
   }
+  // the member schedule's statistics come back with the pair count below
+  const int* mstats = nc ? sched_stats(L.mptr, nc, nullptr, tmp, c.st) : nullptr;
   int32_t* rowidx = tmp.get<int32_t>(nnz);
   row_index(c, L, rowidx);
   int32_t* flag = tmp.get<int32_t>(nnz);
   hipLaunchKernelGGL(k_gal_flags, dim3(nblk(nnz)), dim3(kBlock), 0, c.st, rowidx, L.col, L.agg,
                      nnz, flag);
   int64_t* off = tmp.get<int64_t>(nnz + 1);
-  const int64_t m = scan_i32_to_i64(flag, off, nnz, tmp, c.st, true);
+  scan_i32_to_i64(flag, off, nnz, tmp, c.st, false);
+  int64_t m = 0;
+  int mt[kStat] = {};
+  {
+    const DevRead rd[2] = {{&m, off + nnz, sizeof(m)}, {mt, mstats, sizeof(mt)}};
+    read_dev_n(rd, mstats ? 2 : 1, c.st);
+  }
+  sched_layout(L.msched, mt, L.mptr, nc, n, false, h->mem, tmp, c.st);
   uint64_t* keys = tmp.get<uint64_t>(m);
   double* vals = tmp.get<double>(m);
   hipLaunchKernelGGL(k_gal_emit, dim3(nblk(nnz)), dim3(kBlock), 0, c.st, rowidx, L.col, L.w, L.agg,
@@ -1194,14 +1237,12 @@ void coarsest(Ctx& c, Level& L) {
     int* seen = c.tmp.get<int>(n);
     int* qa = c.tmp.get<int>(n);
     int* qb = c.tmp.get<int>(n);
-    int* cnt = c.tmp.get<int>(1);
+    // reported with the other flags at the end of setup; a split coarsest
+    // level only makes the dense elimination below produce unused values
     hipLaunchKernelGGL(k_coarse_connected, dim3(1), dim3(1024), 0, c.st, L.rp, L.col, (int)n, seen,
-                       qa, qb, cnt);
+                       qa, qb, c.flags);
     LG_LAUNCH_CHECK();
-    int reached = 0;
-    read_dev(&reached, cnt, sizeof(int), c.st);
     c.tmp.rewind(m);
-    if (reached != n) fail(LG_E_DISCONNECTED, "graph is not connected (coarsest level splits)");
   }
   h->Lplus = h->mem.get<double>(n * n);
   hipLaunchKernelGGL(k_dense_lap, dim3((unsigned)n), dim3(kBlock), 0, c.st, L.rp, L.col, L.w, L.d,
@@ -1238,7 +1279,6 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
   c.st = st;
   c.key = seed_key(o.seed);
   c.flags = h->mem.get<int>(4);
-  c.pair = h->mem.get<int64_t>(2);
   if (!h->capture_stream) LG_HIP(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
   c.side.s = h->capture_stream;
   LG_HIP(hipEventCreateWithFlags(&c.side.ready, hipEventDisableTiming));
@@ -1267,7 +1307,7 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
     check_flags(c);  // row pointers must be sane before any row pass
     c.tmp.rewind(m);
   }
-  build_sched(L0->sched, L0->rp, n, nnz, h->mem, c.tmp, st);
+  build_sched(L0->sched, L0->rp, n, nnz, h->mem, c.tmp, st, o.merge_path != 0);
   check_isolated(*L0);
   if (o.validate && nnz) {
     Arena::Mark m = c.tmp.mark();
@@ -1281,11 +1321,12 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
     hipLaunchKernelGGL(k_validate_pairs, dim3(1), dim3(64), 0, st, (const unsigned long long*)searched,
                        nnz, c.flags);
     LG_LAUNCH_CHECK();
-    check_flags(c);
-    c.tmp.rewind(m);
+    c.tmp.rewind(m);  // later work on the stream runs after these kernels
   }
+  // The diagonal pass reads the weights along the (already checked) row
+  // pointers only, so it runs before the validation flags come back; both
+  // come back with the total weight, in one round trip.
   level_diag(c, *L0);
-  check_flags(c);
   {
     // total weight guard of the exact sums
     Arena::Mark m = c.tmp.mark();
@@ -1293,7 +1334,10 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
     double* tot = c.tmp.get<double>(1);
     reduce_dev<RED_SUM>(L0->d, nullptr, nullptr, n, part, tot, st);
     double total = 0.0;
-    read_dev(&total, tot, sizeof(double), st);
+    int f = 0;
+    const DevRead rd[2] = {{&f, c.flags, sizeof(f)}, {&total, tot, sizeof(total)}};
+    read_dev_n(rd, 2, st);
+    raise_flags(f);
     if (!(total < 0x1p62)) fail(LG_E_RANGE, "total edge weight must be below 2^62");
     c.tmp.rewind(m);
   }
@@ -1361,13 +1405,15 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
     for (int i = 0; i < l; i++) make_f32(c, h->lev[i]);
   LG_HIP(hipEventRecord(c.side.done, c.side.s));
   LG_HIP(hipStreamWaitEvent(st, c.side.done, 0));
-  std::vector<double> lm(l + 1, 0.0);
-  read_dev(lm.data(), h->lmax_dev, sizeof(double) * (l + 1), st);
-  for (int i = 0; i <= l; i++) h->lev[i].lmax = h->lev[i].type == LG_LEVEL_AGG ? lm[i] : 0.0;
   // After validation the level loop can only raise F_XSUM (an exact sum out of
-  // range), which never affects an index; it is reported here, once, instead
-  // of after every level.
-  check_flags(c);
+  // range) and the coarsest level F_SPLIT, neither of which affects an index;
+  // they come back here, with the eigenvalue estimates, in one round trip.
+  std::vector<double> lm(l + 1, 0.0);
+  int f = 0;
+  const DevRead rd[2] = {{&f, c.flags, sizeof(f)}, {lm.data(), h->lmax_dev, sizeof(double) * (l + 1)}};
+  read_dev_n(rd, 2, st);
+  raise_flags(f);
+  for (int i = 0; i <= l; i++) h->lev[i].lmax = h->lev[i].type == LG_LEVEL_AGG ? lm[i] : 0.0;
 }
 
 }  // namespace lg
