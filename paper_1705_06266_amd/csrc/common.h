@@ -46,6 +46,9 @@ constexpr int kBlock = 256;
 #ifndef LG_XSUM_UNROLL
 #define LG_XSUM_UNROLL 1
 #endif
+#ifndef LG_LAP_UNROLL
+#define LG_LAP_UNROLL 4
+#endif
 constexpr int kHubChunk = LG_HUB_CHUNK;
 constexpr uint64_t kGolden = 0x9e3779b97f4a7c15ULL;
 

@@ -31,6 +31,7 @@ enum { LAP_SPMV = 0, LAP_RESID = 1, LAP_CHEB = 2, LAP_CHEB_FIRST = 3, LAP_CHEB_Z
 template <typename T, int K, int MODE, int TAG = 0>
 struct LapOp {
   using Acc = VecAcc<T, K>;
+  static constexpr int kUnroll = LG_LAP_UNROLL;
   const int32_t* __restrict__ col;
   const T* __restrict__ w;
   const T* __restrict__ d;

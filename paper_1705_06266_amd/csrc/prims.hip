@@ -619,31 +619,89 @@ __global__ __launch_bounds__(kStat * 64) void k_sched_final(const int* __restric
   if (lane == 0) out[k] = r;
 }
 
-__global__ void k_class_keys(const int32_t* __restrict__ rp, int64_t n, int hub_deg,
-                             uint64_t* __restrict__ keys, uint64_t* __restrict__ vals) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  keys[i] = (uint64_t)degree_class(rp[i + 1] - rp[i], hub_deg);
-  vals[i] = (uint64_t)i;
-}
+// Rows grouped by degree class, in one kernel.  A workgroup takes kPermTile
+// consecutive rows: it counts its rows of each class, reserves its share of
+// each class with one atomic per class (ctr[2 + c]), then places its rows in
+// row order, a round of kBlock rows at a time; hubs and split rows are
+// appended to their lists (ctr[0], ctr[1]; split rows with their chunk
+// counts).  ctr is zero on entry.  Where a workgroup's share lands varies
+// between runs; a row's result does not depend on its place in the schedule.
+constexpr int kPermIPT = 16;
+constexpr int64_t kPermTile = (int64_t)kBlock * kPermIPT;
 
-__global__ void k_u64_to_i32_n(const uint64_t* __restrict__ in, int64_t n, int32_t* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) out[i] = (int32_t)in[i];
-}
-
-__global__ void k_sched_lists(const int32_t* __restrict__ rp, int64_t n, int hub_deg,
-                              int* __restrict__ ctr, int32_t* __restrict__ hub_rows,
-                              int32_t* __restrict__ split_rows, int32_t* __restrict__ split_nch) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const int d = rp[i + 1] - rp[i];
-  if (d > kSplitDeg) {
-    const int k = atomicAdd(&ctr[1], 1);
-    split_rows[k] = (int32_t)i;
-    split_nch[k] = (d + kHubChunk - 1) / kHubChunk;
-  } else if (d > hub_deg) {
-    hub_rows[atomicAdd(&ctr[0], 1)] = (int32_t)i;
+__global__ __launch_bounds__(kBlock) void k_class_perm(
+    const int32_t* __restrict__ rp, int64_t n, int hub_deg, ClassTable ct, int* __restrict__ ctr,
+    int32_t* __restrict__ perm, int32_t* __restrict__ hub_rows, int32_t* __restrict__ split_rows,
+    int32_t* __restrict__ split_nch) {
+  __shared__ int wcnt[kBlock / 64][kClasses];
+  __shared__ int run[kClasses];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t b0 = (int64_t)blockIdx.x * kPermTile;
+  // pass 1: this workgroup's class counts; hubs and split rows go to their lists
+  int cnt[kClasses];
+#pragma unroll
+  for (int k = 0; k < kClasses; k++) cnt[k] = 0;
+  for (int r = 0; r < kPermIPT; r++) {
+    const int64_t i = b0 + (int64_t)r * kBlock + t;
+    if (i >= n) break;
+    const int d = rp[i + 1] - rp[i];
+    const int c = degree_class(d, hub_deg);
+    if (c < kClasses) {
+#pragma unroll
+      for (int k = 0; k < kClasses; k++) cnt[k] += (c == k);
+    } else if (d > kSplitDeg) {
+      const int k = atomicAdd(&ctr[1], 1);
+      split_rows[k] = (int32_t)i;
+      split_nch[k] = (d + kHubChunk - 1) / kHubChunk;
+    } else {
+      hub_rows[atomicAdd(&ctr[0], 1)] = (int32_t)i;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kClasses; k++) {
+    int v = cnt[k];
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+    if (lane == 0) wcnt[w][k] = v;
+  }
+  __syncthreads();
+  if (t < kClasses) {
+    int tot = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / 64; k++) tot += wcnt[k][t];
+    run[t] = tot ? atomicAdd(&ctr[2 + t], tot) : 0;
+  }
+  // pass 2: place the class rows in row order
+  const uint64_t lt = (lane == 0) ? 0ULL : ((~0ULL) >> (64 - lane));
+  for (int r = 0; r < kPermIPT; r++) {
+    if (b0 + (int64_t)r * kBlock >= n) break;  // the same for every thread
+    const int64_t i = b0 + (int64_t)r * kBlock + t;
+    int c = -1;
+    if (i < n) {
+      c = degree_class(rp[i + 1] - rp[i], hub_deg);
+      if (c >= kClasses) c = -1;
+    }
+    __syncthreads();  // run[] is current, the previous round's wcnt is read
+    int rank = 0;
+#pragma unroll
+    for (int k = 0; k < kClasses; k++) {
+      const uint64_t m = __ballot(c == k);
+      if (c == k) rank = __popcll(m & lt);
+      if (lane == 0) wcnt[w][k] = __popcll(m);
+    }
+    __syncthreads();
+    if (c >= 0) {
+      int pos = run[c] + rank;
+      for (int k = 0; k < w; k++) pos += wcnt[k][c];
+      perm[ct.cls_start[c] + pos] = (int32_t)i;
+    }
+    __syncthreads();
+    if (t < kClasses) {
+      int add = 0;
+#pragma unroll
+      for (int k = 0; k < kBlock / 64; k++) add += wcnt[k][t];
+      run[t] += add;
+    }
   }
 }
 
@@ -808,27 +866,17 @@ void sched_layout(Sched& s, const int* t, const int32_t* rp, int64_t n, int64_t 
   }
   s.ct.cls_start[kClasses] = (int32_t)pos;
   s.ct.blk_start[kClasses] = (int32_t)blk;
-  // rows grouped by class, increasing row id inside a class (stable sort)
+  // rows grouped by class, hubs and split rows listed: one pass (k_class_perm)
   {
-    uint64_t* keys = tmp.get<uint64_t>(n);
-    uint64_t* vals = tmp.get<uint64_t>(n);
-    hipLaunchKernelGGL(k_class_keys, dim3((unsigned)nb), dim3(kBlock), 0, st, rp, n, s.hub_deg, keys,
-                       vals);
-    const SortedPairs sp = radix_sort_pairs(keys, vals, n, std::vector<int>{0}, tmp, st);
+    int* ctr = tmp.get<int>(kClasses + 2);
+    hipLaunchKernelGGL(k_zero_i32n, dim3(1), dim3(kBlock), 0, st, (int32_t*)ctr,
+                       (int64_t)(kClasses + 2));
     s.perm = keep.get<int32_t>(pos);
-    if (pos)
-      hipLaunchKernelGGL(k_u64_to_i32_n, dim3((unsigned)ceil_div(pos, kBlock)), dim3(kBlock), 0, st,
-                         (const uint64_t*)sp.vals, pos, s.perm);
-    LG_LAUNCH_CHECK();
-  }
-  if (s.nhub || s.nsplit) {
-    int* ctr = tmp.get<int>(2);
-    hipLaunchKernelGGL(k_zero_i32n, dim3(1), dim3(kBlock), 0, st, (int32_t*)ctr, (int64_t)2);
-    s.hub_rows = keep.get<int32_t>(s.nhub);
-    s.split_rows = keep.get<int32_t>(s.nsplit);
-    int32_t* nch = tmp.get<int32_t>(s.nsplit);
-    hipLaunchKernelGGL(k_sched_lists, dim3((unsigned)nb), dim3(kBlock), 0, st, rp, n, s.hub_deg, ctr,
-                       s.hub_rows, s.split_rows, nch);
+    s.hub_rows = s.nhub ? keep.get<int32_t>(s.nhub) : nullptr;
+    s.split_rows = s.nsplit ? keep.get<int32_t>(s.nsplit) : nullptr;
+    int32_t* nch = s.nsplit ? tmp.get<int32_t>(s.nsplit) : nullptr;
+    hipLaunchKernelGGL(k_class_perm, dim3((unsigned)ceil_div(n, kPermTile)), dim3(kBlock), 0, st, rp,
+                       n, s.hub_deg, s.ct, ctr, s.perm, s.hub_rows, s.split_rows, nch);
     LG_LAUNCH_CHECK();
     if (s.nsplit) {
       int64_t* start = tmp.get<int64_t>(s.nsplit + 1);
