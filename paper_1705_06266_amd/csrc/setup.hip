@@ -711,31 +711,6 @@ __global__ void k_lz_init_scalars(double* lz) {
   for (int i = threadIdx.x; i < LZ_SIZE; i += blockDim.x) lz[i] = 0.0;
 }
 
-// u <- D^-1 u - alpha_j q - beta_{j-1} q_prev
-__global__ void k_lz_update(double* __restrict__ u, const double* __restrict__ q,
-                            const double* __restrict__ qp, const double* __restrict__ d, int64_t n,
-                            const double* __restrict__ lz, int j) {
-  if (lz[LZ_STOP] != 0.0) return;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const double a = lz[LZ_AL + j];
-  const double bp = j > 0 ? lz[LZ_BE + j - 1] : 0.0;
-  u[i] = u[i] / d[i] - a * q[i] - bp * qp[i];
-}
-
-__global__ void k_lz_beta(double* lz, int j, int steps) {
-  if (lz[LZ_STOP] != 0.0) return;
-  const double a = lz[LZ_AL + j];
-  const double bp = j > 0 ? lz[LZ_BE + j - 1] : 0.0;
-  const double b = sqrt(lz[LZ_B2]);
-  double scale = lz[LZ_SCALE];
-  if (fabs(a) + bp > scale) scale = fabs(a) + bp;
-  lz[LZ_SCALE] = scale;
-  lz[LZ_M] = (double)(j + 1);
-  if (j == steps - 1 || b <= 1e-12 * scale) lz[LZ_STOP] = 1.0;
-  else lz[LZ_BE + j] = b;
-}
-
 __global__ void k_lz_next(double* __restrict__ u, double* __restrict__ q, double* __restrict__ qp,
                           int64_t n, const double* __restrict__ lz, int j) {
   if (lz[LZ_STOP] != 0.0) return;
@@ -744,6 +719,69 @@ __global__ void k_lz_next(double* __restrict__ u, double* __restrict__ q, double
   const double b = lz[LZ_BE + j];
   qp[i] = q[i];
   q[i] = u[i] / b;
+}
+
+// Sum of nb partials by one workgroup, in the same order as k_red2, so that
+// every workgroup that calls it obtains the same bits.
+__device__ __forceinline__ double block_sum_partials(const double* __restrict__ partial, int nb,
+                                                     double* sm) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kBlock) s += partial[i];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int m = kBlock / 2; m > 0; m >>= 1) {
+    if ((int)threadIdx.x < m) sm[threadIdx.x] += sm[threadIdx.x + m];
+    __syncthreads();
+  }
+  const double r = sm[0];
+  __syncthreads();
+  return r;
+}
+
+// One Lanczos step after u = L q and the partials of q . u: alpha from those
+// partials, u <- D^-1 u - alpha q - beta_{j-1} q_prev, and the partials of
+// u . D u for beta (grid-stride over a fixed grid, like k_red1).
+__global__ __launch_bounds__(kBlock) void k_lz_update_dd(
+    double* __restrict__ u, const double* __restrict__ q, const double* __restrict__ qp,
+    const double* __restrict__ d, int64_t n, double* __restrict__ lz, int j,
+    const double* __restrict__ dot_part, int nb_dot, double* __restrict__ dd_part) {
+  __shared__ double sm[kBlock];
+  if (lz[LZ_STOP] != 0.0) return;  // uniform: every workgroup reads the same flag
+  const double a = block_sum_partials(dot_part, nb_dot, sm);
+  if (blockIdx.x == 0 && threadIdx.x == 0) lz[LZ_AL + j] = a;
+  const double bp = j > 0 ? lz[LZ_BE + j - 1] : 0.0;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    const double v = u[i] / d[i] - a * q[i] - bp * qp[i];
+    u[i] = v;
+    s += d[i] * v * v;
+  }
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int m = kBlock / 2; m > 0; m >>= 1) {
+    if ((int)threadIdx.x < m) sm[threadIdx.x] += sm[threadIdx.x + m];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dd_part[blockIdx.x] = sm[0];
+}
+
+// beta_j from the partials of u . D u, then the stopping test.
+__global__ __launch_bounds__(kBlock) void k_lz_beta_dd(const double* __restrict__ dd_part, int nb,
+                                                       double* lz, int j, int steps) {
+  __shared__ double sm[kBlock];
+  if (lz[LZ_STOP] != 0.0) return;
+  const double b2 = block_sum_partials(dd_part, nb, sm);
+  if (threadIdx.x != 0) return;
+  const double a = lz[LZ_AL + j];
+  const double bp = j > 0 ? lz[LZ_BE + j - 1] : 0.0;
+  const double b = sqrt(b2);
+  double scale = lz[LZ_SCALE];
+  if (fabs(a) + bp > scale) scale = fabs(a) + bp;
+  lz[LZ_SCALE] = scale;
+  lz[LZ_M] = (double)(j + 1);
+  if (j == steps - 1 || b <= 1e-12 * scale) lz[LZ_STOP] = 1.0;
+  else lz[LZ_BE + j] = b;
 }
 
 __device__ int sturm_below(const double* a, const double* b, int m, double x) {
@@ -1212,14 +1250,19 @@ void lanczos(Ctx& c, Level& L, int level, double* out) {
   hipLaunchKernelGGL(k_lz_center, dim3(nblk(n)), dim3(kBlock), 0, st, q, n, lz);
   reduce_dev<RED_DDOT>(q, nullptr, L.d, n, part, lz + LZ_B2, st);
   hipLaunchKernelGGL(k_lz_scale, dim3(nblk(n)), dim3(kBlock), 0, st, q, n, lz);
+  double* part2 = tmp.get<double>(kRedBlocks);
+  const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ceil_div(n, kBlock)));
   for (int j = 0; j < steps; j++) {
     LapOp<double, 1, LAP_SPMV> op{L.col, L.w, L.d, L.dinv, q, u, nullptr, nullptr, 0.0, 0.0, 0.0};
     // same kernel and bytes as the solve's fp64 product (family "spmv")
     run_rows(L.sched, L.rp, op, st, "spmv", 4.0 * (n + 1) + 12.0 * L.nnz + 24.0 * n);
-    reduce_dev<RED_DOT>(q, u, nullptr, n, part, lz + LZ_AL + j, st);
-    hipLaunchKernelGGL(k_lz_update, dim3(nblk(n)), dim3(kBlock), 0, st, u, q, qp, L.d, n, lz, j);
-    reduce_dev<RED_DDOT>(u, nullptr, L.d, n, part, lz + LZ_B2, st);
-    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(1), 0, st, lz, j, steps);
+    hipLaunchKernelGGL((k_red1<RED_DOT>), dim3(nb), dim3(kBlock), 0, st, (const double*)q,
+                       (const double*)u, (const double*)nullptr, n, part);
+    hipLaunchKernelGGL(k_lz_update_dd, dim3(nb), dim3(kBlock), 0, st, u, (const double*)q,
+                       (const double*)qp, (const double*)L.d, n, lz, j, (const double*)part, nb,
+                       part2);
+    hipLaunchKernelGGL(k_lz_beta_dd, dim3(1), dim3(kBlock), 0, st, (const double*)part2, nb, lz, j,
+                       steps);
     hipLaunchKernelGGL(k_lz_next, dim3(nblk(n)), dim3(kBlock), 0, st, u, q, qp, n, lz, j);
   }
   hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(64), 0, st, lz, out);
