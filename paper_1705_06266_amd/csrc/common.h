@@ -798,6 +798,8 @@ void run_merge(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st,
 // ------------------------------------------------------------- memory
 // Bump allocator over large device chunks.  The hierarchy owns one for its
 // lifetime; setup uses a second one for temporaries and rewinds it per level.
+// Released chunks go to a process-wide cache (bounded) that later arenas on
+// the same device draw from before calling hipMalloc.
 class Arena {
  public:
   explicit Arena(size_t chunk = (size_t)64 << 20) : chunk_(chunk) {}
@@ -824,6 +826,7 @@ class Arena {
   struct Chunk {
     char* p;
     size_t size;
+    int dev;
   };
   std::vector<Chunk> chunks_;
   size_t cur_ = 0, off_ = 0, total_ = 0, chunk_;

@@ -19,6 +19,41 @@ const char* last_error_cstr() { return g_last_error.c_str(); }
 [[noreturn]] void fail(lg_status code, const std::string& msg) { throw Error{code, msg}; }
 
 // ------------------------------------------------------------------ arena
+// Device chunks of released arenas are kept, up to kChunkCacheBytes per
+// process, and handed to later arenas on the same device: hipMalloc and
+// hipFree of tens of megabytes cost tens to hundreds of microseconds each,
+// which a setup that follows a release (a serving loop, a benchmark) would
+// otherwise pay every time.  A cached chunk serves a request of at least 4/5
+// of its size.
+namespace {
+struct CachedChunk {
+  char* p;
+  size_t size;
+  int dev;
+};
+std::mutex g_chunk_mu;
+std::vector<CachedChunk> g_chunk_cache;
+size_t g_chunk_cache_bytes = 0;
+constexpr size_t kChunkCacheBytes = (size_t)4 << 30;
+
+char* chunk_take(size_t want, int dev, size_t* got) {
+  std::lock_guard<std::mutex> g(g_chunk_mu);
+  int best = -1;
+  for (size_t k = 0; k < g_chunk_cache.size(); k++) {
+    const CachedChunk& c = g_chunk_cache[k];
+    if (c.dev == dev && c.size >= want && c.size - want <= want / 4 &&
+        (best < 0 || c.size < g_chunk_cache[best].size))
+      best = (int)k;
+  }
+  if (best < 0) return nullptr;
+  const CachedChunk c = g_chunk_cache[best];
+  g_chunk_cache.erase(g_chunk_cache.begin() + best);
+  g_chunk_cache_bytes -= c.size;
+  *got = c.size;
+  return c.p;
+}
+}  // namespace
+
 void* Arena::alloc(size_t bytes) {
   bytes = (bytes + 255) & ~(size_t)255;
   while (cur_ < chunks_.size()) {
@@ -32,13 +67,20 @@ void* Arena::alloc(size_t bytes) {
     off_ = 0;
   }
   size_t sz = bytes > chunk_ ? bytes : chunk_;
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, sz);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    fail(LG_E_NOMEM, "device allocation of " + std::to_string(sz) + " bytes failed");
+  int dev = 0;
+  LG_HIP(hipGetDevice(&dev));
+  size_t got = 0;
+  char* p = chunk_take(sz, dev, &got);
+  if (p) {
+    sz = got;
+  } else {
+    hipError_t e = hipMalloc((void**)&p, sz);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(LG_E_NOMEM, "device allocation of " + std::to_string(sz) + " bytes failed");
+    }
   }
-  chunks_.push_back({(char*)p, sz});
+  chunks_.push_back({p, sz, dev});
   total_ += sz;
   cur_ = chunks_.size() - 1;
   off_ = bytes;
@@ -46,7 +88,30 @@ void* Arena::alloc(size_t bytes) {
 }
 
 void Arena::release() {
-  for (auto& c : chunks_) (void)hipFree(c.p);
+  if (chunks_.empty()) return;
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  // work still queued on the device may use the memory: wait for it, as
+  // hipFree would, before another arena can take a chunk
+  bool synced = false;
+  for (auto& c : chunks_) {
+    bool keep = false;
+    if (c.dev == dev) {
+      std::lock_guard<std::mutex> g(g_chunk_mu);
+      keep = g_chunk_cache_bytes + c.size <= kChunkCacheBytes;
+      if (keep) g_chunk_cache_bytes += c.size;  // reserved; the chunk is added below
+    }
+    if (!keep) {
+      (void)hipFree(c.p);
+      continue;
+    }
+    if (!synced) {
+      (void)hipDeviceSynchronize();
+      synced = true;
+    }
+    std::lock_guard<std::mutex> g(g_chunk_mu);
+    g_chunk_cache.push_back({c.p, c.size, c.dev});
+  }
   chunks_.clear();
   cur_ = off_ = total_ = 0;
 }
