@@ -51,12 +51,10 @@ struct NoAcc {
 // searching entries map one-to-one onto distinct non-searching partners, so
 // the matrix is symmetric iff every search succeeds with an equal weight and
 // exactly half of the entries search (k_validate_pairs).
-constexpr int kValidateSlots = 64;
-
 __global__ void k_validate(const int32_t* __restrict__ rowidx, const int32_t* __restrict__ rp,
                            const int32_t* __restrict__ col, const double* __restrict__ w,
                            int64_t n, int64_t nnz, int* __restrict__ flags,
-                           unsigned long long* __restrict__ searched) {
+                           int32_t* __restrict__ searched) {
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   int f = 0;
   bool srch = false;
@@ -74,7 +72,14 @@ __global__ void k_validate(const int32_t* __restrict__ rowidx, const int32_t* __
       int lo = rp[j], hi = rp[j + 1] - 1;
       const int dj = hi + 1 - lo, di = rp[row + 1] - r0;
       srch = dj < di || (dj == di && j < row);
-      if (srch) {
+      if (srch && dj <= 32) {
+        // short row: independent loads, one round trip
+        int found = -1;
+#pragma unroll 8
+        for (int k = 0; k < dj; k++)
+          if (col[lo + k] == row) found = lo + k;
+        if (found < 0 || w[found] != we) f |= F_ASYM;
+      } else if (srch) {
         int found = -1;
         while (lo <= hi) {
           const int mid = lo + ((hi - lo) >> 1);
@@ -92,19 +97,36 @@ __global__ void k_validate(const int32_t* __restrict__ rowidx, const int32_t* __
   }
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) f |= __shfl_xor(f, m);
-  const unsigned long long cnt = __popcll(__ballot(srch));
+  __shared__ int wcnt[kBlock / 64];
+  const int cnt = __popcll(__ballot(srch));  // the whole wavefront's searches
   if ((threadIdx.x & 63) == 0) {
     if (f) atomicOr(flags, f);
-    if (cnt) atomicAdd(&searched[(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) % kValidateSlots], cnt);
+    wcnt[threadIdx.x >> 6] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / 64; k++) c += wcnt[k];
+    searched[blockIdx.x] = c;  // one slot per workgroup: no contended atomics
   }
 }
 
-__global__ void k_validate_pairs(const unsigned long long* __restrict__ searched, int64_t nnz,
-                                 int* __restrict__ flags) {
-  unsigned long long v = threadIdx.x < kValidateSlots ? searched[threadIdx.x] : 0ULL;
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
-  if (threadIdx.x == 0 && 2 * v != (unsigned long long)nnz) atomicOr(flags, F_ASYM);
+// Total of the per-workgroup search counts against nnz / 2.
+constexpr int kPairThreads = 1024;
+__global__ __launch_bounds__(kPairThreads) void k_validate_pairs(const int32_t* __restrict__ searched,
+                                                                 int64_t nb, int64_t nnz,
+                                                                 int* __restrict__ flags) {
+  __shared__ unsigned long long sm[kPairThreads];
+  unsigned long long v = 0;
+  for (int64_t i = threadIdx.x; i < nb; i += kPairThreads) v += (unsigned long long)searched[i];
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int m = kPairThreads / 2; m > 0; m >>= 1) {
+    if ((int)threadIdx.x < m) sm[threadIdx.x] += sm[threadIdx.x + m];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && 2 * sm[0] != (unsigned long long)nnz) atomicOr(flags, F_ASYM);
 }
 
 // ------------------------------------------------------------ connectivity
@@ -1355,14 +1377,13 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
   if (o.validate && nnz) {
     Arena::Mark m = c.tmp.mark();
     int32_t* rowidx = c.tmp.get<int32_t>(nnz);
-    unsigned long long* searched = c.tmp.get<unsigned long long>(kValidateSlots);
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, st, (int32_t*)searched,
-                       (int64_t)(2 * kValidateSlots), 0);
+    const int64_t nbv = nblk(nnz);
+    int32_t* searched = c.tmp.get<int32_t>(nbv);
     run_rows(L0->sched, L0->rp, RowIdxOp{rowidx}, st);
-    hipLaunchKernelGGL(k_validate, dim3(nblk(nnz)), dim3(kBlock), 0, st, rowidx, L0->rp, L0->col,
+    hipLaunchKernelGGL(k_validate, dim3((unsigned)nbv), dim3(kBlock), 0, st, rowidx, L0->rp, L0->col,
                        L0->w, n, nnz, c.flags, searched);
-    hipLaunchKernelGGL(k_validate_pairs, dim3(1), dim3(64), 0, st, (const unsigned long long*)searched,
-                       nnz, c.flags);
+    hipLaunchKernelGGL(k_validate_pairs, dim3(1), dim3(kPairThreads), 0, st, (const int32_t*)searched,
+                       nbv, nnz, c.flags);
     LG_LAUNCH_CHECK();
     c.tmp.rewind(m);  // later work on the stream runs after these kernels
   }
