@@ -626,14 +626,15 @@ constexpr int kStatRows = 16;  // rows per thread in k_sched_stats
 // n_dev (optional): the actual row count on the device, at most n.
 __global__ __launch_bounds__(kBlock) void k_sched_stats(const int32_t* __restrict__ rp, int64_t n,
                                                         const int64_t* __restrict__ n_dev,
-                                                        int hub_deg, int* __restrict__ partial) {
+                                                        int rows, int hub_deg,
+                                                        int* __restrict__ partial) {
   if (n_dev) n = min(n, *n_dev);
   int v[kStat];
 #pragma unroll
   for (int k = 0; k < kStat; k++) v[k] = 0;
   v[ST_MIN] = 0x7fffffff;
-  for (int q = 0; q < kStatRows; q++) {
-    const int64_t i = ((int64_t)blockIdx.x * kStatRows + q) * kBlock + threadIdx.x;
+  for (int q = 0; q < rows; q++) {
+    const int64_t i = ((int64_t)blockIdx.x * rows + q) * kBlock + threadIdx.x;
     if (i >= n) break;
     const int d = rp[i + 1] - rp[i];
     const int c = degree_class(d, hub_deg);
@@ -684,29 +685,35 @@ __global__ __launch_bounds__(kStat * 64) void k_sched_final(const int* __restric
   if (lane == 0) out[k] = r;
 }
 
-// Rows grouped by degree class, in one kernel.  A workgroup takes kPermTile
-// consecutive rows: it counts its rows of each class, reserves its share of
-// each class with one atomic per class (ctr[2 + c]), then places its rows in
-// row order, a round of kBlock rows at a time; hubs and split rows are
+// Rows grouped by degree class, in one kernel.  A workgroup takes ipt * kBlock
+// consecutive rows (ipt grows with n so that the class reservations stay
+// few): it counts its rows of each class, reserves its share of each class
+// with one atomic per class (ctr[2 + c]), then places its rows in row order,
+// a round of kBlock rows at a time; hubs and split rows are
 // appended to their lists (ctr[0], ctr[1]; split rows with their chunk
 // counts).  ctr is zero on entry.  Where a workgroup's share lands varies
 // between runs; a row's result does not depend on its place in the schedule.
-constexpr int kPermIPT = 16;
-constexpr int64_t kPermTile = (int64_t)kBlock * kPermIPT;
+constexpr int kPermMaxIPT = 16;
+
+// Rounds of kBlock rows per workgroup: one below about 2^17 rows, at most
+// kPermMaxIPT (about 512 workgroups, 8 reservations each, before that cap).
+inline int perm_ipt(int64_t n) {
+  return (int)std::min<int64_t>(kPermMaxIPT, std::max<int64_t>(1, ceil_div(n, (int64_t)kBlock * 512)));
+}
 
 __global__ __launch_bounds__(kBlock) void k_class_perm(
-    const int32_t* __restrict__ rp, int64_t n, int hub_deg, ClassTable ct, int* __restrict__ ctr,
-    int32_t* __restrict__ perm, int32_t* __restrict__ hub_rows, int32_t* __restrict__ split_rows,
-    int32_t* __restrict__ split_nch) {
+    const int32_t* __restrict__ rp, int64_t n, int ipt, int hub_deg, ClassTable ct,
+    int* __restrict__ ctr, int32_t* __restrict__ perm, int32_t* __restrict__ hub_rows,
+    int32_t* __restrict__ split_rows, int32_t* __restrict__ split_nch) {
   __shared__ int wcnt[kBlock / 64][kClasses];
   __shared__ int run[kClasses];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int64_t b0 = (int64_t)blockIdx.x * kPermTile;
+  const int64_t b0 = (int64_t)blockIdx.x * ipt * kBlock;
   // pass 1: this workgroup's class counts; hubs and split rows go to their lists
   int cnt[kClasses];
 #pragma unroll
   for (int k = 0; k < kClasses; k++) cnt[k] = 0;
-  for (int r = 0; r < kPermIPT; r++) {
+  for (int r = 0; r < ipt; r++) {
     const int64_t i = b0 + (int64_t)r * kBlock + t;
     if (i >= n) break;
     const int d = rp[i + 1] - rp[i];
@@ -738,7 +745,7 @@ __global__ __launch_bounds__(kBlock) void k_class_perm(
   }
   // pass 2: place the class rows in row order
   const uint64_t lt = (lane == 0) ? 0ULL : ((~0ULL) >> (64 - lane));
-  for (int r = 0; r < kPermIPT; r++) {
+  for (int r = 0; r < ipt; r++) {
     if (b0 + (int64_t)r * kBlock >= n) break;  // the same for every thread
     const int64_t i = b0 + (int64_t)r * kBlock + t;
     int c = -1;
@@ -888,10 +895,13 @@ __global__ void k_merge_split(const int32_t* __restrict__ rp, int64_t n, int64_t
 }
 
 int* sched_stats(const int32_t* rp, int64_t n, const int64_t* n_dev, Arena& tmp, hipStream_t st) {
-  const int64_t nbs = std::max<int64_t>(1, ceil_div(n, (int64_t)kBlock * kStatRows));
+  // rows per thread: one up to about 2^18 rows, then up to kStatRows
+  const int rows =
+      (int)std::min<int64_t>(kStatRows, std::max<int64_t>(1, ceil_div(n, (int64_t)kBlock * 1024)));
+  const int64_t nbs = std::max<int64_t>(1, ceil_div(n, (int64_t)kBlock * rows));
   int* part = tmp.get<int>(kStat * nbs);
   int* tot = tmp.get<int>(kStat);
-  hipLaunchKernelGGL(k_sched_stats, dim3((unsigned)nbs), dim3(kBlock), 0, st, rp, n, n_dev,
+  hipLaunchKernelGGL(k_sched_stats, dim3((unsigned)nbs), dim3(kBlock), 0, st, rp, n, n_dev, rows,
                      (int)LG_HUB_DEG, part);
   hipLaunchKernelGGL(k_sched_final, dim3(1), dim3(kStat * 64), 0, st, (const int*)part, nbs, tot);
   LG_LAUNCH_CHECK();
@@ -940,8 +950,9 @@ void sched_layout(Sched& s, const int* t, const int32_t* rp, int64_t n, int64_t 
     s.hub_rows = s.nhub ? keep.get<int32_t>(s.nhub) : nullptr;
     s.split_rows = s.nsplit ? keep.get<int32_t>(s.nsplit) : nullptr;
     int32_t* nch = s.nsplit ? tmp.get<int32_t>(s.nsplit) : nullptr;
-    hipLaunchKernelGGL(k_class_perm, dim3((unsigned)ceil_div(n, kPermTile)), dim3(kBlock), 0, st, rp,
-                       n, s.hub_deg, s.ct, ctr, s.perm, s.hub_rows, s.split_rows, nch);
+    const int ipt = perm_ipt(n);
+    hipLaunchKernelGGL(k_class_perm, dim3((unsigned)ceil_div(n, (int64_t)ipt * kBlock)), dim3(kBlock),
+                       0, st, rp, n, ipt, s.hub_deg, s.ct, ctr, s.perm, s.hub_rows, s.split_rows, nch);
     LG_LAUNCH_CHECK();
     if (s.nsplit) {
       int64_t* start = tmp.get<int64_t>(s.nsplit + 1);
