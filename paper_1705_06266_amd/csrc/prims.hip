@@ -546,6 +546,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_block_sort(uint64_t* __restric
     // radix_round's first barrier orders these reads before the writes below
 #pragma unroll
     for (int r = 0; r < kBlockSortRounds; r++) {
+      if (r * kBlock >= n) break;  // the same for every thread: only rounds that hold items
       const bool valid = r * kBlock + t < n;
       const int d = valid ? radix_digit(k[r], shift, pack) : 0;
       const int pos = radix_round(valid, d, run, wc);
