@@ -344,3 +344,41 @@ def torch_empty(n):
     import torch
 
     return torch.empty((n, 1), dtype=torch.float64, device="cuda:0")
+
+
+@pytest.mark.parametrize("name", ["rmat_s12", "chunglu_30k_hubs", "star_40000_split_hub",
+                                  "grid3d_12_loguniform"])
+def test_repeated_setups_are_bit_identical(built, name):
+    """Setups of one graph in a row, each freed before the next: later setups
+    reuse cached device memory and may place row-schedule shares in another
+    order, and none of that may change a bit of the hierarchy (every level's
+    CSR, diagonal and map, the eigenvalue estimates) or of a solve."""
+    g = CASES[name]()
+    say(f"[case] {name} repeated setups")
+    b = gg.rhs(g.n, 1, 11)[:, 0]
+    b -= b.mean()
+    ref = None
+    for rep in range(3):
+        h = gpu_setup(g)
+        stats = lg.lg_hierarchy_stats(h)
+        levels = [lg.lg_export_level(h, l) for l in range(len(stats))]
+        X, info, st = lg.lg_solve(h, to_dev(b[:, None]), rtol=1e-8, max_iter=300)
+        assert st == 0
+        cur = (levels, [s["lmax"] for s in stats], X.cpu().numpy()[:, 0], info[0]["iters"])
+        del h
+        if ref is None:
+            ref = cur
+            continue
+        assert len(cur[0]) == len(ref[0])
+        for l, (a, r) in enumerate(zip(cur[0], ref[0])):
+            for k, (u, v) in enumerate(zip(a, r)):
+                if u is None or v is None:
+                    assert u is None and v is None
+                    continue
+                u, v = np.asarray(u), np.asarray(v)
+                if u.dtype == np.float64:
+                    u, v = bits(u), bits(v)
+                assert np.array_equal(u, v), f"rep {rep} level {l} array {k}"
+        assert cur[1] == ref[1], f"rep {rep} lmax"
+        assert np.array_equal(bits(cur[2]), bits(ref[2])), f"rep {rep} solution"
+        assert cur[3] == ref[3]
