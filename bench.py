@@ -88,6 +88,36 @@ def load_traffic(family, workload):
     return rec.get("hbm_bytes_per_launch")
 
 
+def stream_roof(dev, elems=128 << 20, reps=8):
+    """On-box HBM roofs next to the published 8 TB/s: device copy (read +
+    write) and triad a = b + s c over 1 GiB fp64 arrays, best of reps, timed
+    with events.  Measured after the timed steps (outside them)."""
+    import torch
+
+    a = torch.empty(elems, dtype=torch.float64, device=dev)
+    b = torch.ones(elems, dtype=torch.float64, device=dev)
+    c = torch.ones(elems, dtype=torch.float64, device=dev)
+    nbytes = elems * 8
+    res = {}
+    for name, fn, moved in (("copy_gbs", lambda: a.copy_(b), 2 * nbytes),
+                            ("triad_gbs", lambda: torch.add(b, c, alpha=3.0, out=a), 3 * nbytes)):
+        fn()
+        best = None
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        res[name] = moved / (best * 1e-3) / 1e9
+    del a, b, c
+    torch.cuda.empty_cache()
+    res["array_gib"] = elems * 8 / 2**30
+    return res
+
+
 def cpu_baseline(g, b, seconds_target=20.0):
     """The oracle as it stands, single thread, on whole steps of the same
     workload (setup + one solve), for about `seconds_target` seconds."""
@@ -348,6 +378,8 @@ def main():
     ap.add_argument("--latency-solves", type=int, default=100)
     ap.add_argument("--family", default=None, help="kernel family timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stream-roof", action="store_true",
+                    help="skip the on-box copy / triad bandwidth measurement")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="end with a 512 MiB device copy (scale for rocprofv3 byte counters)")
     ap.add_argument("--pmc-summary", default=None,
@@ -508,6 +540,8 @@ def main():
                              "p50_ms": float(np.percentile(lat, 50)),
                              "p99_ms": float(np.percentile(lat, 99)), "solves": int(lat.size)}
     del h
+    if not args.no_stream_roof and not args.calibration_copy:  # (counter runs calibrate on a copy)
+        out["stream_roof"] = stream_roof(dev)
     if args.calibration_copy:
         src = torch.empty(64 << 20, dtype=torch.float64, device=dev)  # 512 MiB
         dst = torch.empty_like(src)
