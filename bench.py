@@ -88,6 +88,37 @@ def load_traffic(family, workload):
     return rec.get("hbm_bytes_per_launch")
 
 
+def eigs_bench(lg, rp, col, w, opts, nev, reps=3):
+    """Time of lg_eigs (nev smallest nonzero eigenpairs to tol 1e-8, block
+    inverse subspace iteration) on a hierarchy of the same graph built with room
+    for its block; setup is timed separately.  Median of reps calls."""
+    import torch
+
+    o = type(opts).from_buffer_copy(opts)
+    block = 1
+    while block < nev + 1:
+        block *= 2
+    o.max_rhs = max(o.max_rhs, block)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = lg.lg_setup(rp, col, w, o)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    ms, last = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last = lg.lg_eigs(h, nev=nev, tol=1e-8, max_iter=200)
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1e3)
+    lam, X, iters, resid, st = last
+    del h
+    return {"nev": nev, "block": block, "setup_ms": setup_ms, "eigs_ms": float(np.median(ms)),
+            "block_iterations": int(iters), "lambda": [float(v) for v in lam],
+            "max_rel_residual": float(np.max(np.asarray(resid) / np.maximum(np.abs(lam), 1e-300))),
+            "status": int(st)}
+
+
 def stream_roof(dev, elems=128 << 20, reps=8):
     """On-box HBM roofs next to the published 8 TB/s: device copy (read +
     write) and triad a = b + s c over 1 GiB fp64 arrays, best of reps, timed
@@ -378,6 +409,11 @@ def main():
     ap.add_argument("--latency-solves", type=int, default=100)
     ap.add_argument("--family", default=None, help="kernel family timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cycle", type=int, default=None, choices=(1, 2),
+                    help="1: V-cycle under CG (default), 2: K-cycle under flexible CG")
+    ap.add_argument("--eigs", type=int, default=0, metavar="NEV",
+                    help="also time lg_eigs for the NEV smallest nonzero eigenpairs (tol 1e-8) "
+                         "on a hierarchy of the workload's graph")
     ap.add_argument("--no-stream-roof", action="store_true",
                     help="skip the on-box copy / triad bandwidth measurement")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -433,6 +469,8 @@ def main():
         opts.autotune = args.autotune
     if args.merge_path is not None:
         opts.merge_path = args.merge_path
+    if args.cycle is not None:
+        opts.cycle = args.cycle
     torch.cuda.synchronize()
 
     def step():
@@ -540,6 +578,8 @@ def main():
                              "p50_ms": float(np.percentile(lat, 50)),
                              "p99_ms": float(np.percentile(lat, 99)), "solves": int(lat.size)}
     del h
+    if args.eigs:
+        out["eigs"] = eigs_bench(lg, rp, col, w, opts, args.eigs)
     if not args.no_stream_roof and not args.calibration_copy:  # (counter runs calibrate on a copy)
         out["stream_roof"] = stream_roof(dev)
     if args.calibration_copy:
