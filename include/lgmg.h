@@ -192,7 +192,10 @@ size_t lg_hierarchy_bytes(const lg_hierarchy* h);
 /* Milliseconds the last lg_setup on h took (host wall clock). */
 double lg_setup_ms(const lg_hierarchy* h);
 
-/* Release every device allocation of h.  NULL is ignored. */
+/* Release h.  Waits for the work queued on the device (as hipFree would),
+ * then keeps its device blocks, up to 4 GiB per process, in a per-device
+ * cache that later lg_setup calls draw from before allocating; blocks beyond
+ * that are freed.  NULL is ignored. */
 void lg_free(lg_hierarchy* h);
 
 /* Kernel timing with HIP events for one kernel family (name as listed by
