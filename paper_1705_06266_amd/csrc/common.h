@@ -43,9 +43,6 @@ constexpr int kBlock = 256;
 #ifndef LG_PER_LANE
 #define LG_PER_LANE 4
 #endif
-#ifndef LG_XSUM_UNROLL
-#define LG_XSUM_UNROLL 1
-#endif
 #ifndef LG_LAP_UNROLL
 #define LG_LAP_UNROLL 4
 #endif
@@ -100,36 +97,37 @@ constexpr int kLanczosStream = 64;
 // ------------------------------------------------ exact (order-free) sums
 // A sum that feeds a decision is formed on the fixed-point grid 2^-64: each
 // fp64 term is rounded to the nearest multiple of 2^-64 (ties to even), the
-// 128-bit integers are added (wrapping; associative, hence order free) and the
-// total is rounded once to the nearest fp64 (ties to even).
+// 128-bit two's-complement integers are added (wrapping; associative, hence
+// order free) and the total is rounded once to the nearest fp64 (ties to even).
 //
-// The conversion is branch-free (both shift directions are formed and one is
-// selected), so the lanes of a wave never diverge on the magnitudes of their
-// terms.
-__device__ __forceinline__ u128 xs_term(double v, int& bad) {
-  const uint64_t bits = (uint64_t)__double_as_longlong(v);
-  const uint64_t mag = bits & 0x7fffffffffffffffULL;
-  const int ex = (int)(mag >> 52);
-  const uint64_t frac = mag & 0x000fffffffffffffULL;
-  const uint64_t m = ex ? (frac | 0x0010000000000000ULL) : frac;
-  // |v| * 2^64 = m * 2^sh
-  const int sh = (ex ? ex : 1) - 1011;
-  const bool inval = (ex == 0x7ff) | (sh > 73);  // not finite, or |v| * 2^64 >= 2^126
-  bad |= inval;
-  // sh >= 0: exact left shift of the 53-bit significand
-  const int ls = sh < 0 ? 0 : (sh > 73 ? 73 : sh);
-  const uint64_t lo_l = ls >= 64 ? 0 : (m << (ls & 63));
-  const uint64_t hi_l = ls >= 64 ? (m << ((ls - 64) & 63)) : (ls == 0 ? 0 : (m >> ((64 - ls) & 63)));
-  // sh < 0: right shift, rounded to nearest, ties to even (shifts past 54 give 0)
-  const int rs = sh >= 0 ? 1 : (sh < -63 ? 63 : -sh);
-  const uint64_t q = m >> rs;
-  const uint64_t rem = m & ((1ULL << rs) - 1);
-  const uint64_t half = 1ULL << (rs - 1);
-  const uint64_t qr = q + (uint64_t)((rem > half) | ((rem == half) & (q & 1)));
-  const uint64_t lo = inval ? 0 : (sh >= 0 ? lo_l : qr);
-  const uint64_t hi = inval ? 0 : (sh >= 0 ? hi_l : 0);
-  const u128 r = ((u128)hi << 64) | lo;
-  return (bits >> 63) ? (u128)0 - r : r;
+// A term is added as four 32-bit limbs of its 128-bit integer into four 64-bit
+// accumulators, with fp64 arithmetic only and no branches: |v| 2^64 is exact,
+// rint rounds it to the grid, and floor and the subtractions that peel the
+// limbs off are exact.  A negative term adds the complemented limbs plus one
+// (its two's complement mod 2^128), with no carries between limbs until
+// xs_limbs_total.  The low two accumulators stay below 2^64 for fewer than
+// 2^32 terms, the bound for exactness mod 2^128.  Terms that are not finite or
+// have |v| 2^64 >= 2^126 add nothing and set `bad`.
+__device__ __forceinline__ void xs_limbs_add(double v, uint64_t (&acc)[4], int& bad) {
+  const double a = fabs(v) * 0x1p64;
+  const bool ok = a < 0x1p126;  // false for NaN and infinities
+  bad |= !ok;
+  const double y = ok ? rint(a) : 0.0;
+  const double t3 = floor(y * 0x1p-96);
+  const double y3 = y - t3 * 0x1p96;
+  const double t2 = floor(y3 * 0x1p-64);
+  const double y2 = y3 - t2 * 0x1p64;
+  const double t1 = floor(y2 * 0x1p-32);
+  const double t0 = y2 - t1 * 0x1p32;
+  const uint32_t neg = (ok && signbit(v)) ? 0xffffffffu : 0u;
+  acc[0] += (uint64_t)(((uint32_t)t0) ^ neg) + (neg & 1u);
+  acc[1] += (uint64_t)(((uint32_t)t1) ^ neg);
+  acc[2] += (uint64_t)(((uint32_t)t2) ^ neg);
+  acc[3] += (uint64_t)(((uint32_t)t3) ^ neg);
+}
+
+__device__ __forceinline__ u128 xs_limbs_total(const uint64_t (&acc)[4]) {
+  return (u128)acc[0] + ((u128)acc[1] << 32) + ((u128)acc[2] << 64) + ((u128)acc[3] << 96);
 }
 
 __device__ __forceinline__ double xs_value(u128 s) {

@@ -2,7 +2,7 @@
 //
 // Decisions (which vertices are eliminated, which aggregates form) must not
 // depend on thread scheduling.  All sums that feed them or a stored level are
-// exact and order free (xs_term/xs_value in common.h); products, quotients
+// exact and order free (xs_limbs_add/xs_value in common.h); products, quotients
 // and the per-edge affinity use a fixed operand order, and the argmin/argmax
 // reductions use total orders.  Integer atomics only count.
 #include <algorithm>
@@ -175,29 +175,34 @@ __global__ __launch_bounds__(1024) void k_coarse_connected(const int32_t* __rest
 }
 
 // ------------------------------------------------------ exact row sums
-struct XAcc {
-  u128 s;
+// one sum in limb form (xs_limbs_add)
+struct XLAcc {
+  uint64_t l[4];
   int bad;
   int pad[3];
 };
+#define XSUM_ACC_OPS                                                         \
+  __device__ Acc identity() const { return {{0, 0, 0, 0}, 0, {0, 0, 0}}; } \
+  __device__ static void add(Acc& a, double v) { xs_limbs_add(v, a.l, a.bad); } \
+  __device__ void combine(Acc& a, const Acc& o) const {                     \
+    for (int q = 0; q < 4; q++) a.l[q] += o.l[q];                           \
+    a.bad |= o.bad;                                                         \
+  }                                                                         \
+  __device__ static double total(const Acc& a) { return xs_value(xs_limbs_total(a.l)); }
 
 // out[row] = exact sum of val over the row; outinv[row] = 1 / out[row].
 struct RowXsumOp {
-  using Acc = XAcc;
+  using Acc = XLAcc;
   const double* __restrict__ val;
   double* __restrict__ out;
   double* __restrict__ outinv;
   int* flags;
-  __device__ Acc identity() const { return {0, 0, {0, 0, 0}}; }
+  XSUM_ACC_OPS
   __device__ bool active(int64_t) const { return true; }
-  __device__ void accum(Acc& a, int64_t, int e) const { a.s += xs_term(val[e], a.bad); }
-  __device__ void combine(Acc& a, const Acc& o) const {
-    a.s += o.s;
-    a.bad |= o.bad;
-  }
+  __device__ void accum(Acc& a, int64_t, int e) const { add(a, val[e]); }
   __device__ void finish(int64_t row, const Acc& a, int lane, int) const {
     if (lane) return;
-    const double v = xs_value(a.s);
+    const double v = total(a);
     out[row] = v;
     if (outinv) outinv[row] = v > 0.0 ? 1.0 / v : 0.0;
     if (a.bad) atomicOr(flags, F_XSUM);
@@ -206,23 +211,19 @@ struct RowXsumOp {
 
 // Runs of equal (row, col) keys after sorting: one exact sum per run.
 struct RunXsumOp {
-  using Acc = XAcc;
+  using Acc = XLAcc;
   const double* __restrict__ val;
   const uint64_t* __restrict__ keys;
   const int32_t* __restrict__ start;
   int32_t* __restrict__ ocol;
   double* __restrict__ ow;
   int* flags;
-  __device__ Acc identity() const { return {0, 0, {0, 0, 0}}; }
+  XSUM_ACC_OPS
   __device__ bool active(int64_t) const { return true; }
-  __device__ void accum(Acc& a, int64_t, int e) const { a.s += xs_term(val[e], a.bad); }
-  __device__ void combine(Acc& a, const Acc& o) const {
-    a.s += o.s;
-    a.bad |= o.bad;
-  }
+  __device__ void accum(Acc& a, int64_t, int e) const { add(a, val[e]); }
   __device__ void finish(int64_t run, const Acc& a, int lane, int) const {
     if (lane) return;
-    ow[run] = xs_value(a.s);
+    ow[run] = total(a);
     ocol[run] = (int32_t)(keys[start[run]] & 0xffffffffULL);
     if (a.bad) atomicOr(flags, F_XSUM);
   }
@@ -412,8 +413,9 @@ __global__ void k_tv_init(double* __restrict__ X, int64_t n, uint64_t key, int l
   for (int k = 0; k < 4; k++) X[i * 4 + k] = counter_uniform(key, level, k, i);
 }
 
-struct X4Acc {
-  u128 s[4];
+// four sums in limb form (xs_limbs_add)
+struct X4LAcc {
+  uint64_t l[4][4];
   int bad;
   int pad[3];
 };
@@ -421,8 +423,9 @@ struct X4Acc {
 // One weighted-Jacobi sweep on L y = 0 for the four test vectors:
 // Y_i = (1 - omega) X_i + omega * (exact sum_j w_ij X_j) / d_i.
 struct JacobiOp {
-  using Acc = X4Acc;
-  static constexpr int kUnroll = LG_XSUM_UNROLL;
+  using Acc = X4LAcc;
+  // one entry per lane step: the 16 limb accumulators already hold 132 VGPRs
+  static constexpr int kUnroll = 1;
   const int32_t* __restrict__ col;
   const double* __restrict__ w;
   const double* __restrict__ d;
@@ -433,27 +436,32 @@ struct JacobiOp {
   __device__ Acc identity() const {
     Acc a;
 #pragma unroll
-    for (int k = 0; k < 4; k++) a.s[k] = 0;
+    for (int k = 0; k < 4; k++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) a.l[k][q] = 0;
     a.bad = 0;
     return a;
   }
-  __device__ bool active(int64_t) const { return true; }
   __device__ void accum(Acc& a, int64_t, int e) const {
     const double we = w[e];
     const double* xj = X + (int64_t)col[e] * 4;
 #pragma unroll
-    for (int k = 0; k < 4; k++) a.s[k] += xs_term(we * xj[k], a.bad);
+    for (int k = 0; k < 4; k++) xs_limbs_add(we * xj[k], a.l[k], a.bad);
   }
   __device__ void combine(Acc& a, const Acc& o) const {
 #pragma unroll
-    for (int k = 0; k < 4; k++) a.s[k] += o.s[k];
+    for (int k = 0; k < 4; k++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) a.l[k][q] += o.l[k][q];
     a.bad |= o.bad;
   }
+  __device__ static u128 total(const Acc& a, int k) { return xs_limbs_total(a.l[k]); }
+  __device__ bool active(int64_t) const { return true; }
   __device__ void finish(int64_t row, const Acc& a, int lane, int G) const {
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       if (k % G != lane) continue;
-      const double t = xs_value(a.s[k]) / d[row];
+      const double t = xs_value(total(a, k)) / d[row];
       Y[row * 4 + k] = keep * X[row * 4 + k] + omega * t;
     }
     if (lane == 0 && a.bad) atomicOr(flags, F_XSUM);
@@ -960,6 +968,7 @@ void check_isolated(const Level& L) {
 void level_diag(Ctx& c, Level& L) {
   L.d = c.h->mem.get<double>(L.n);
   L.dinv = c.h->mem.get<double>(L.n);
+  ProfScope ps("row_xsum", c.st, 4.0 * (L.n + 1) + 8.0 * L.nnz + 16.0 * L.n);
   run_rows(L.sched, L.rp, RowXsumOp{L.w, L.d, L.dinv, c.flags}, c.st);
 }
 
