@@ -237,8 +237,10 @@ namespace lg {
 // ------------------------------------------------------------------- scan
 // Reduce-then-scan over tiles of kScanTile items; each thread owns kScanIPT
 // consecutive items, moved with 16-byte vector loads and stores when the
-// buffers are 16-byte aligned.  Pass 1 writes tile sums, the sums are scanned
-// (recursively), pass 2 writes out[i] = tile offset + in-tile prefix.
+// buffers are 16-byte aligned.  Pass 1 writes tile sums; pass 2 writes
+// out[i] = tile offset + in-tile prefix, each workgroup summing the tile sums
+// before its own (up to kScanFuse tiles; beyond that the sums are scanned
+// recursively first).
 constexpr int kScanIPT = 8;
 constexpr int kScanTile = kBlock * kScanIPT;
 
@@ -292,13 +294,27 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const TI* __restrict__ i
   if (threadIdx.x == 0) sums[blockIdx.x] = s;
 }
 
-// offs == nullptr: a single tile.  The last tile also writes out[n], the total.
+// A tile's offset: offs[tile] if offs is set, else the sum of sums[0, tile)
+// formed by the workgroup itself if sums is set (at most kScanFuse tiles),
+// else 0 (a single tile).  The last tile also writes out[n], the total.
+constexpr int kScanFuse = 4 * kBlock;
+
 template <typename TI>
 __global__ __launch_bounds__(kBlock) void k_scan_tiles(const TI* __restrict__ in,
                                                        int64_t* __restrict__ out, int64_t n,
-                                                       bool vec, const int64_t* __restrict__ offs) {
+                                                       bool vec, const int64_t* __restrict__ offs,
+                                                       const int64_t* __restrict__ sums) {
   __shared__ int64_t wsum[kBlock / 64];
+  __shared__ int64_t wbase[kBlock / 64];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int64_t base = 0;
+  if (offs) {
+    base = offs[blockIdx.x];
+  } else if (sums) {
+    int64_t p = 0;
+    for (int k = t; k < (int)blockIdx.x; k += kBlock) p += sums[k];
+    base = block_sum_i64(p, wbase);
+  }
   const int64_t i0 = (int64_t)blockIdx.x * kScanTile + (int64_t)t * kScanIPT;
   int64_t v[kScanIPT];
   scan_load8(in, i0, n, vec, v);
@@ -313,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const TI* __restrict__ in
   }
   if (lane == 63) wsum[w] = x;
   __syncthreads();
-  int64_t run = offs ? offs[blockIdx.x] : 0;
+  int64_t run = base;
   for (int k = 0; k < w; k++) run += wsum[k];
   run += x - s;
   int64_t r[kScanIPT];
@@ -345,17 +361,22 @@ static void scan_core(const TI* in, int64_t* out, int64_t n, Arena& tmp, hipStre
   const int64_t nb = ceil_div(n, kScanTile);
   const bool vec = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
   const int64_t* offs = nullptr;
+  int64_t* sums = nullptr;
   if (nb > 1) {
-    int64_t* sums = tmp.get<int64_t>(nb);
-    int64_t* o = tmp.get<int64_t>(nb + 1);
+    sums = tmp.get<int64_t>(nb);
     hipLaunchKernelGGL((k_scan_reduce<TI>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, vec,
                        sums);
     LG_LAUNCH_CHECK();
-    scan_core<int64_t>(sums, o, nb, tmp, st);
-    offs = o;
+    if (nb > kScanFuse) {
+      // too many tiles for each workgroup to sum its predecessors: scan the sums
+      int64_t* o = tmp.get<int64_t>(nb + 1);
+      scan_core<int64_t>(sums, o, nb, tmp, st);
+      offs = o;
+      sums = nullptr;
+    }
   }
   hipLaunchKernelGGL((k_scan_tiles<TI>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, out, n, vec,
-                     offs);
+                     offs, sums);
   LG_LAUNCH_CHECK();
 }
 
@@ -901,9 +922,13 @@ int* sched_stats(const int32_t* rp, int64_t n, const int64_t* n_dev, Arena& tmp,
       (int)std::min<int64_t>(kStatRows, std::max<int64_t>(1, ceil_div(n, (int64_t)kBlock * 1024)));
   const int64_t nbs = std::max<int64_t>(1, ceil_div(n, (int64_t)kBlock * rows));
   int* part = tmp.get<int>(kStat * nbs);
-  int* tot = tmp.get<int>(kStat);
   hipLaunchKernelGGL(k_sched_stats, dim3((unsigned)nbs), dim3(kBlock), 0, st, rp, n, n_dev, rows,
                      (int)LG_HUB_DEG, part);
+  if (nbs == 1) {  // one workgroup's statistics are the totals
+    LG_LAUNCH_CHECK();
+    return part;
+  }
+  int* tot = tmp.get<int>(kStat);
   hipLaunchKernelGGL(k_sched_final, dim3(1), dim3(kStat * 64), 0, st, (const int*)part, nbs, tot);
   LG_LAUNCH_CHECK();
   return tot;
