@@ -204,7 +204,11 @@ void lg_free(lg_hierarchy* h);
  * alone: "spmv" the fp64 L x of setup's Lanczos steps and of the CG iteration,
  * "spmm" lg_spmv's own launches, "cheb0" the zero-start smoother step, "cheb1"
  * the first step from a nonzero iterate, "cheb" the later steps, "resid" the
- * cycle's residual, "resid64" the CG's true residual.  lg_profile_read returns
+ * cycle's residual, "resid64" the CG's true residual, "spmm_inner" the
+ * K-cycle's coarse-level FCG products; "restrict", "prolong" and "coarse" time those
+ * cycle steps.  The setup families ("jacobi_xsum", "row_xsum", "affinity",
+ * "vote", "elim_select", "galerkin_reduce") time the span of each call of
+ * that setup step, "radix" each radix sort.  lg_profile_read returns
  * the launch count, the summed event time and the summed algorithmic bytes of
  * those launches, then resets the counters.  Disabled by default (NULL). */
 lg_status lg_profile_enable(const char* family);
