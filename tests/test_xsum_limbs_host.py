@@ -5,7 +5,8 @@ Every sum that feeds a decision or a stored level value is formed on the
 fixed-point grid 2^-64 (each fp64 term rounded to the nearest multiple of
 2^-64, ties to even; 128-bit integer adds that wrap).  The GPU kernels add a
 term as four 32-bit limbs computed with fp64 rint/floor (xs_limbs_add in
-csrc/common.h).  Here those two helpers are compiled for the host (HIP,
+csrc/common.h) and rounds the 128-bit total once (xs_value).  Here those
+helpers are compiled for the host (HIP,
 host-only, with the header's device functions declared host+device) and
 checked term by term and sum by sum against the oracle's definition
 (nearest integer to v * 2^64, summed as Python integers mod 2^128), on the
@@ -30,8 +31,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HARNESS = r"""
 #include <hip/hip_runtime.h>
 #include <cmath>
-// host twin of the device signbit, for a host build of the limb helpers
+// host twins of device-only functions, for a host build of the helpers
 __attribute__((host)) inline int signbit(double x) { return std::signbit(x); }
+__attribute__((host)) inline int __clzll(long long x) {
+  return x ? __builtin_clzll((unsigned long long)x) : 64;
+}
 #undef __device__
 #define __device__ __attribute__((host)) __attribute__((device))
 #include "common.h"
@@ -45,6 +49,10 @@ extern "C" int limb_sum(const double* v, long n, unsigned long long* hi,
   *hi = (unsigned long long)(t >> 64);
   *lo = (unsigned long long)t;
   return bad;
+}
+
+extern "C" double total_value(unsigned long long hi, unsigned long long lo) {
+  return lg::xs_value(((u128)hi << 64) | (u128)lo);
 }
 """
 
@@ -67,6 +75,9 @@ def limbs(tmp_path_factory):
     lib.limb_sum.argtypes = [C.POINTER(C.c_double), C.c_long, C.POINTER(C.c_ulonglong),
                              C.POINTER(C.c_ulonglong)]
 
+    lib.total_value.restype = C.c_double
+    lib.total_value.argtypes = [C.c_ulonglong, C.c_ulonglong]
+
     def run(values):
         a = np.ascontiguousarray(values, dtype=np.float64)
         hi, lo = C.c_ulonglong(), C.c_ulonglong()
@@ -74,6 +85,11 @@ def limbs(tmp_path_factory):
                            C.byref(lo))
         return bad, (hi.value << 64) | lo.value
 
+    def value(total):
+        total &= M128
+        return lib.total_value(total >> 64, total & ((1 << 64) - 1))
+
+    run.value = value
     return run
 
 
@@ -144,3 +160,22 @@ def test_sums_wrap_like_128_bit_integers(limbs):
     assert limbs(v) == oracle_sum(v) == (0, 0)
     v = [big, big, big, big]
     assert limbs(v) == oracle_sum(v)
+
+
+def test_total_rounding_matches_the_oracle(limbs):
+    """xs_value: nearest fp64 to total * 2^-64, ties to even, both signs."""
+    cases = [0, 1, 2, 3, (1 << 53) - 1, 1 << 53, (1 << 53) + 1, (1 << 54) + 2, (1 << 54) + 6,
+             (1 << 127) - 1, 1 << 126, (1 << 64) + 1]
+    rng = np.random.default_rng(13)
+    for bits in range(1, 127):
+        top = 1 << (bits - 1)
+        for _ in range(20):
+            cases.append(top | int(rng.integers(0, 2**62)) % top if bits > 1 else top)
+        if bits > 54:
+            # exact ties between two neighbouring doubles, odd and even
+            rs = bits - 53
+            for q in (top >> rs, (top >> rs) + 1):
+                cases.append((q << rs) | (1 << (rs - 1)))
+    for s in cases:
+        for t in (s, (-s) & M128):
+            assert limbs.value(t) == oracle.xs_round(t), t
