@@ -1,5 +1,6 @@
-"""The library's exact-sum limb arithmetic, built for the host, against the
-oracle's term conversion.
+"""Helpers of the HIP library, built for the host, against the oracle: the
+exact-sum arithmetic, the counter-based random numbers and the elimination
+hash (each side implements them on its own, from their definitions).
 
 Every sum that feeds a decision or a stored level value is formed on the
 fixed-point grid 2^-64 (each fp64 term rounded to the nearest multiple of
@@ -54,17 +55,23 @@ extern "C" int limb_sum(const double* v, long n, unsigned long long* hi,
 extern "C" double total_value(unsigned long long hi, unsigned long long lo) {
   return lg::xs_value(((u128)hi << 64) | (u128)lo);
 }
+
+extern "C" double test_vector(unsigned long long seed, int level, int k, long long i) {
+  return lg::counter_uniform(lg::seed_key(seed), level, k, i);
+}
+
+extern "C" unsigned long long elim_hash(long long i, int mode) { return lg::vertex_hash(i, mode); }
 """
 
 M128 = (1 << 128) - 1
 
 
 @pytest.fixture(scope="module")
-def limbs(tmp_path_factory):
+def hostlib(tmp_path_factory):
     if not os.access(HIPCC, os.X_OK):
         pytest.skip("hipcc not available")
-    d = tmp_path_factory.mktemp("limbs")
-    src, so = d / "limbs.hip", d / "limbs.so"
+    d = tmp_path_factory.mktemp("hostlib")
+    src, so = d / "hostlib.hip", d / "hostlib.so"
     src.write_text(HARNESS)
     cmd = [HIPCC, "-x", "hip", "--offload-host-only", "-std=c++17", "-O2", "-ffp-contract=off",
            "-fPIC", "-shared", "-I", os.path.join(ROOT, "include"), "-I", CSRC, str(src),
@@ -77,6 +84,10 @@ def limbs(tmp_path_factory):
 
     lib.total_value.restype = C.c_double
     lib.total_value.argtypes = [C.c_ulonglong, C.c_ulonglong]
+    lib.test_vector.restype = C.c_double
+    lib.test_vector.argtypes = [C.c_ulonglong, C.c_int, C.c_int, C.c_longlong]
+    lib.elim_hash.restype = C.c_ulonglong
+    lib.elim_hash.argtypes = [C.c_longlong, C.c_int]
 
     def run(values):
         a = np.ascontiguousarray(values, dtype=np.float64)
@@ -90,6 +101,7 @@ def limbs(tmp_path_factory):
         return lib.total_value(total >> 64, total & ((1 << 64) - 1))
 
     run.value = value
+    run.lib = lib
     return run
 
 
@@ -123,46 +135,46 @@ def edge_values():
     return vals
 
 
-def test_single_terms_match_the_oracle(limbs):
+def test_single_terms_match_the_oracle(hostlib):
     for v in edge_values():
-        bad, s = limbs([v])
+        bad, s = hostlib([v])
         ob, os_ = oracle_sum([v])
         assert bad == 0 and ob == 0, v
         assert s == os_, v
 
 
-def test_random_terms_match_the_oracle(limbs):
+def test_random_terms_match_the_oracle(hostlib):
     rng = np.random.default_rng(11)
     e = rng.integers(-100, 62, size=20000)
     m = rng.random(20000) + 1.0
     v = np.ldexp(m, e) * np.where(rng.random(20000) < 0.5, -1.0, 1.0)
     for x in v:
-        assert limbs([x]) == oracle_sum([x]), x
+        assert hostlib([x]) == oracle_sum([x]), x
 
 
-def test_out_of_range_terms_add_nothing_and_flag(limbs):
+def test_out_of_range_terms_add_nothing_and_flag(hostlib):
     for bad_v in (math.ldexp(1, 62), -math.ldexp(1, 62), 1e300, math.inf, -math.inf, math.nan):
         assert oracle_sum([bad_v])[0] == 1
-        assert limbs([bad_v]) == (1, 0), bad_v
-        assert limbs([1.0, bad_v, -0.25]) == oracle_sum([1.0, bad_v, -0.25])
+        assert hostlib([bad_v]) == (1, 0), bad_v
+        assert hostlib([1.0, bad_v, -0.25]) == oracle_sum([1.0, bad_v, -0.25])
 
 
-def test_sums_wrap_like_128_bit_integers(limbs):
+def test_sums_wrap_like_128_bit_integers(hostlib):
     rng = np.random.default_rng(12)
     for n in (1, 2, 7, 64, 1000, 5000):
         for _ in range(5):
             e = rng.integers(-90, 60, size=n)
             v = np.ldexp(rng.random(n) + 1.0, e) * np.where(rng.random(n) < 0.5, -1.0, 1.0)
-            assert limbs(v) == oracle_sum(v)
+            assert hostlib(v) == oracle_sum(v)
     # cancellation to zero and a total that wraps past 2^127
     big = math.nextafter(math.ldexp(1, 62), 0.0)
     v = [big, big, -big, 3.0, -big, -3.0]
-    assert limbs(v) == oracle_sum(v) == (0, 0)
+    assert hostlib(v) == oracle_sum(v) == (0, 0)
     v = [big, big, big, big]
-    assert limbs(v) == oracle_sum(v)
+    assert hostlib(v) == oracle_sum(v)
 
 
-def test_total_rounding_matches_the_oracle(limbs):
+def test_total_rounding_matches_the_oracle(hostlib):
     """xs_value: nearest fp64 to total * 2^-64, ties to even, both signs."""
     cases = [0, 1, 2, 3, (1 << 53) - 1, 1 << 53, (1 << 53) + 1, (1 << 54) + 2, (1 << 54) + 6,
              (1 << 127) - 1, 1 << 126, (1 << 64) + 1]
@@ -178,4 +190,23 @@ def test_total_rounding_matches_the_oracle(limbs):
                 cases.append((q << rs) | (1 << (rs - 1)))
     for s in cases:
         for t in (s, (-s) & M128):
-            assert limbs.value(t) == oracle.xs_round(t), t
+            assert hostlib.value(t) == oracle.xs_round(t), t
+
+
+def test_random_numbers_and_hash_match_the_oracle(hostlib):
+    """Test-vector entries (every level, vector and Lanczos stream used) and
+    elimination hashes agree bit for bit with the oracle's."""
+    lib = hostlib.lib
+    rng = np.random.default_rng(14)
+    seeds = [0, 1, 7, 2**63 + 5, 2**64 - 1]
+    ids = [0, 1, 2, 3, 255, 256, 2**20 - 1, 2**31 - 2] + [int(x) for x in rng.integers(0, 2**31 - 1, 50)]
+    for seed in seeds:
+        for level in (0, 1, 5, 39):
+            for k in (0, 1, 2, 3, 64, 65):
+                for i in ids:
+                    a = lib.test_vector(seed, level, k, i)
+                    assert a == oracle.tv(seed, level, k, i), (seed, level, k, i)
+                    assert -1.0 <= a < 1.0
+    for i in ids:
+        for mode in (0, 1):
+            assert lib.elim_hash(i, mode) == oracle.vertex_hash(i, mode), (i, mode)
