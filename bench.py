@@ -38,22 +38,22 @@ KERNEL_SOURCES = ["paper_1705_06266_amd/csrc/common.h", "paper_1705_06266_amd/cs
 # family: the kernel timed for the roofline (one kernel instance per workload);
 # kernel: its symbol as rocprofv3 prints it.
 WORKLOADS = {
-    "rmat_s18": dict(cfg="c2_rmat_s18", precision="fp64", k=1,
+    "rmat_s18": dict(cfg="rmat_s18", precision="fp64", k=1,
                      label="rmat_s18_ef16_lcc_u01_fp64_1rhs", family="spmv",
                      kernel="k_rows<lg::LapOp<double, 1, 0, 0> >"),
-    "grid2d_64": dict(cfg="c1_grid2d_64", precision="fp64", k=1,
+    "grid2d_64": dict(cfg="grid2d_64", precision="fp64", k=1,
                       label="grid2d_64x64_unit_fp64_1rhs", family="spmv",
                       kernel="k_rows<lg::LapOp<double, 1, 0, 0> >"),
-    "grid3d_128_mixed": dict(cfg="c3_grid3d_128", precision="mixed", k=32,
+    "grid3d_128_mixed": dict(cfg="grid3d_128_loguniform", precision="mixed", k=32,
                              label="grid3d_128cube_loguniform_mixed_32rhs", family="cheb",
                              kernel="k_rows_col<lg::LapColOp<float, 32, 2, 0> >"),
-    "grid3d_128_fp64": dict(cfg="c3_grid3d_128", precision="fp64", k=32,
+    "grid3d_128_fp64": dict(cfg="grid3d_128_loguniform", precision="fp64", k=32,
                             label="grid3d_128cube_loguniform_fp64_32rhs", family="cheb",
                             kernel="k_rows_col<lg::LapColOp<double, 32, 2, 0> >"),
-    "chunglu_4m_mixed": dict(cfg="c4_chunglu_4m", precision="mixed", k=16,
+    "chunglu_4m_mixed": dict(cfg="chunglu_4m", precision="mixed", k=16,
                              label="chunglu_4m_g2.1_d16_mixed_16rhs", family="cheb",
                              kernel="k_rows_col<lg::LapColOp<float, 16, 2, 0> >"),
-    "chunglu_4m_fp64": dict(cfg="c4_chunglu_4m", precision="fp64", k=16,
+    "chunglu_4m_fp64": dict(cfg="chunglu_4m", precision="fp64", k=16,
                             label="chunglu_4m_g2.1_d16_fp64_16rhs", family="cheb",
                             kernel="k_rows_col<lg::LapColOp<double, 16, 2, 0> >"),
 }

@@ -283,15 +283,17 @@ def rhs(n, k=1, seed=1):
     return _rng(seed).standard_normal((n, k))
 
 
-# The five evaluation workloads (graph recipe, RHS count, precision).
+# The evaluation workloads (graph recipe, RHS count, precision); the serving
+# pool is built by serving_pool below.
 CONFIGS = {
-    "c1_grid2d_64": dict(graph=("grid2d", dict(nx=64, ny=64)), k=1, rhs_seed=1, precision="fp64"),
-    "c2_rmat_s18": dict(graph=("rmat", dict(scale=18, edge_factor=16, seed=2)), k=1, rhs_seed=3,
-                        precision="fp64"),
-    "c3_grid3d_128": dict(graph=("grid3d", dict(nx=128, ny=128, nz=128, weights="loguniform", seed=4)),
-                          k=32, rhs_seed=5, precision="mixed"),
-    "c4_chunglu_4m": dict(graph=("chung_lu", dict(n=4 << 20, gamma=2.1, mean_deg=16.0, max_deg=1e5,
-                                                   seed=6)), k=16, rhs_seed=6, precision="mixed"),
+    "grid2d_64": dict(graph=("grid2d", dict(nx=64, ny=64)), k=1, rhs_seed=1, precision="fp64"),
+    "rmat_s18": dict(graph=("rmat", dict(scale=18, edge_factor=16, seed=2)), k=1, rhs_seed=3,
+                     precision="fp64"),
+    "grid3d_128_loguniform": dict(
+        graph=("grid3d", dict(nx=128, ny=128, nz=128, weights="loguniform", seed=4)),
+        k=32, rhs_seed=5, precision="mixed"),
+    "chunglu_4m": dict(graph=("chung_lu", dict(n=4 << 20, gamma=2.1, mean_deg=16.0, max_deg=1e5,
+                                                seed=6)), k=16, rhs_seed=6, precision="mixed"),
 }
 
 
