@@ -1,0 +1,48 @@
+"""Host-side behaviour of bench.py: the one-GPU guard and the HBM traffic
+figures it takes from committed counter summaries (keyed by a hash of the
+kernel sources, so a changed kernel reports no stale traffic)."""
+
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    for extra, env in ((["--gpus", "2"], {}), ([], {"WORLD_SIZE": "4"})):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + extra,
+                           capture_output=True, text=True, timeout=120,
+                           env=dict(os.environ, **env))
+        assert r.returncode == 2
+        assert "one GPU only" in r.stderr
+
+
+def _write_summary(dirpath, family, workload, source_hash, nbytes):
+    rec = {"workload": workload, "family": family, "kernel_source_hash": source_hash,
+           "hbm_bytes_per_launch": nbytes}
+    path = os.path.join(dirpath, f"{family}_{workload}_pmc.txt")
+    with open(path, "w") as f:
+        f.write("# summary\n\njson: " + json.dumps(rec) + "\n")
+
+
+def test_traffic_is_taken_only_from_summaries_of_the_current_kernels(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    current = bench.kernel_source_hash()
+    assert len(current) == 16
+    assert bench.load_traffic("spmv", "rmat_s18") is None  # no summary
+    _write_summary(tmp_path, "spmv", "rmat_s18", current, 1.25e8)
+    assert bench.load_traffic("spmv", "rmat_s18") == 1.25e8
+    _write_summary(tmp_path, "spmv", "rmat_s18", "0" * 16, 1.25e8)
+    assert bench.load_traffic("spmv", "rmat_s18") is None  # taken on other kernels
+
+
+def test_every_workload_names_a_graph_recipe():
+    import graphgen as gg
+
+    for name, wl in bench.WORKLOADS.items():
+        assert wl["cfg"] in gg.CONFIGS, name
+        assert wl["family"] in ("spmv", "cheb"), name
