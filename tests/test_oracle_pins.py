@@ -646,3 +646,26 @@ def test_eigs_dense_grid_is_a_sum_of_path_spectra():
     assert np.allclose(lam, want, rtol=0, atol=1e-12)
     assert np.allclose(V.T @ V, np.eye(6), atol=1e-12)
     assert np.allclose(V.sum(axis=0), 0.0, atol=1e-10)  # orthogonal to the constant
+
+
+@pytest.mark.parametrize("mk", [lambda: gg.grid2d(64, 64), lambda: gg.rmat(11, 16, seed=2),
+                                lambda: gg.grid3d(9, 8, 7, weights="loguniform", seed=4)])
+def test_laplacian_product_matches_scipy_on_every_level(mk):
+    """The oracle's L x (Section 2.1, L = D - A) on every level of a hierarchy,
+    against scipy's sparse product with the level's own diagonal; and L 1 = 0
+    up to the rounding of the row sums."""
+    g = mk()
+    h = oracle.Hierarchy(g)
+    rng = np.random.default_rng(21)
+    for l in range(h.num_levels):
+        gl, d = h.csr(l)
+        A = sparse_A(gl)
+        x = rng.standard_normal(gl.n)
+        y = h.spmv(l, x)
+        ref = d * x - A @ x
+        scale = d * np.abs(x) + abs(A) @ np.abs(x)
+        assert np.all(np.abs(y - ref) <= 1e-13 * scale + 1e-300), l
+        y1 = h.spmv(l, np.ones(gl.n))
+        assert np.all(np.abs(y1) <= 1e-13 * d + 1e-300), l
+        # a planted sign error (L = D + A) would fail the first check
+        assert gl.nnz == 0 or not np.allclose(d * x + A @ x, ref)
