@@ -100,6 +100,8 @@ def lib():
         "lgo_coarsest_pinv": (C.c_int, [_P, _P]),
         "lgo_cycle_work": (_D, [_P]),
         "lgo_cycle": (C.c_int, [_P, _P, _P]),
+        "lgo_level_cycle": (C.c_int, [_P, _I32, _P, _P]),
+        "lgo_level_fcg2": (C.c_int, [_P, _I32, _P, _P]),
         "lgo_spmv": (C.c_int, [_P, _I32, _P, _P]),
         "lgo_solve": (C.c_int, [_P, _P, _P, _D, _I32, _P, _P, _P]),
     }
@@ -400,6 +402,25 @@ class Hierarchy:
         b = np.ascontiguousarray(b, dtype=np.float64)
         x = np.empty(self.n)
         lib().lgo_cycle(self._h, _ptr(b), _ptr(x))
+        return x
+
+    def level_cycle(self, l, b):
+        """Algorithm 1 started on level l with zero initial guess (test hook)."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.empty_like(b)
+        st = lib().lgo_level_cycle(self._h, l, _ptr(b), _ptr(x))
+        if st:
+            raise OracleError(st, "level_cycle")
+        return x
+
+    def level_fcg2(self, l, b):
+        """The K-cycle's inner solve on level l: two flexible-CG steps
+        preconditioned by the cycle from level l (test hook)."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.empty_like(b)
+        st = lib().lgo_level_fcg2(self._h, l, _ptr(b), _ptr(x))
+        if st:
+            raise OracleError(st, "level_fcg2")
         return x
 
     def spmv(self, l, x):

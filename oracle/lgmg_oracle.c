@@ -1155,11 +1155,15 @@ static void precond(lgo_hier* h, int l, const double* b, double* x) {
 }
 
 double lgo_cycle_work(const lgo_hier* h) {
-  /* work of one cycle in finest-residual units, measured on a zero vector */
+  /* work of one cycle in finest-residual units (Section 2.3.1: operator
+     applications weighted by their nonzeros), counted while the cycle runs on
+     the nonzero mean-zero vector b_i = i - (n-1)/2, so that a K-cycle's inner
+     FCG takes both of its steps as it does on any residual the solver hands it */
   lgo_hier* hh = (lgo_hier*)h;
   int64_t n = h->lev[0].A.n;
-  double* b = (double*)xcalloc((size_t)n, sizeof(double));
+  double* b = (double*)xmalloc(sizeof(double) * (size_t)n);
   double* x = (double*)xmalloc(sizeof(double) * (size_t)n);
+  for (int64_t i = 0; i < n; i++) b[i] = (double)i - 0.5 * (double)(n - 1);
   double saved = hh->work;
   hh->work = 0.0;
   precond(hh, 0, b, x);
@@ -1172,6 +1176,27 @@ double lgo_cycle_work(const lgo_hier* h) {
 
 int lgo_cycle(const lgo_hier* h, const double* b, double* x) {
   precond((lgo_hier*)h, 0, b, x);
+  return LGO_OK;
+}
+
+/* Test hooks: Algorithm 1 started on level l (zero initial guess), and the
+ * K-cycle's inner solve on level l (two FCG steps preconditioned by that
+ * cycle, Section 3.7).  Both leave the work counter as it was. */
+int lgo_level_cycle(const lgo_hier* h, int32_t l, const double* b, double* x) {
+  if (l < 0 || l >= h->nlev) return LGO_E_ARG;
+  lgo_hier* hh = (lgo_hier*)h;
+  double saved = hh->work;
+  precond(hh, l, b, x);
+  hh->work = saved;
+  return LGO_OK;
+}
+
+int lgo_level_fcg2(const lgo_hier* h, int32_t l, const double* b, double* x) {
+  if (l < 0 || l >= h->nlev || h->lev[l].type == LGO_COARSEST) return LGO_E_ARG;
+  lgo_hier* hh = (lgo_hier*)h;
+  double saved = hh->work;
+  fcg2(hh, l, b, x);
+  hh->work = saved;
   return LGO_OK;
 }
 

@@ -95,6 +95,8 @@ int lgo_level_votes(const lgo_hier* h, int32_t l, int32_t* state, int32_t* idx, 
 int lgo_coarsest_pinv(const lgo_hier* h, double* out);
 double lgo_cycle_work(const lgo_hier* h);
 int lgo_cycle(const lgo_hier* h, const double* b, double* x);
+int lgo_level_cycle(const lgo_hier* h, int32_t l, const double* b, double* x);
+int lgo_level_fcg2(const lgo_hier* h, int32_t l, const double* b, double* x);
 int lgo_spmv(const lgo_hier* h, int32_t l, const double* x, double* y);
 int lgo_solve(const lgo_hier* h, const double* b, double* x, double rtol, int32_t max_iter,
               int32_t* iters, double* rel_residual, double* work_units);

@@ -669,3 +669,112 @@ def test_laplacian_product_matches_scipy_on_every_level(mk):
         assert np.all(np.abs(y1) <= 1e-13 * d + 1e-300), l
         # a planted sign error (L = D + A) would fail the first check
         assert gl.nnz == 0 or not np.allclose(d * x + A @ x, ref)
+
+
+# ---------------------------------------------- K-cycle inner solve (3.7)
+
+def _fcg_levels(h):
+    """Levels whose coarse solve is the K-cycle's inner FCG: the coarse level
+    of an aggregation level, unless it is the coarsest."""
+    lv = h.levels()
+    return [l for l in range(1, len(lv))
+            if lv[l - 1].type == oracle.AGG and lv[l].type != oracle.COARSEST]
+
+
+@pytest.mark.parametrize("cycle", [1, 2])
+@pytest.mark.parametrize("mk", [lambda: gg.grid2d(40, 40),
+                                lambda: gg.chung_lu(4000, seed=9, max_deg=300),
+                                lambda: gg.grid3d(10, 10, 10, weights="loguniform", seed=2)])
+def test_kcycle_inner_fcg_minimises_energy_over_its_two_directions(mk, cycle):
+    """Two steps of flexible CG from x = 0 with preconditioner M (the cycle
+    from that level) give the L-energy minimiser of the error over the span
+    of p1 = M b and M r1, r1 = b - a1 L p1 (the second direction differs from
+    M r1 by a multiple of p1 only).  Equivalently the residual b - L x is
+    orthogonal to both directions (Galerkin condition).  The reference here
+    is that minimiser from a dense 2x2 solve with scipy's L; a wrong sign of
+    the orthogonalisation coefficient, or a skipped orthogonalisation, moves
+    x off it."""
+    g = mk()
+    h = oracle.Hierarchy(g, oracle.default_opts(cycle=cycle))
+    targets = _fcg_levels(h)
+    assert targets, "hierarchy has no level with an inner FCG"
+    rng = np.random.default_rng(5)
+    for l in targets:
+        G, d = h.csr(l)
+        L = (sp.diags(d) - sparse_A(G)).tocsr()
+        b = rng.standard_normal(G.n)
+        b -= b.mean()
+        x = h.level_fcg2(l, b)
+        p1 = h.level_cycle(l, b)
+        q1 = L @ p1
+        r1 = b - (p1 @ b) / (p1 @ q1) * q1
+        V = np.stack([p1, h.level_cycle(l, r1)], axis=1)
+        xs = V @ np.linalg.solve(V.T @ (L @ V), V.T @ b)
+        e = x - xs
+        err = math.sqrt(max(e @ (L @ e), 0.0)) / math.sqrt(xs @ (L @ xs))
+        assert err <= 1e-9, (l, err)
+        r = b - L @ x
+        for v in V.T:
+            assert abs(v @ r) <= 1e-9 * np.linalg.norm(v) * np.linalg.norm(b), l
+
+
+# --------------------------------------------------- work count (2.3.1)
+# Work is counted in units of one finest-level residual, i.e. nnz(L_0) =
+# n_0 + nnz(A_0) multiply-adds, and every operator application adds the
+# nonzeros of that operator (Section 2.3.1).  With Chebyshev degree 2: an
+# aggregation level costs 1 L (pre-smoothing from zero: its first step needs
+# no product) + 1 L (residual) + n (R) + n (P) + 2 L (post-smoothing) plus its
+# coarse solve; an elimination level costs nnz(P) (restriction P^T) + nnz(P)
+# + |F| (prolongation and the F-point update) plus its coarse solve; the
+# coarsest level costs n_c^2 (dense L^+).  The totals below are counted by
+# hand from those rules on hierarchies whose structure is asserted first.
+
+def _structure(h):
+    return [(L.type, L.n, L.nnz, L.nc) for L in h.levels()]
+
+
+def test_cycle_work_hand_count_star():
+    # K_{1,9} without elimination, coarsest at n + nnz <= 10: the nine leaves
+    # vote for the hub, so one aggregate.  nnz(L_0) = 10 + 18 = 28.
+    # Level 0: 28 + 28 + 10 + 10 + 2 * 28 = 132; coarsest 1^2 = 1.
+    h = oracle.Hierarchy(gg.star(9), oracle.default_opts(elim_enable=0, coarsest_nnz=10))
+    assert _structure(h) == [(oracle.AGG, 10, 18, 1), (oracle.COARSEST, 1, 0, 0)]
+    assert h.cycle_work() == pytest.approx(133 / 28, rel=1e-15)
+
+
+def test_cycle_work_hand_count_elimination():
+    # Path 0-1-2-3-4 with the identity hash: only vertex 0 is a local minimum,
+    # so F = {0}, C = {1, 2, 3, 4}; nnz(P) = |C| + deg(0) = 4 + 1 = 5.
+    # Level 0: 5 (P^T) + 5 (P) + 1 (F update) = 11; coarsest path of 4 vertices:
+    # 4^2 = 16.  nnz(L_0) = 5 + 8 = 13.
+    h = oracle.Hierarchy(gg.path(5), oracle.default_opts(hash_mode=1, coarsest_nnz=10))
+    assert _structure(h) == [(oracle.ELIM, 5, 8, 4), (oracle.COARSEST, 4, 6, 0)]
+    assert h.cycle_work() == pytest.approx(27 / 13, rel=1e-15)
+
+
+def test_cycle_work_hand_count_v_and_k_cycles():
+    # Path of 7 without elimination, coarsest at n + nnz <= 6:
+    # aggregation 7 -> 3 -> coarsest 1.  nnz(L_0) = 19, nnz(L_1) = 7.
+    # V: level 1 = 7 + 7 + 3 + 3 + 14 = 34, coarsest 1, level 0 = 19 + 19 + 7
+    #    + 7 + 38 = 90 plus 35 -> 125.
+    # K: level 0's coarse solve is two FCG steps on level 1, each one cycle
+    #    from level 1 (35) and one product with L_1 (7): 84 -> 90 + 84 = 174.
+    for cycle, units in ((1, 125), (2, 174)):
+        h = oracle.Hierarchy(gg.path(7), oracle.default_opts(elim_enable=0, coarsest_nnz=6,
+                                                             cycle=cycle))
+        assert _structure(h) == [(oracle.AGG, 7, 12, 3), (oracle.AGG, 3, 4, 1),
+                                 (oracle.COARSEST, 1, 0, 0)]
+        assert h.cycle_work() == pytest.approx(units / 19, rel=1e-15), cycle
+
+
+def test_solve_work_counts_cycles_and_products():
+    # PCG (Section 2.3.2) applies the cycle once before the loop and once per
+    # further iteration, one product with L_0 per iteration, and one more for
+    # the true residual that confirms convergence: it * (cycle + 1) + 1 units
+    # when no restart happens (the solve below converges without one).
+    g = gg.path(7)
+    h = oracle.Hierarchy(g, oracle.default_opts(elim_enable=0, coarsest_nnz=6))
+    b = np.linspace(-1.0, 1.0, g.n) ** 3
+    x, st, it, rel, work = h.solve(b, 1e-10, 50)
+    assert st == 0 and it >= 2
+    assert work == pytest.approx(it * (125 / 19 + 1) + 1, rel=1e-14)
