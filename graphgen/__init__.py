@@ -91,7 +91,9 @@ def from_edges(n, u, v, w=None, name=""):
     rows = np.concatenate([a, b])
     cols = np.concatenate([b, a])
     ww = np.concatenate([w, w])
-    order = np.lexsort((cols, rows))
+    # (row, col) pairs are distinct, so ordering by the combined key is the
+    # row-major order
+    order = np.argsort(rows * np.int64(n) + cols)
     rows, cols, ww = rows[order], cols[order], ww[order]
     counts = np.bincount(rows, minlength=n)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
@@ -243,6 +245,8 @@ def _chung_lu_offset(n, alpha, mean_deg, max_deg):
     lo, hi = 1e-6, float(n)
     for _ in range(200):  # ratio decreases as i0 grows
         mid = np.sqrt(lo * hi)
+        if mid == lo or mid == hi:  # converged: later steps would not move lo or hi
+            break
         if ratio(mid) > target:
             lo = mid
         else:
@@ -250,6 +254,15 @@ def _chung_lu_offset(n, alpha, mean_deg, max_deg):
     i0 = np.sqrt(lo * hi)
     t = np.power(i + i0, -alpha)
     return t * (mean_deg / t.mean())
+
+
+def _sorted_search(cdf, r):
+    """np.searchsorted(cdf, r, side="right"), computed on sorted queries
+    (cache-friendly) and returned in the queries' order."""
+    order = np.argsort(r)
+    out = np.empty(r.shape[0], dtype=np.int64)
+    out[order] = np.searchsorted(cdf, r[order], side="right")
+    return out
 
 
 def chung_lu(n, gamma=2.1, mean_deg=16.0, max_deg=1e5, seed=6, weights="uniform01"):
@@ -265,8 +278,8 @@ def chung_lu(n, gamma=2.1, mean_deg=16.0, max_deg=1e5, seed=6, weights="uniform0
     cdf = np.cumsum(wexp)
     cdf /= cdf[-1]
     m = int(n * mean_deg / 2)
-    u = np.searchsorted(cdf, rng.random(m), side="right")
-    v = np.searchsorted(cdf, rng.random(m), side="right")
+    u = _sorted_search(cdf, rng.random(m))
+    v = _sorted_search(cdf, rng.random(m))
     u = np.minimum(u, n - 1)
     v = np.minimum(v, n - 1)
     g = from_edges(n, u, v, None, f"chunglu_{n}_g{gamma}")
