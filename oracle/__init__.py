@@ -2,8 +2,9 @@
 
 TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT PATH: only the test suite,
 ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline leg import this.
-The oracle is plain C (``lgmg_oracle.c``), fp64, single-threaded, and shares
-no code with the GPU library.
+The oracle is plain C (``lgmg_oracle.c``), fp64, and shares no code with the
+GPU library.  The tests use its single-threaded build; the benchmark's CPU
+baseline also times the OpenMP build, which computes identical bits.
 """
 
 from __future__ import annotations
@@ -16,6 +17,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblgmg_oracle.so")
+# the same source built with -fopenmp: row-parallel loops, identical results;
+# used for the benchmark's CPU timing baseline
+OMP_LIB_PATH = os.path.join(_HERE, "liblgmg_oracle_omp.so")
 SRC = os.path.join(_HERE, "lgmg_oracle.c")
 
 AGG, ELIM, COARSEST = 0, 1, 2
@@ -24,12 +28,17 @@ STATUS = {0: "ok", 1: "bad argument", 2: "invalid graph", 3: "disconnected", 4: 
 
 
 def build(verbose=False):
-    """Compile the oracle with gcc (strict IEEE: no contraction, no fast-math)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-Wall", "-Wno-unused-function", SRC, "-o", LIB_PATH, "-lm"]
-    if verbose:
-        print(" ".join(cmd))
-    subprocess.check_call(cmd)
+    """Compile the oracle with gcc (strict IEEE: no contraction, no fast-math),
+    single-threaded and with OpenMP."""
+    base = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+            "-Wall", "-Wno-unused-function"]
+    for extra, out in (([], LIB_PATH), (["-fopenmp"], OMP_LIB_PATH)):
+        cmd = base + extra + [SRC, "-o", out, "-lm"]
+        if not extra:
+            cmd.insert(len(base), "-Wno-unknown-pragmas")
+        if verbose:
+            print(" ".join(cmd))
+        subprocess.check_call(cmd)
     return LIB_PATH
 
 
@@ -56,20 +65,22 @@ class Opts(C.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 _P = C.c_void_p
 _I32, _I64, _U64, _D = C.c_int32, C.c_int64, C.c_uint64, C.c_double
 
 
-def lib():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
+def lib(threaded=False):
+    """The single-threaded oracle, or (threaded=True) the OpenMP build."""
+    if threaded in _libs:
+        return _libs[threaded]
+    path = OMP_LIB_PATH if threaded else LIB_PATH
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC):
         build()
-    L = C.CDLL(LIB_PATH)
+    L = C.CDLL(path)
     sig = {
+        "lgo_threads": (_I32, []),
         "lgo_default_opts": (None, [_P]),
         "lgo_mix64": (_U64, [_U64]),
         "lgo_hash": (_U64, [_I64, _I32]),
@@ -109,8 +120,13 @@ def lib():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
-    _lib = L
+    _libs[threaded] = L
     return L
+
+
+def threads(threaded=False):
+    """Threads the chosen build's row-parallel loops use."""
+    return int(lib(threaded).lgo_threads())
 
 
 def _ptr(a):
@@ -309,11 +325,12 @@ class Level:
 class Hierarchy:
     """Oracle hierarchy built by ``lgo_setup``; all exports are numpy copies."""
 
-    def __init__(self, g, opts=None):
+    def __init__(self, g, opts=None, threaded=False):
         self.opts = opts or default_opts()
+        self._L = lib(threaded)
         rp, col, w = _graph_arrays(g)
         h = C.c_void_p()
-        st = lib().lgo_setup(g.n, _ptr(rp), _ptr(col), _ptr(w), C.byref(self.opts), C.byref(h))
+        st = self._L.lgo_setup(g.n, _ptr(rp), _ptr(col), _ptr(w), C.byref(self.opts), C.byref(h))
         if st:
             raise OracleError(st, "setup")
         self._h = h
@@ -321,20 +338,20 @@ class Hierarchy:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h and _lib is not None:
+        if h:
             try:
-                _lib.lgo_free(h)
+                self._L.lgo_free(h)
             except Exception:
                 pass
             self._h = None
 
     @property
     def num_levels(self):
-        return int(lib().lgo_num_levels(self._h))
+        return int(self._L.lgo_num_levels(self._h))
 
     def level(self, l):
         t, n, nnz, nc, lm = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64(), C.c_double()
-        st = lib().lgo_level_info(self._h, l, C.byref(t), C.byref(n), C.byref(nnz), C.byref(nc),
+        st = self._L.lgo_level_info(self._h, l, C.byref(t), C.byref(n), C.byref(nnz), C.byref(nc),
                                   C.byref(lm))
         if st:
             raise OracleError(st, "level_info")
@@ -351,13 +368,13 @@ class Hierarchy:
         col = np.empty(max(L.nnz, 1), dtype=np.int32)
         w = np.empty(max(L.nnz, 1))
         d = np.empty(L.n)
-        lib().lgo_level_csr(self._h, l, _ptr(rp), _ptr(col), _ptr(w), _ptr(d))
+        self._L.lgo_level_csr(self._h, l, _ptr(rp), _ptr(col), _ptr(w), _ptr(d))
         return graphgen.Graph(L.n, rp, col[:L.nnz].copy(), w[:L.nnz].copy()), d
 
     def map(self, l):
         L = self.level(l)
         out = np.empty(L.n, dtype=np.int32)
-        st = lib().lgo_level_map(self._h, l, _ptr(out))
+        st = self._L.lgo_level_map(self._h, l, _ptr(out))
         if st:
             raise OracleError(st, "level_map")
         return out
@@ -365,7 +382,7 @@ class Hierarchy:
     def elim_z(self, l):
         L = self.level(l)
         out = np.empty(L.n, dtype=np.int32)
-        st = lib().lgo_level_elim(self._h, l, _ptr(out))
+        st = self._L.lgo_level_elim(self._h, l, _ptr(out))
         if st:
             raise OracleError(st, "level_elim")
         return out
@@ -374,7 +391,7 @@ class Hierarchy:
         L = self.level(l)
         X = np.empty((L.n, 4))
         S = np.empty(max(L.nnz, 1))
-        st = lib().lgo_level_soc(self._h, l, _ptr(X), _ptr(S))
+        st = self._L.lgo_level_soc(self._h, l, _ptr(X), _ptr(S))
         if st:
             raise OracleError(st, "level_soc")
         return X, S[:L.nnz].copy()
@@ -384,7 +401,7 @@ class Hierarchy:
         s = np.empty(L.n, dtype=np.int32)
         i = np.empty(L.n, dtype=np.int32)
         v = np.empty(L.n, dtype=np.int32)
-        st = lib().lgo_level_votes(self._h, l, _ptr(s), _ptr(i), _ptr(v))
+        st = self._L.lgo_level_votes(self._h, l, _ptr(s), _ptr(i), _ptr(v))
         if st:
             raise OracleError(st, "level_votes")
         return s, i, v
@@ -392,23 +409,23 @@ class Hierarchy:
     def coarsest_pinv(self):
         n = self.level(self.num_levels - 1).n
         out = np.empty((n, n))
-        lib().lgo_coarsest_pinv(self._h, _ptr(out))
+        self._L.lgo_coarsest_pinv(self._h, _ptr(out))
         return out
 
     def cycle_work(self):
-        return float(lib().lgo_cycle_work(self._h))
+        return float(self._L.lgo_cycle_work(self._h))
 
     def cycle(self, b):
         b = np.ascontiguousarray(b, dtype=np.float64)
         x = np.empty(self.n)
-        lib().lgo_cycle(self._h, _ptr(b), _ptr(x))
+        self._L.lgo_cycle(self._h, _ptr(b), _ptr(x))
         return x
 
     def level_cycle(self, l, b):
         """Algorithm 1 started on level l with zero initial guess (test hook)."""
         b = np.ascontiguousarray(b, dtype=np.float64)
         x = np.empty_like(b)
-        st = lib().lgo_level_cycle(self._h, l, _ptr(b), _ptr(x))
+        st = self._L.lgo_level_cycle(self._h, l, _ptr(b), _ptr(x))
         if st:
             raise OracleError(st, "level_cycle")
         return x
@@ -418,7 +435,7 @@ class Hierarchy:
         preconditioned by the cycle from level l (test hook)."""
         b = np.ascontiguousarray(b, dtype=np.float64)
         x = np.empty_like(b)
-        st = lib().lgo_level_fcg2(self._h, l, _ptr(b), _ptr(x))
+        st = self._L.lgo_level_fcg2(self._h, l, _ptr(b), _ptr(x))
         if st:
             raise OracleError(st, "level_fcg2")
         return x
@@ -426,7 +443,7 @@ class Hierarchy:
     def spmv(self, l, x):
         x = np.ascontiguousarray(x, dtype=np.float64)
         y = np.empty_like(x)
-        lib().lgo_spmv(self._h, l, _ptr(x), _ptr(y))
+        self._L.lgo_spmv(self._h, l, _ptr(x), _ptr(y))
         return y
 
     def solve(self, b, rtol=1e-8, max_iter=500):
@@ -434,7 +451,7 @@ class Hierarchy:
         b = np.ascontiguousarray(b, dtype=np.float64)
         x = np.empty(self.n)
         it, rel, work = C.c_int32(), C.c_double(), C.c_double()
-        st = lib().lgo_solve(self._h, _ptr(b), _ptr(x), rtol, max_iter, C.byref(it), C.byref(rel),
+        st = self._L.lgo_solve(self._h, _ptr(b), _ptr(x), rtol, max_iter, C.byref(it), C.byref(rel),
                              C.byref(work))
         return x, int(st), it.value, rel.value, work.value
 

@@ -8,9 +8,13 @@
  * It shares no code with the GPU library; both are written independently from
  * the paper and from the conventions listed below.
  *
- * Slow and obvious on purpose: single thread, fp64, loops in the order the
- * paper states the steps.  Compile with -ffp-contract=off (no fused
- * multiply-add) so every product and sum is rounded on its own.
+ * Slow and obvious on purpose: fp64, loops in the order the paper states the
+ * steps.  Compile with -ffp-contract=off (no fused multiply-add) so every
+ * product and sum is rounded on its own.  The tests use a single-threaded
+ * build.  A second build with -fopenmp (for the CPU timing baseline only) runs
+ * the loops whose iterations each write their own row in parallel; every
+ * floating-point reduction, and every loop that adds into shared entries in
+ * floating point, stays serial, so both builds compute identical bits.
  *
  * Conventions where the paper leaves the arithmetic open (each is a reading):
  *  - Exact sums ("XSUM").  Every sum that feeds a decision or a stored
@@ -30,6 +34,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef __int128 i128;
 typedef unsigned __int128 u128;
@@ -40,6 +47,15 @@ typedef unsigned __int128 u128;
 #define ST_UNDECIDED 1
 #define ST_SEED 2
 #define TV_LANCZOS_STREAM 64
+
+/* Threads the row-parallel loops use: 1 in the single-threaded build. */
+int32_t lgo_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 void lgo_default_opts(lgo_opts* o) {
   memset(o, 0, sizeof(*o));
@@ -195,18 +211,21 @@ int lgo_validate(int64_t n, const int64_t* rp, const int32_t* col, const double*
     if (rp[i + 1] < rp[i]) return LGO_E_GRAPH;
   if (rp[n] > 0 && (!col || !w)) return LGO_E_ARG;
   if (rp[n] >= ((int64_t)1 << 31)) return LGO_E_ARG;
-  double total = 0.0;
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(| : bad)
   for (int64_t i = 0; i < n; i++) {
     for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
       int64_t j = col[e];
-      if (j < 0 || j >= n || j == i) return LGO_E_GRAPH;
-      if (e > rp[i] && col[e - 1] >= j) return LGO_E_GRAPH;
-      if (!(w[e] > 0.0) || !isfinite(w[e])) return LGO_E_GRAPH;
+      if (j < 0 || j >= n || j == i) { bad = 1; break; }
+      if (e > rp[i] && col[e - 1] >= j) { bad = 1; break; }
+      if (!(w[e] > 0.0) || !isfinite(w[e])) { bad = 1; break; }
       int64_t back = find_entry(rp, col, j, i);
-      if (back < 0 || w[back] != w[e]) return LGO_E_GRAPH;
-      total += w[e];
+      if (back < 0 || w[back] != w[e]) { bad = 1; break; }
     }
   }
+  if (bad) return LGO_E_GRAPH;
+  double total = 0.0;
+  for (int64_t e = 0; e < rp[n]; e++) total += w[e];
   if (!(total < 0x1p62)) return LGO_E_RANGE;
   /* connectivity by breadth-first search from vertex 0 */
   int32_t* queue = (int32_t*)xmalloc(sizeof(int32_t) * n);
@@ -233,6 +252,7 @@ int lgo_validate(int64_t n, const int64_t* rp, const int32_t* col, const double*
 int lgo_diag(int64_t n, const int64_t* rp, const int32_t* col, const double* w, double* d) {
   (void)col;
   int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(| : bad)
   for (int64_t i = 0; i < n; i++) {
     xacc a;
     xa_init(&a);
@@ -245,6 +265,7 @@ int lgo_diag(int64_t n, const int64_t* rp, const int32_t* col, const double* w, 
 
 /* y = L x = D x - A x, plain fp64 in row order. */
 static void spmv(const ocsr* A, const double* x, double* y) {
+#pragma omp parallel for schedule(dynamic, 1024)
   for (int64_t i = 0; i < A->n; i++) {
     double s = 0.0;
     for (int64_t e = A->rp[i]; e < A->rp[i + 1]; e++) s += A->w[e] * x[A->col[e]];
@@ -262,6 +283,7 @@ static void spmv(const ocsr* A, const double* x, double* y) {
 int64_t lgo_elim_select(int64_t n, const int64_t* rp, const int32_t* col, int32_t max_degree,
                         int32_t hash_mode, int32_t* z, uint8_t* F) {
   int64_t count = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : count)
   for (int64_t i = 0; i < n; i++) {
     int64_t best = -1;
     uint64_t best_h = UINT64_MAX; /* hash of "no candidate" is infinity */
@@ -392,11 +414,13 @@ int lgo_soc(int64_t n, const int64_t* rp, const int32_t* col, const double* w, c
             const lgo_opts* o, int32_t level, double* X, double* S) {
   double* Y = (double*)xmalloc(sizeof(double) * 4 * (size_t)n);
   int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1024)
   for (int64_t i = 0; i < n; i++)
     for (int k = 0; k < 4; k++) X[i * 4 + k] = lgo_tv(o->seed, level, k, i);
   const double omega = o->tv_omega;
   const double keep = 1.0 - omega;
   for (int sweep = 0; sweep < o->tv_sweeps; sweep++) {
+#pragma omp parallel for schedule(dynamic, 1024) reduction(| : bad)
     for (int64_t i = 0; i < n; i++) {
       for (int k = 0; k < 4; k++) {
         xacc a;
@@ -412,10 +436,12 @@ int lgo_soc(int64_t n, const int64_t* rp, const int32_t* col, const double* w, c
   free(Y);
   double* sq = (double*)xmalloc(sizeof(double) * (size_t)n);
   double* M = (double*)xmalloc(sizeof(double) * (size_t)n);
+#pragma omp parallel for schedule(dynamic, 1024)
   for (int64_t i = 0; i < n; i++) {
     const double* xi = X + i * 4;
     sq[i] = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2] + xi[3] * xi[3];
   }
+#pragma omp parallel for schedule(dynamic, 1024)
   for (int64_t i = 0; i < n; i++) {
     const double* xi = X + i * 4;
     double m = 0.0;
@@ -429,6 +455,7 @@ int lgo_soc(int64_t n, const int64_t* rp, const int32_t* col, const double* w, c
     }
     M[i] = m;
   }
+#pragma omp parallel for schedule(dynamic, 1024)
   for (int64_t i = 0; i < n; i++) {
     for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
       double mx = M[i] > M[col[e]] ? M[i] : M[col[e]];
@@ -476,6 +503,7 @@ int64_t lgo_aggregate(int64_t n, const int64_t* rp, const int32_t* col, const do
     memcpy(nstate, state, sizeof(int32_t) * (size_t)n);
     memcpy(nidx, idx, sizeof(int32_t) * (size_t)n);
     memset(lv, 0, sizeof(int32_t) * (size_t)n);
+#pragma omp parallel for schedule(dynamic, 1024)
     for (int64_t i = 0; i < n; i++) {
       if (state[i] != ST_UNDECIDED) continue;
       int have = 0, bs = 0;
@@ -496,7 +524,8 @@ int64_t lgo_aggregate(int64_t n, const int64_t* rp, const int32_t* col, const do
         nstate[i] = ST_DECIDED;
         nidx[i] = (int32_t)bj;
       } else if (bs == ST_UNDECIDED) {
-        lv[bj] += 1;
+#pragma omp atomic
+        lv[bj] += 1; /* integer tally: the same total in any order */
       }
     }
     for (int64_t i = 0; i < n; i++) votes[i] += lv[i];
@@ -684,11 +713,14 @@ static void cheb(const ocsr* A, double lmax, const lgo_opts* o, double* x, const
   double sigma = theta / delta;
   double rho = 1.0 / sigma;
   if (x_is_zero) {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++) r[i] = b[i] / A->d[i];
   } else {
     spmv(A, x, t);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++) r[i] = (b[i] - t[i]) / A->d[i];
   }
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; i++) {
     p[i] = r[i] / theta;
     x[i] = (x_is_zero ? 0.0 : x[i]) + p[i];
@@ -697,6 +729,7 @@ static void cheb(const ocsr* A, double lmax, const lgo_opts* o, double* x, const
     double rho1 = 1.0 / (2.0 * sigma - rho);
     double c1 = rho1 * rho, c2 = 2.0 * rho1 / delta;
     spmv(A, x, t);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++) {
       r[i] = (b[i] - t[i]) / A->d[i];
       p[i] = c1 * p[i] + c2 * r[i];
@@ -1092,6 +1125,7 @@ static void precond(lgo_hier* h, int l, const double* b, double* x) {
   olevel* L = &h->lev[l];
   int64_t n = L->A.n;
   if (L->type == LGO_COARSEST) {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++) {
       double s = 0.0;
       for (int64_t j = 0; j < n; j++) s += h->Lplus[i * n + j] * b[j];
@@ -1116,6 +1150,7 @@ static void precond(lgo_hier* h, int l, const double* b, double* x) {
     add_work(h, (double)L->nnzP);
     precond(h, l + 1, bc, xc); /* no Krylov acceleration on elimination levels */
     /* x = P x_c + F-smoother (additive two-level form) */
+#pragma omp parallel for schedule(dynamic, 1024)
     for (int64_t a = 0; a < n; a++) {
       if (L->map[a] >= 0) {
         x[a] = xc[L->map[a]];

@@ -45,6 +45,8 @@ typedef struct {
 } lgo_opts;
 
 void lgo_default_opts(lgo_opts* o);
+/* Threads of the row-parallel loops (1 unless built with -fopenmp). */
+int32_t lgo_threads(void);
 
 /* ---- primitives (pinned individually by the tests) ---- */
 uint64_t lgo_mix64(uint64_t z);
