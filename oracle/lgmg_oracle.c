@@ -640,10 +640,39 @@ double lgo_tridiag_max(const double* alpha, const double* beta, int32_t m) {
   return 0.5 * (lo + hi);
 }
 
+/* Exact (order-free) sums for the Lanczos estimate: like every other sum that
+ * feeds a stored hierarchy value, they are XSUM accumulations (lambda_max
+ * sets the smoother's interval).  xdot: sum of a_i b_i, or of (d_i a_i) a_i
+ * when d is given, or of a_i when b and d are NULL. */
+static double xdot(const double* a, const double* b, const double* d, int64_t n, int* bad) {
+  xacc s;
+  xa_init(&s);
+  for (int64_t i = 0; i < n; i++)
+    xa_add(&s, d ? (d[i] * a[i]) * a[i] : b ? a[i] * b[i] : a[i]);
+  *bad |= s.bad;
+  return xa_value(&s);
+}
+
+/* y = L x with each row's sum of w_ij x_j exact. */
+static void spmv_exact(const ocsr* A, const double* x, double* y, int* bad) {
+  int b = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(| : b)
+  for (int64_t i = 0; i < A->n; i++) {
+    xacc s;
+    xa_init(&s);
+    for (int64_t e = A->rp[i]; e < A->rp[i + 1]; e++) xa_add(&s, A->w[e] * x[A->col[e]]);
+    b |= s.bad;
+    y[i] = A->d[i] * x[i] - xa_value(&s);
+  }
+  *bad |= b;
+}
+
 /* lambda_max of D^-1 L by `steps` Lanczos steps in the D inner product
  * (equivalent to Arnoldi for this D-self-adjoint operator; Section 3.6 uses
  * 10 Arnoldi iterations).  Start vector: the counter generator's stream 64 at
- * this level, mean-projected.  Returns the largest Ritz value. */
+ * this level, mean-projected.  Every sum is exact, so the Ritz values do not
+ * depend on summation order (a clustered spectrum makes ten steps sensitive
+ * to it).  Returns the largest Ritz value. */
 double lgo_lanczos_lmax(int64_t n, const int64_t* rp, const int32_t* col, const double* w,
                         const double* d, int32_t steps, uint64_t seed, int32_t level) {
   if (n < 2 || steps < 1) return 0.0;
@@ -653,33 +682,21 @@ double lgo_lanczos_lmax(int64_t n, const int64_t* rp, const int32_t* col, const 
   double* u = (double*)xmalloc(sizeof(double) * (size_t)n);
   double* al = (double*)xcalloc((size_t)steps, sizeof(double));
   double* be = (double*)xcalloc((size_t)steps, sizeof(double));
-  double mean = 0.0;
-  for (int64_t i = 0; i < n; i++) {
-    q[i] = lgo_tv(seed, level, TV_LANCZOS_STREAM, i);
-    mean += q[i];
-  }
-  mean /= (double)n;
-  double nrm = 0.0;
-  for (int64_t i = 0; i < n; i++) {
-    q[i] -= mean;
-    nrm += d[i] * q[i] * q[i];
-  }
-  nrm = sqrt(nrm);
+  int bad = 0;
+  for (int64_t i = 0; i < n; i++) q[i] = lgo_tv(seed, level, TV_LANCZOS_STREAM, i);
+  double mean = xdot(q, NULL, NULL, n, &bad);
+  for (int64_t i = 0; i < n; i++) q[i] -= mean / (double)n;
+  double nrm = sqrt(xdot(q, NULL, d, n, &bad));
   for (int64_t i = 0; i < n; i++) q[i] /= nrm;
   double bprev = 0.0, scale = 0.0;
   int m = 0;
   for (int j = 0; j < steps; j++) {
-    spmv(&A, q, u); /* u = L q */
-    double a = 0.0;
-    for (int64_t i = 0; i < n; i++) a += q[i] * u[i];
+    spmv_exact(&A, q, u, &bad); /* u = L q */
+    double a = xdot(q, u, NULL, n, &bad);
     al[j] = a;
     m = j + 1;
-    double b2 = 0.0;
-    for (int64_t i = 0; i < n; i++) {
-      u[i] = u[i] / d[i] - a * q[i] - bprev * qp[i];
-      b2 += d[i] * u[i] * u[i];
-    }
-    double b = sqrt(b2);
+    for (int64_t i = 0; i < n; i++) u[i] = u[i] / d[i] - a * q[i] - bprev * qp[i];
+    double b = sqrt(xdot(u, NULL, d, n, &bad));
     if (fabs(a) + bprev > scale) scale = fabs(a) + bprev;
     if (j == steps - 1 || b <= 1e-12 * scale) break;
     be[j] = b;
@@ -755,13 +772,23 @@ int lgo_cheb_apply(int64_t n, const int64_t* rp, const int32_t* col, const doubl
 
 /* --------------------------------------------------------- coarsest ---- */
 
-/* Dense pseudo-inverse of a connected graph's Laplacian:
- * L^+ = (L + 11^T/n)^-1 - 11^T/n, by Cholesky in fp64. */
+/* Dense pseudo-inverse of a connected graph's Laplacian, the coarsest
+ * level's direct solve (Algorithm 1):
+ *     L^+ = (L + (s/n) 11^T)^-1 - 11^T/(s n)    for any s > 0,
+ * because 1 spans the null space and is an eigenvector of L + (s/n)11^T with
+ * eigenvalue s.  s = max_i d_i (an order-free choice) puts that eigenvalue
+ * inside the range of L's other eigenvalues, so the matrix inverted is no worse
+ * conditioned than L is on the mean-zero space; s = 1 would not be when the
+ * weights are far from 1.  Inverted by Cholesky in fp64. */
 int lgo_pinv_dense(int64_t n, const int64_t* rp, const int32_t* col, const double* w,
                    const double* d, double* out) {
-  double inv_n = 1.0 / (double)n;
+  double s = 0.0;
+  for (int64_t i = 0; i < n; i++)
+    if (d[i] > s) s = d[i];
+  if (!(s > 0.0)) s = 1.0; /* one vertex: L = 0 */
+  double shift = s / (double)n, inv_sn = 1.0 / (s * (double)n);
   double* M = (double*)xmalloc(sizeof(double) * (size_t)(n * n));
-  for (int64_t i = 0; i < n * n; i++) M[i] = inv_n;
+  for (int64_t i = 0; i < n * n; i++) M[i] = shift;
   for (int64_t i = 0; i < n; i++) {
     M[i * n + i] += d[i];
     for (int64_t e = rp[i]; e < rp[i + 1]; e++) M[i * n + col[e]] -= w[e];
@@ -795,7 +822,7 @@ int lgo_pinv_dense(int64_t n, const int64_t* rp, const int32_t* col, const doubl
       for (int64_t k = i + 1; k < n; k++) t -= M[k * n + i] * y[k];
       y[i] = t / M[i * n + i];
     }
-    for (int64_t i = 0; i < n; i++) out[i * n + c] = y[i] - inv_n;
+    for (int64_t i = 0; i < n; i++) out[i * n + c] = y[i] - inv_sn;
   }
   free(y);
   free(M);

@@ -229,6 +229,27 @@ struct RunXsumOp {
   }
 };
 
+// u[row] = (L q)_row = d_row q_row - exact sum of w q over the row (the
+// Lanczos product: its sums are order free, so the estimate does not depend
+// on how rows are split among lanes).
+struct LzXsumOp {
+  using Acc = XLAcc;
+  const int32_t* __restrict__ col;
+  const double* __restrict__ w;
+  const double* __restrict__ d;
+  const double* __restrict__ q;
+  double* __restrict__ u;
+  int* flags;
+  XSUM_ACC_OPS
+  __device__ bool active(int64_t) const { return true; }
+  __device__ void accum(Acc& a, int64_t, int e) const { add(a, w[e] * q[col[e]]); }
+  __device__ void finish(int64_t row, const Acc& a, int lane, int) const {
+    if (lane) return;
+    u[row] = d[row] * q[row] - total(a);
+    if (a.bad) atomicOr(flags, F_XSUM);
+  }
+};
+
 // --------------------------------------- Algorithm 2: elimination choice
 struct MinAcc {
   uint64_t h;
@@ -715,7 +736,82 @@ static void reduce_dev(const double* a, const double* b, const double* d, int64_
   hipLaunchKernelGGL(k_red2, dim3(1), dim3(kBlock), 0, st, partial, nb, out);
 }
 
+// ------------------------------------------ exact reductions over n entries
+// Terms of a sum, an inner product a.b or a D-weighted square (d a) a, added
+// exactly in limb form by every thread of a fixed grid; each workgroup folds
+// its threads' limbs (integer adds: order free) into partial[block].  Any
+// workgroup can then form the same total from the partials.
+struct XPartial {
+  uint64_t l[4];
+  int bad;
+  int pad[3];
+};
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_xred(const double* __restrict__ a,
+                                                 const double* __restrict__ b,
+                                                 const double* __restrict__ d, int64_t n,
+                                                 XPartial* __restrict__ partial) {
+  uint64_t acc[4] = {0, 0, 0, 0};
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    const double t = MODE == RED_SUM ? a[i] : MODE == RED_DOT ? a[i] * b[i] : (d[i] * a[i]) * a[i];
+    xs_limbs_add(t, acc, bad);
+  }
+  __shared__ uint64_t sm[4][kBlock];
+  __shared__ int sbad;
+  if (threadIdx.x == 0) sbad = 0;
+  for (int q = 0; q < 4; q++) sm[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  if (bad) atomicOr(&sbad, 1);
+  for (int m = kBlock / 2; m > 0; m >>= 1) {
+    if ((int)threadIdx.x < m)
+      for (int q = 0; q < 4; q++) sm[q][threadIdx.x] += sm[q][threadIdx.x + m];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < 4; q++) partial[blockIdx.x].l[q] = sm[q][0];
+    partial[blockIdx.x].bad = sbad;
+  }
+}
+
+// The exact total of nb partials, rounded once (every workgroup that calls it
+// obtains the same bits); raises F_XSUM for terms outside the range.
+__device__ __forceinline__ double xred_total(const XPartial* __restrict__ partial, int nb,
+                                             int* flags) {
+  __shared__ uint64_t sm[4][kBlock];
+  uint64_t acc[4] = {0, 0, 0, 0};
+  int bad = 0;
+  for (int i = threadIdx.x; i < nb; i += kBlock) {
+    for (int q = 0; q < 4; q++) acc[q] += partial[i].l[q];
+    bad |= partial[i].bad;
+  }
+  for (int q = 0; q < 4; q++) sm[q][threadIdx.x] = acc[q];
+  if (bad) atomicOr(flags, F_XSUM);
+  __syncthreads();
+  for (int m = kBlock / 2; m > 0; m >>= 1) {
+    if ((int)threadIdx.x < m)
+      for (int q = 0; q < 4; q++) sm[q][threadIdx.x] += sm[q][threadIdx.x + m];
+    __syncthreads();
+  }
+  uint64_t tot[4];
+  for (int q = 0; q < 4; q++) tot[q] = sm[q][0];
+  __syncthreads();
+  return xs_value(xs_limbs_total(tot));
+}
+
+__global__ __launch_bounds__(kBlock) void k_xred_final(const XPartial* __restrict__ partial, int nb,
+                                                       double* __restrict__ out, int* flags) {
+  const double v = xred_total(partial, nb, flags);
+  if (threadIdx.x == 0) *out = v;
+}
+
 // ---------------------------------------------- Lanczos (Section 3.6)
+// Every sum of the estimate (the products' rows, the inner products and
+// norms) is exact and order free, like the other sums that feed stored
+// hierarchy values: lambda_max is reproducible bit for bit whatever the row
+// schedule, and equal to a sequential evaluation of the same steps.
 enum { LZ_AL = 0, LZ_BE = 64, LZ_B2 = 128, LZ_SCALE = 129, LZ_M = 130, LZ_STOP = 131,
        LZ_SUM = 132, LZ_SIZE = 136 };
 
@@ -751,57 +847,49 @@ __global__ void k_lz_next(double* __restrict__ u, double* __restrict__ q, double
   q[i] = u[i] / b;
 }
 
-// Sum of nb partials by one workgroup, in the same order as k_red2, so that
-// every workgroup that calls it obtains the same bits.
-__device__ __forceinline__ double block_sum_partials(const double* __restrict__ partial, int nb,
-                                                     double* sm) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kBlock) s += partial[i];
-  sm[threadIdx.x] = s;
-  __syncthreads();
-  for (int m = kBlock / 2; m > 0; m >>= 1) {
-    if ((int)threadIdx.x < m) sm[threadIdx.x] += sm[threadIdx.x + m];
-    __syncthreads();
-  }
-  const double r = sm[0];
-  __syncthreads();
-  return r;
-}
-
 // One Lanczos step after u = L q and the partials of q . u: alpha from those
-// partials, u <- D^-1 u - alpha q - beta_{j-1} q_prev, and the partials of
-// u . D u for beta (grid-stride over a fixed grid, like k_red1).
-__global__ __launch_bounds__(kBlock) void k_lz_update_dd(
+// partials (exact, the same bits in every workgroup),
+// u <- D^-1 u - alpha q - beta_{j-1} q_prev, and the partials of (d u) u for
+// beta.
+__global__ __launch_bounds__(kBlock) void k_lz_update_x(
     double* __restrict__ u, const double* __restrict__ q, const double* __restrict__ qp,
     const double* __restrict__ d, int64_t n, double* __restrict__ lz, int j,
-    const double* __restrict__ dot_part, int nb_dot, double* __restrict__ dd_part) {
-  __shared__ double sm[kBlock];
+    const XPartial* __restrict__ dot_part, int nb_dot, XPartial* __restrict__ dd_part,
+    int* flags) {
   if (lz[LZ_STOP] != 0.0) return;  // uniform: every workgroup reads the same flag
-  const double a = block_sum_partials(dot_part, nb_dot, sm);
+  const double a = xred_total(dot_part, nb_dot, flags);
   if (blockIdx.x == 0 && threadIdx.x == 0) lz[LZ_AL + j] = a;
   const double bp = j > 0 ? lz[LZ_BE + j - 1] : 0.0;
-  double s = 0.0;
+  uint64_t acc[4] = {0, 0, 0, 0};
+  int bad = 0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kBlock) {
     const double v = u[i] / d[i] - a * q[i] - bp * qp[i];
     u[i] = v;
-    s += d[i] * v * v;
+    xs_limbs_add((d[i] * v) * v, acc, bad);
   }
-  sm[threadIdx.x] = s;
+  __shared__ uint64_t sm[4][kBlock];
+  __shared__ int sbad;
+  if (threadIdx.x == 0) sbad = 0;
+  for (int q2 = 0; q2 < 4; q2++) sm[q2][threadIdx.x] = acc[q2];
   __syncthreads();
+  if (bad) atomicOr(&sbad, 1);
   for (int m = kBlock / 2; m > 0; m >>= 1) {
-    if ((int)threadIdx.x < m) sm[threadIdx.x] += sm[threadIdx.x + m];
+    if ((int)threadIdx.x < m)
+      for (int q2 = 0; q2 < 4; q2++) sm[q2][threadIdx.x] += sm[q2][threadIdx.x + m];
     __syncthreads();
   }
-  if (threadIdx.x == 0) dd_part[blockIdx.x] = sm[0];
+  if (threadIdx.x == 0) {
+    for (int q2 = 0; q2 < 4; q2++) dd_part[blockIdx.x].l[q2] = sm[q2][0];
+    dd_part[blockIdx.x].bad = sbad;
+  }
 }
 
-// beta_j from the partials of u . D u, then the stopping test.
-__global__ __launch_bounds__(kBlock) void k_lz_beta_dd(const double* __restrict__ dd_part, int nb,
-                                                       double* lz, int j, int steps) {
-  __shared__ double sm[kBlock];
+// beta_j from the partials of (d u) u, then the stopping test.
+__global__ __launch_bounds__(kBlock) void k_lz_beta_x(const XPartial* __restrict__ dd_part, int nb,
+                                                      double* lz, int j, int steps, int* flags) {
   if (lz[LZ_STOP] != 0.0) return;
-  const double b2 = block_sum_partials(dd_part, nb, sm);
+  const double b2 = xred_total(dd_part, nb, flags);
   if (threadIdx.x != 0) return;
   const double a = lz[LZ_AL + j];
   const double bp = j > 0 ? lz[LZ_BE + j - 1] : 0.0;
@@ -862,17 +950,38 @@ __global__ __launch_bounds__(64) void k_lz_eig(const double* __restrict__ lz,
 }
 
 // --------------------------------------------- coarsest pseudo-inverse
+// L^+ = (L + (s/n) 11^T)^-1 - 11^T/(s n) for any s > 0 on a connected graph:
+// 1 is an eigenvector of the shifted matrix with eigenvalue s.  With
+// s = max_i d_i that eigenvalue lies inside the range of L's others, so the
+// inverted matrix is as well conditioned as L on the mean-zero space (a fixed
+// s = 1 is not when the weights are far from 1).
+
+// s = max_i d_i (1 for a single vertex, whose L is 0), one workgroup.
+__global__ __launch_bounds__(kBlock) void k_coarse_shift(const double* __restrict__ d, int64_t n,
+                                                         double* __restrict__ s_out) {
+  __shared__ double red[kBlock];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kBlock) m = fmax(m, d[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *s_out = red[0] > 0.0 ? red[0] : 1.0;
+}
+
 __global__ void k_dense_lap(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                             const double* __restrict__ w, const double* __restrict__ d, int64_t n,
-                            double* __restrict__ M) {
+                            const double* __restrict__ s, double* __restrict__ M) {
   const int64_t i = blockIdx.x;
-  const double inv_n = 1.0 / (double)n;
-  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) M[i * n + j] = inv_n + (i == j ? d[i] : 0.0);
+  const double shift = *s / (double)n;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) M[i * n + j] = shift + (i == j ? d[i] : 0.0);
   __syncthreads();
   for (int e = rp[i] + threadIdx.x; e < rp[i + 1]; e += blockDim.x) M[i * n + col[e]] -= w[e];
 }
 
-// In-place Gauss-Jordan inversion of the SPD matrix L + 11^T/n (no pivoting),
+// In-place Gauss-Jordan inversion of the SPD matrix L + (s/n) 11^T (no pivoting),
 // one workgroup, for the small coarsest level.
 __global__ __launch_bounds__(1024) void k_gauss_jordan(double* __restrict__ M, int n,
                                                        double* __restrict__ colbuf) {
@@ -893,9 +1002,10 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(double* __restrict__ M, i
   }
 }
 
-__global__ void k_sub_inv_n(double* __restrict__ M, int64_t nn, int64_t n) {
+__global__ void k_sub_shift(double* __restrict__ M, int64_t nn, int64_t n,
+                            const double* __restrict__ s) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t < nn) M[t] -= 1.0 / (double)n;
+  if (t < nn) M[t] -= 1.0 / (*s * (double)n);
 }
 
 __global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
@@ -1269,31 +1379,36 @@ void lanczos(Ctx& c, Level& L, int level, double* out) {
   double* qp = tmp.get<double>(n);
   double* u = tmp.get<double>(n);
   double* lz = tmp.get<double>(LZ_SIZE);
-  double* part = tmp.get<double>(kRedBlocks);
   const int steps = std::min(o.eig_iters, 64);
   hipLaunchKernelGGL(k_lz_init_scalars, dim3(1), dim3(64), 0, st, lz);
   if (n < 2 || steps < 1) {
     hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(64), 0, st, lz, out);
     return;
   }
-  hipLaunchKernelGGL(k_lz_start, dim3(nblk(n)), dim3(kBlock), 0, st, q, qp, n, c.key, level);
-  reduce_dev<RED_SUM>(q, nullptr, nullptr, n, part, lz + LZ_SUM, st);
-  hipLaunchKernelGGL(k_lz_center, dim3(nblk(n)), dim3(kBlock), 0, st, q, n, lz);
-  reduce_dev<RED_DDOT>(q, nullptr, L.d, n, part, lz + LZ_B2, st);
-  hipLaunchKernelGGL(k_lz_scale, dim3(nblk(n)), dim3(kBlock), 0, st, q, n, lz);
-  double* part2 = tmp.get<double>(kRedBlocks);
   const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ceil_div(n, kBlock)));
+  XPartial* part = tmp.get<XPartial>(kRedBlocks);
+  XPartial* part2 = tmp.get<XPartial>(kRedBlocks);
+  hipLaunchKernelGGL(k_lz_start, dim3(nblk(n)), dim3(kBlock), 0, st, q, qp, n, c.key, level);
+  hipLaunchKernelGGL((k_xred<RED_SUM>), dim3(nb), dim3(kBlock), 0, st, (const double*)q,
+                     (const double*)nullptr, (const double*)nullptr, n, part);
+  hipLaunchKernelGGL(k_xred_final, dim3(1), dim3(kBlock), 0, st, (const XPartial*)part, nb,
+                     lz + LZ_SUM, c.flags);
+  hipLaunchKernelGGL(k_lz_center, dim3(nblk(n)), dim3(kBlock), 0, st, q, n, lz);
+  hipLaunchKernelGGL((k_xred<RED_DDOT>), dim3(nb), dim3(kBlock), 0, st, (const double*)q,
+                     (const double*)nullptr, (const double*)L.d, n, part);
+  hipLaunchKernelGGL(k_xred_final, dim3(1), dim3(kBlock), 0, st, (const XPartial*)part, nb,
+                     lz + LZ_B2, c.flags);
+  hipLaunchKernelGGL(k_lz_scale, dim3(nblk(n)), dim3(kBlock), 0, st, q, n, lz);
   for (int j = 0; j < steps; j++) {
-    LapOp<double, 1, LAP_SPMV> op{L.col, L.w, L.d, L.dinv, q, u, nullptr, nullptr, 0.0, 0.0, 0.0};
-    // same kernel and bytes as the solve's fp64 product (family "spmv")
-    run_rows(L.sched, L.rp, op, st, "spmv", 4.0 * (n + 1) + 12.0 * L.nnz + 24.0 * n);
-    hipLaunchKernelGGL((k_red1<RED_DOT>), dim3(nb), dim3(kBlock), 0, st, (const double*)q,
+    run_rows(L.sched, L.rp, LzXsumOp{L.col, L.w, L.d, q, u, c.flags}, st, "lanczos",
+             4.0 * (n + 1) + 12.0 * L.nnz + 24.0 * n);
+    hipLaunchKernelGGL((k_xred<RED_DOT>), dim3(nb), dim3(kBlock), 0, st, (const double*)q,
                        (const double*)u, (const double*)nullptr, n, part);
-    hipLaunchKernelGGL(k_lz_update_dd, dim3(nb), dim3(kBlock), 0, st, u, (const double*)q,
-                       (const double*)qp, (const double*)L.d, n, lz, j, (const double*)part, nb,
-                       part2);
-    hipLaunchKernelGGL(k_lz_beta_dd, dim3(1), dim3(kBlock), 0, st, (const double*)part2, nb, lz, j,
-                       steps);
+    hipLaunchKernelGGL(k_lz_update_x, dim3(nb), dim3(kBlock), 0, st, u, (const double*)q,
+                       (const double*)qp, (const double*)L.d, n, lz, j, (const XPartial*)part, nb,
+                       part2, c.flags);
+    hipLaunchKernelGGL(k_lz_beta_x, dim3(1), dim3(kBlock), 0, st, (const XPartial*)part2, nb, lz,
+                       j, steps, c.flags);
     hipLaunchKernelGGL(k_lz_next, dim3(nblk(n)), dim3(kBlock), 0, st, u, q, qp, n, lz, j);
   }
   hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(64), 0, st, lz, out);
@@ -1319,11 +1434,14 @@ void coarsest(Ctx& c, Level& L) {
     c.tmp.rewind(m);
   }
   h->Lplus = h->mem.get<double>(n * n);
+  double* shift = c.tmp.get<double>(1);
+  hipLaunchKernelGGL(k_coarse_shift, dim3(1), dim3(kBlock), 0, c.st, L.d, n, shift);
   hipLaunchKernelGGL(k_dense_lap, dim3((unsigned)n), dim3(kBlock), 0, c.st, L.rp, L.col, L.w, L.d,
-                     n, h->Lplus);
+                     n, shift, h->Lplus);
   double* colbuf = c.tmp.get<double>(n);
   hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, c.st, h->Lplus, (int)n, colbuf);
-  hipLaunchKernelGGL(k_sub_inv_n, dim3(nblk(n * n)), dim3(kBlock), 0, c.st, h->Lplus, n * n, n);
+  hipLaunchKernelGGL(k_sub_shift, dim3(nblk(n * n)), dim3(kBlock), 0, c.st, h->Lplus, n * n, n,
+                     shift);
   LG_LAUNCH_CHECK();
 }
 

@@ -61,7 +61,8 @@ def compare_hierarchies(hg, ho, setup_data=False):
             assert a["nc"] == b.nc
             assert np.array_equal(mp, ho.map(l)), f"level {l} map"
         if a["type"] == oracle.AGG:
-            assert abs(a["lmax"] - b.lmax) <= 1e-10 * abs(b.lmax), f"level {l} lmax"
+            # same exact-sum Lanczos steps; the two tridiagonal eigensolvers differ in ulps
+            assert abs(a["lmax"] - b.lmax) <= 1e-12 * abs(b.lmax), f"level {l} lmax"
         if setup_data and a["type"] == oracle.AGG:
             sd = lg.lg_export_setup_data(hg, l)
             Xo, So = ho.soc(l)

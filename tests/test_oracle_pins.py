@@ -451,6 +451,19 @@ def test_coarsest_pseudo_inverse():
     assert np.abs(L @ P @ L - L).max() <= 1e-10 * np.abs(L).max()
 
 
+@pytest.mark.parametrize("scale", [1e-3, 1.0, 1e5])
+def test_coarsest_pseudo_inverse_at_any_weight_scale(scale):
+    """The dense direct solve stays accurate to rounding when the weights are
+    far from 1: the null-space shift follows the diagonal's scale, so the
+    inverted matrix is as well conditioned as L on the mean-zero space."""
+    g = gg.gnp(60, 0.15, seed=5)
+    g.w = g.w * scale
+    d = np.bincount(np.repeat(np.arange(g.n), np.diff(g.row_ptr)), weights=g.w, minlength=g.n)
+    P = oracle.pinv_dense(g)
+    ref = np.linalg.pinv(dense_L(g, d))
+    assert np.abs(P - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 # ------------------------------------------------------------- eigenvalue
 
 def test_tridiag_max_matches_eigvalsh():
