@@ -91,6 +91,12 @@ typedef struct {
   int32_t merge_path;       /* one-column Laplacian products: 0 degree-class rows only (default),
                                1 the autotuner may pick a merge-path traversal per level, 2 every
                                level uses it (the autotuner then leaves one-column levels alone) */
+  int32_t row_shift;        /* -1: lanes per row chosen by the autotuner (shift 1 without it);
+                               0, 1, 2: every level's row products use 2^(class - row_shift)
+                               lanes and the autotuner is not run.  The shift fixes the
+                               summation order inside a row, so a solve is bit-reproducible
+                               given the shifts in lg_level_stats, and a tuned run can differ
+                               from another process's in the last bits */
 } lg_setup_opts;
 
 typedef struct lg_hierarchy lg_hierarchy;
@@ -158,15 +164,26 @@ lg_status lg_eigs(lg_hierarchy* h, int32_t nev, double tol, int32_t max_iter, do
 lg_status lg_cycle(lg_hierarchy* h, const double* B, double* X, int32_t k, void* hip_stream);
 
 /* Y = L_l X on hierarchy level l for device n_l x k fp64 arrays (fp64
- * values).  Asynchronous on hip_stream. */
+ * values), with L_l = D_l - A_l the level's Laplacian (Section 2.1; coarse
+ * levels are the Galerkin and Schur-complement operators of Sections 3.4-3.5).
+ * k must be 1, 2, 4, 8, 16 or 32.  X and Y are caller-owned; the call only
+ * queues work on hip_stream (asynchronous).  Errors: LG_E_ARG for a bad level
+ * or k. */
 lg_status lg_spmv(lg_hierarchy* h, int32_t level, const double* X, double* Y, int32_t k,
                   void* hip_stream);
 
-/* Level statistics into out[0 .. min(cap, levels)); *n_levels = depth. */
+/* Level statistics into out[0 .. min(cap, levels)) (host), *n_levels = depth
+ * (host): the level sequence of the setup loop (Section 4: elimination and
+ * aggregation levels down to a coarsest level of at most coarsest_nnz
+ * entries) and the lambda_max estimates of Section 3.6.  Errors: LG_E_ARG for
+ * a null h or n_levels. */
 lg_status lg_hierarchy_stats(const lg_hierarchy* h, lg_level_stats* out, int32_t cap,
                              int32_t* n_levels);
 
-/* Copy level l's operator to host buffers sized from lg_hierarchy_stats:
+/* Parity hook.  Copy level l's operator (its Laplacian as adjacency plus
+ * diagonal, Section 2.1) and its transfer map (the aggregates of Algorithm 3,
+ * or the kept vertices of Algorithm 2's elimination) to host buffers sized from
+ * lg_hierarchy_stats:
  * row_ptr int64[n+1], col int32[nnz], w float64[nnz], d float64[n] (any may
  * be NULL).  map (int32[n], may be NULL) receives the aggregate of each vertex
  * (aggregation level) or its coarse index, -1 if eliminated (elimination
@@ -174,7 +191,9 @@ lg_status lg_hierarchy_stats(const lg_hierarchy* h, lg_level_stats* out, int32_t
 lg_status lg_export_level(const lg_hierarchy* h, int32_t level, int64_t* row_ptr, int32_t* col,
                           double* w, double* d, int32_t* map);
 
-/* Setup intermediates of level l, kept only when keep_setup_data was set
+/* Parity hook: setup intermediates of level l (the smoothed test vectors and
+ * affinity strengths of Section 3.5, the voting state of Algorithm 3 and the
+ * elimination product of Algorithm 2), kept only when keep_setup_data was set
  * (else LG_E_ARG); any pointer may be NULL.  Host buffers:
  * X float64[n*4] (test vectors after smoothing), S float64[nnz] (strength per
  * stored edge), state int32[n] (0 Decided, 1 Undecided, 2 Seed), idx int32[n]
@@ -183,25 +202,33 @@ lg_status lg_export_level(const lg_hierarchy* h, int32_t level, int64_t* row_ptr
 lg_status lg_export_setup_data(const lg_hierarchy* h, int32_t level, double* X, double* S,
                                int32_t* state, int32_t* idx, int32_t* votes, int32_t* z);
 
-/* Dense pseudo-inverse of the coarsest level, host float64[nc*nc]. */
+/* Parity hook: the dense pseudo-inverse used as the coarsest-level solve
+ * (Algorithm 1's direct solve at the bottom of the cycle), host
+ * float64[nc*nc] row-major.  Errors: LG_E_ARG for a null argument. */
 lg_status lg_export_coarsest(const lg_hierarchy* h, double* Lplus);
 
-/* Device bytes held by the hierarchy, including the solve workspace. */
+/* Device bytes held by the hierarchy, including the solve workspace; the
+ * serving loop admits hierarchies by this figure.  No passage of the paper
+ * defines it.  0 for NULL. */
 size_t lg_hierarchy_bytes(const lg_hierarchy* h);
 
-/* Milliseconds the last lg_setup on h took (host wall clock). */
+/* Milliseconds the lg_setup call that built h took (host wall clock, for
+ * measurement; no passage of the paper defines it).  0 for NULL. */
 double lg_setup_ms(const lg_hierarchy* h);
 
-/* Release h.  Waits for the work queued on the device (as hipFree would),
+/* Release h (memory management only; no passage of the paper applies).
+ * Waits for the work queued on the device (as hipFree would),
  * then keeps its device blocks, up to 4 GiB per process, in a per-device
  * cache that later lg_setup calls draw from before allocating; blocks beyond
  * that are freed.  NULL is ignored. */
 void lg_free(lg_hierarchy* h);
 
-/* Kernel timing with HIP events for one kernel family (name as listed by
- * lg_profile_names), recorded around each of its launches on the launch
- * stream while enabled.  Families of the sparse products time the row kernel
- * alone: "spmv" the fp64 L x of setup's Lanczos steps and of the CG iteration,
+/* Kernel timing with HIP events for kernel families (one name as listed by
+ * lg_profile_names, or several separated by commas), recorded around each of
+ * their launches on the launch stream while enabled.  Families of the sparse
+ * products time the row kernel alone: "spmv" the CG iteration's fp64 L x,
+ * "lanczos" the fp64 L x of setup's Lanczos steps (one column: the same kernel
+ * instance as a one-column "spmv"),
  * "spmm" lg_spmv's own launches, "cheb0" the zero-start smoother step, "cheb1"
  * the first step from a nonzero iterate, "cheb" the later steps, "resid" the
  * cycle's residual, "resid64" the CG's true residual, "spmm_inner" the
@@ -219,18 +246,24 @@ const char* lg_status_str(lg_status s);
 const char* lg_last_error(void);
 
 /* ------------------------------------------------------------------------
- * Solve server: continuous batching over a pool of graphs.  Requests (graph,
- * right-hand sides, tolerance) may arrive at any time from any thread.  Worker
- * threads, each with its own HIP stream, take the oldest request whose graph
- * is idle together with every queued request for the same graph, tolerance
- * and iteration cap (up to max_batch_rhs columns) and run them as one
- * batched lg_solve; batches of different graphs overlap on the device.  A
- * graph's hierarchy is built on its first request and cached; it is admitted
- * when it fits hbm_budget after freeing the least recently used idle
- * hierarchies (a hierarchy larger than the budget runs alone).  A request's
- * columns are computed independently of the rest of its batch; the batch's
- * width (see lg_solve) only changes summation orders, so each result agrees
- * with the same request solved alone within the solver tolerance.
+ * Solve server: continuous batching over a pool of graphs (a serving layer
+ * over lg_setup / lg_solve; no passage of the paper describes it).  Requests
+ * (graph, right-hand sides, tolerance) may arrive at any time from any thread.
+ * A worker thread, each with its own HIP stream, opens a session on the graph
+ * of the oldest waiting request: one batched CG (as lg_solve) whose columns
+ * are slots, as wide as the columns then queued for that graph (a power of
+ * two, at most max_batch_rhs).  At every CG iteration boundary the columns
+ * that have converged leave, a request completes when all its columns have,
+ * and freed or idle slots take the next queued requests for the same graph,
+ * tolerance and iteration cap (a request's columns enter together), unless a
+ * request of another graph has waited longer and no worker is free.  Each
+ * column runs its own CG (iteration cap, restarts, convergence test).
+ * Sessions on different graphs overlap on the device.  A graph's hierarchy is
+ * built on its first request and cached; it is admitted when it fits
+ * hbm_budget after freeing the least recently used idle hierarchies (a
+ * hierarchy larger than the budget runs alone).  A column's result depends on
+ * the session's width and its slot only through summation orders, so it
+ * agrees with the same request solved alone within the solver tolerance.
  * ------------------------------------------------------------------------ */
 typedef struct lg_server lg_server;
 
@@ -243,12 +276,13 @@ typedef struct {
 
 typedef struct {
   int64_t submitted, completed; /* requests */
-  int64_t batches;              /* batched solves run */
+  int64_t batches;              /* sessions (slot-batched solves) run */
   int64_t batched_columns;      /* right-hand sides solved in them */
   int64_t setups, evictions;    /* hierarchies built and freed for room */
   size_t resident_bytes;        /* device bytes of the cached hierarchies */
   size_t budget_bytes;          /* the admission budget in effect */
   int32_t resident_graphs;
+  int64_t refills;              /* right-hand sides admitted into a session already running */
 } lg_server_stats;
 
 /* Fill o with the defaults (4 workers, 32 columns, budget from free memory,

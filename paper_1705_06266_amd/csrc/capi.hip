@@ -59,6 +59,7 @@ extern "C" lg_status lg_default_opts(lg_setup_opts* o) {
   o->autotune = 1;
   o->elim_passes = 1;
   o->merge_path = 0;
+  o->row_shift = -1;
   return LG_OK;
 }
 
@@ -78,6 +79,7 @@ static const char* check_opts(const lg_setup_opts& o) {
   if (o.autotune != 0 && o.autotune != 1) return "autotune must be 0 or 1";
   if (o.elim_passes < 1 || o.elim_passes > 16) return "elim_passes must be in 1..16";
   if (o.merge_path < 0 || o.merge_path > 2) return "merge_path must be 0, 1 or 2";
+  if (o.row_shift < -1 || o.row_shift > 2) return "row_shift must be -1, 0, 1 or 2";
   return nullptr;
 }
 
@@ -107,7 +109,11 @@ extern "C" lg_status lg_setup(const lg_graph* g, const lg_setup_opts* o, void* h
   lg::alloc_solve_workspace(h, st);
   if (opts.merge_path == 2)
     for (auto& L : h->lev) L.sched.merge = true;
-  if (opts.autotune) lg::autotune(h, st);
+  if (opts.row_shift >= 0) {
+    for (auto& L : h->lev) L.sched.lane_shift = L.sched.col_shift = opts.row_shift;
+  } else if (opts.autotune) {
+    lg::autotune(h, st);
+  }
   LG_HIP(hipStreamSynchronize(st));
   h->setup_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

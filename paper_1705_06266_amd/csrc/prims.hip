@@ -3,6 +3,7 @@
 // device arena and the HIP-event profiler behind lg_profile_*.
 #include <cstring>
 #include <atomic>
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -143,7 +144,7 @@ namespace {
 struct Prof {
   std::mutex mu;
   std::atomic<bool> enabled{false};  // checked without the lock on every launch
-  std::string family;
+  std::vector<std::string> families;  // the enabled families
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
   std::vector<double> pending_bytes;
   std::vector<hipEvent_t> pool;
@@ -173,7 +174,7 @@ ProfScope::ProfScope(const char* family, hipStream_t s, double b, bool att)
   Prof& p = prof();
   if (!p.enabled.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> g(p.mu);
-  if (p.family.empty() || p.family != family) return;
+  if (std::find(p.families.begin(), p.families.end(), family) == p.families.end()) return;
   a = take_event(p);
   this->b = take_event(p);
   if (!attached) LG_HIP(hipEventRecord(a, st));
@@ -194,8 +195,20 @@ ProfScope::~ProfScope() {
 extern "C" lg_status lg_profile_enable(const char* family) {
   auto& p = lg::prof();
   std::lock_guard<std::mutex> g(p.mu);
-  p.family = family ? family : "";
-  p.enabled.store(!p.family.empty());
+  p.families.clear();
+  if (family) {
+    std::string f;
+    for (const char* c = family;; c++) {
+      if (*c == ',' || *c == '\0') {
+        if (!f.empty()) p.families.push_back(f);
+        f.clear();
+        if (*c == '\0') break;
+      } else {
+        f.push_back(*c);
+      }
+    }
+  }
+  p.enabled.store(!p.families.empty());
   p.launches = 0;
   p.ms = p.bytes = 0.0;
   return LG_OK;
@@ -228,7 +241,7 @@ extern "C" lg_status lg_profile_read(int64_t* launches, double* total_ms, double
 }
 
 extern "C" const char* lg_profile_names(void) {
-  return "spmv,spmm,resid64,cheb0,cheb1,cheb,resid,spmm_inner,restrict,prolong,coarse,"
+  return "spmv,lanczos,spmm,resid64,cheb0,cheb1,cheb,resid,spmm_inner,restrict,prolong,coarse,"
          "jacobi_xsum,row_xsum,affinity,vote,elim_select,radix,galerkin_reduce";
 }
 

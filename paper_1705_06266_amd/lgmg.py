@@ -48,6 +48,7 @@ class lg_setup_opts(C.Structure):
         ("seed", C.c_uint64), ("precision", C.c_int32), ("max_rhs", C.c_int32),
         ("keep_setup_data", C.c_int32), ("validate", C.c_int32), ("graphs", C.c_int32),
         ("autotune", C.c_int32), ("elim_passes", C.c_int32), ("merge_path", C.c_int32),
+        ("row_shift", C.c_int32),
     ]
 
 
@@ -71,7 +72,7 @@ class lg_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
                 ("batched_columns", C.c_int64), ("setups", C.c_int64), ("evictions", C.c_int64),
                 ("resident_bytes", C.c_size_t), ("budget_bytes", C.c_size_t),
-                ("resident_graphs", C.c_int32)]
+                ("resident_graphs", C.c_int32), ("refills", C.c_int64)]
 
 
 class LgError(RuntimeError):

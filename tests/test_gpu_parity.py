@@ -115,6 +115,10 @@ def test_solve_fp64_matches(built, name, cycle):
     bp = b - b.mean()
     rel_true = np.linalg.norm(bp - laplacian_apply(g, xg)) / np.linalg.norm(bp)
     assert rel_true <= 1e-8 * 1.001
+    # the library's residual and this one are fp64 sums in different orders: an
+    # entry of L x carries up to deg * eps * max|w x| of rounding, which at the
+    # 40,000-leaf star's hub is 4e-12 against ||b|| ~ 200, i.e. 2e-14 on the
+    # relative residual; 1e-13 bounds it with margin
     assert abs(info[0]["rel_residual"] - rel_true) <= 1e-3 * rel_true + 1e-13
     assert abs(info[0]["iters"] - ito) <= 1
     # both solve L x = b to 1e-8; the iterates of two fp64 runs of one method differ
@@ -382,3 +386,46 @@ def test_repeated_setups_are_bit_identical(built, name):
         assert cur[1] == ref[1], f"rep {rep} lmax"
         assert np.array_equal(bits(cur[2]), bits(ref[2])), f"rep {rep} solution"
         assert cur[3] == ref[3]
+
+
+@pytest.mark.parametrize("shift", [0, 1, 2])
+@pytest.mark.parametrize("name", ["chunglu_30k_hubs", "rmat_s12", "grid3d_12_loguniform"])
+def test_forced_row_shifts_match(built, name, shift):
+    """Every lane count the autotuner can choose (row_shift 0, 1, 2 on every
+    level, one-column and column-split kernels): products, one cycle and
+    solves against the oracle at the usual bars."""
+    import torch
+
+    g, hg, ho = _pair(name, row_shift=shift, max_rhs=4)
+    stats = lg.lg_hierarchy_stats(hg)
+    assert all(s["lane_shift"] == shift and s["col_shift"] == shift for s in stats)
+    rng = np.random.default_rng(5)
+    for l, s in enumerate(stats):
+        for k in (1, 4):
+            X = rng.standard_normal((s["n"], k))
+            Y = torch.empty((s["n"], k), dtype=torch.float64, device="cuda:0")
+            lg.lg_spmv(hg, l, to_dev(X), Y)
+            torch.cuda.synchronize()
+            Yo = np.stack([ho.spmv(l, X[:, c]) for c in range(k)], axis=1)
+            assert np.abs(Y.cpu().numpy() - Yo).max() <= 1e-12 * (np.abs(Yo).max() + 1e-300), (l, k)
+    B = gg.rhs(g.n, 4, 9)
+    B -= B.mean(axis=0)
+    Xc = lg.lg_cycle(hg, to_dev(B)).cpu().numpy()
+    for c in range(4):
+        xo = ho.cycle(B[:, c])
+        assert np.linalg.norm(Xc[:, c] - xo) <= 1e-10 * np.linalg.norm(xo), c
+    X, info, st = lg.lg_solve(hg, to_dev(B), rtol=1e-8, max_iter=300)
+    assert st == 0
+    X = X.cpu().numpy()
+    hm = gpu_setup(g, row_shift=shift, max_rhs=4, precision=lg.LG_MIXED)
+    Xm, infm, stm = lg.lg_solve(hm, to_dev(B), rtol=1e-8, max_iter=300)
+    assert stm == 0
+    Xm = Xm.cpu().numpy()
+    for c in (0, 3):
+        xo, sto, ito, relo, _ = ho.solve(B[:, c], 1e-8, 300)
+        d64 = dense_laplacian_norm(g, X[:, c] - xo) / dense_laplacian_norm(g, xo)
+        dmx = dense_laplacian_norm(g, Xm[:, c] - xo) / dense_laplacian_norm(g, xo)
+        say(f"  shift {shift} column {c}: fp64 iters {info[c]['iters']} mixed {infm[c]['iters']} "
+            f"oracle {ito}; energy differences {d64:.1e} / {dmx:.1e}")
+        assert abs(info[c]["iters"] - ito) <= 1 and d64 <= 1e-6
+        assert infm[c]["rel_residual"] <= 1e-8 and dmx <= 1e-5
