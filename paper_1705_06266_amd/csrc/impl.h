@@ -108,9 +108,34 @@ constexpr int kDotPartials = 2048;  // most workgroups of a column-dot launch
 // scalar slots (each K wide) of lg_hierarchy::scal
 enum {
   S_BN = 0, S_RZ, S_PQ, S_ALPHA, S_BETA, S_RR, S_PR, S_ZQ, S_ACTIVE, S_MEAN, S_TMP, S_TR,
-  S_ZSUM, S_ZY, S_YSUM, S_RESTART,
+  S_ZSUM, S_ZY, S_YSUM, S_RESTART, S_FILL,
   S_COUNT = 32
 };
+
+// Continuous batching (the solve server): a batched solve whose columns are
+// slots.  At each CG iteration boundary the columns that finished are written
+// to their destinations and their slots are refilled with queued right-hand
+// sides; every column runs its own CG (own iteration count, restarts and
+// convergence test), so a column's arithmetic does not depend on what the
+// other slots hold.
+struct SlotFeed {
+  struct Col {
+    int slot;
+    const double* B;  // right-hand side: B[i * ldb], i < n (device)
+    int ldb;
+    double* X;        // its solution goes to X[i * ldx] (device)
+    int ldx;
+  };
+  // Columns to load into some of the free slots (at most one per slot).
+  virtual void refill(const std::vector<int>& free_slots, std::vector<Col>& out) = 0;
+  // The slot's column finished; its solution is in place (stream synchronised).
+  virtual void finished(int slot, const lg_rhs_info& info) = 0;
+  virtual ~SlotFeed() = default;
+};
+// Runs until every slot is empty and refill offers nothing.  K: the width
+// (a power of two, at most the hierarchy's).
+lg_status solve_slots(lg_hierarchy* h, int K, double rtol, int max_iter, hipStream_t st,
+                      SlotFeed* feed);
 
 void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st);
 void alloc_solve_workspace(lg_hierarchy* h, hipStream_t st);

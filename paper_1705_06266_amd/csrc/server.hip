@@ -1,14 +1,16 @@
 // server.hip -- continuous-batching solve server over a pool of graphs.
 //
-// Requests (graph, right-hand sides, tolerance) arrive at any time.  Worker
-// threads, each with its own HIP stream, take the oldest request whose graph
-// is idle together with every other queued request for that graph (same
-// tolerance and iteration cap, up to max_batch_rhs columns) and solve them as
-// one batched lg_solve, so requests that arrive while others run join the
-// next batch of their graph and different graphs overlap on the device.
-// Hierarchies are built on a graph's first request and stay resident; a
-// graph is admitted when its hierarchy fits the HBM budget after evicting
-// the least recently used idle ones (one that cannot fit runs alone).
+// Requests (graph, right-hand sides, tolerance) arrive at any time.  A worker
+// thread (each with its own HIP stream) opens a session on the graph of the
+// oldest waiting request: one batched CG whose columns are slots.  At every CG
+// iteration boundary the columns that have converged leave (their request
+// completes once all its columns have), and the freed slots take the next
+// queued requests for the same graph, tolerance and iteration cap, so requests
+// are admitted as slots free up instead of waiting for a whole batch; sessions
+// on different graphs overlap on the device.  Hierarchies are built on a
+// graph's first request and stay resident; a graph is admitted when its
+// hierarchy fits the HBM budget after evicting the least recently used idle
+// ones (one that cannot fit runs alone).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,22 +27,6 @@
 #include "impl.h"
 
 namespace {
-
-__global__ void k_pack_cols(const double* __restrict__ src, int64_t n, int k,
-                            double* __restrict__ dst, int K, int off) {
-  const int64_t i = (int64_t)blockIdx.x * lg::kBlock + threadIdx.x;
-  if (i >= n * k) return;
-  const int64_t row = i / k;
-  dst[row * K + off + (i - row * k)] = src[i];
-}
-
-__global__ void k_unpack_cols(const double* __restrict__ src, int64_t n, int K, int off,
-                              double* __restrict__ dst, int k) {
-  const int64_t i = (int64_t)blockIdx.x * lg::kBlock + threadIdx.x;
-  if (i >= n * k) return;
-  const int64_t row = i / k;
-  dst[i] = src[row * K + off + (i - row * k)];
-}
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(
@@ -71,6 +57,7 @@ struct Request {
   double rtol = 0.0;
   int max_iter = 0;
   double t_submit = 0.0, t_done = 0.0;
+  int cols_left = 0;  // columns still in a session's slots
   bool done = false;
   lg_status status = LG_OK;
   std::string error;
@@ -102,6 +89,7 @@ struct lg_server {
   size_t resident = 0;  // built hierarchies
   size_t reserved = 0;  // hierarchies being built (admission estimates)
   lg_server_stats st{};
+  int idle_workers = 0;  // workers waiting for work
   std::vector<std::thread> workers;
 
   bool pickable() const {
@@ -146,165 +134,198 @@ struct lg_server {
     return false;
   }
 
-  void finish(std::vector<Request*>& batch, GraphEntry& G) {
-    const double t = now_ms();
-    for (Request* r : batch) {
-      r->t_done = t;
-      r->done = true;
+  // Does request r (for a running session on gid) go ahead of every waiting
+  // request of another graph that no worker is free to take?  Keeps one
+  // graph's stream of requests from starving the others.  Caller holds mu.
+  bool may_join(const Request* r) const {
+    if (idle_workers > 0) return true;
+    for (const Request* q : pending) {
+      if (q == r) return true;
+      if (q->gid != r->gid && !graphs[q->gid]->busy) return false;
     }
-    G.busy = false;
-    G.last_use = ++clock;
-    st.completed += (int64_t)batch.size();
-    cv_done.notify_all();
-    cv_work.notify_all();
+    return true;
   }
+
+  struct Session;  // the slot feed of one worker's batched solve
 
   void worker() {
     (void)hipSetDevice(device);
     hipStream_t strm = nullptr;
     if (hipStreamCreateWithFlags(&strm, hipStreamNonBlocking) != hipSuccess) strm = nullptr;
-    double* stage = nullptr;  // n x K batch input and output
-    size_t stage_rows = 0;
-    std::vector<lg_rhs_info> info;
     for (;;) {
-      std::vector<Request*> batch;
+      std::vector<Request*> first;
       GraphEntry* G = nullptr;
       int32_t gid = -1;
+      int width = 1;
       {
         std::unique_lock<std::mutex> lk(mu);
+        idle_workers++;
         cv_work.wait(lk, [&] { return (stop && pending.empty()) || pickable(); });
-        if (stop && pending.empty()) break;
+        if (stop && pending.empty()) {
+          idle_workers--;
+          break;
+        }
         // the oldest request whose graph is idle and resident, or admissible
-        Request* first = nullptr;
+        Request* head = nullptr;
         for (Request* r : pending) {
           GraphEntry* e = graphs[r->gid].get();
           if (e->busy) continue;
           if (e->h || e->failed != LG_OK || admit(r->gid)) {
-            first = r;
+            head = r;
             break;
           }
         }
-        if (!first) {  // every candidate waits for memory held by running batches
+        if (!head) {  // every candidate waits for memory held by running sessions
+          idle_workers--;
           cv_done.wait_for(lk, std::chrono::milliseconds(5));
           continue;
         }
-        gid = first->gid;
+        idle_workers--;
+        gid = head->gid;
         G = graphs[gid].get();
         G->busy = true;
+        // session width: the columns queued for this graph now (at least the
+        // head request's), rounded up to a power of two
         int cols = 0;
-        for (auto it = pending.begin(); it != pending.end();) {
-          Request* r = *it;
-          if (r->gid == gid && r->rtol == first->rtol && r->max_iter == first->max_iter &&
-              cols + r->k <= opts.max_batch_rhs) {
-            batch.push_back(r);
-            cols += r->k;
-            it = pending.erase(it);
-          } else {
-            ++it;
-          }
-        }
+        for (Request* r : pending)
+          if (r->gid == gid && r->rtol == head->rtol && r->max_iter == head->max_iter) cols += r->k;
+        cols = std::min(std::max(cols, head->k), opts.max_batch_rhs);
+        while (width < cols) width <<= 1;
+        first.push_back(head);
+        pending.erase(std::find(pending.begin(), pending.end(), head));
       }
-      run_batch(*G, gid, batch, strm, stage, stage_rows, info);
+      run_session(*G, gid, first, width, strm);
       std::lock_guard<std::mutex> lk(mu);
-      finish(batch, *G);
+      G->busy = false;
+      G->last_use = ++clock;
+      cv_work.notify_all();
     }
-    if (stage) (void)hipFree(stage);
     if (strm) (void)hipStreamDestroy(strm);
   }
 
-  void fail_batch(std::vector<Request*>& batch, lg_status s, const std::string& msg) {
-    for (Request* r : batch) {
-      r->status = s;
-      r->error = msg;
+  void complete(Request* r) {  // caller holds mu
+    r->t_done = now_ms();
+    r->done = true;
+    st.completed++;
+    cv_done.notify_all();
+  }
+
+  void fail_request(Request* r, lg_status s, const std::string& msg) {  // caller holds mu
+    r->status = s;
+    r->error = msg;
+    r->info.assign(r->k, lg_rhs_info{});
+    complete(r);
+  }
+
+  // Builds the hierarchy if needed, then one slot-batched solve that keeps
+  // taking this graph's requests while it runs.
+  void run_session(GraphEntry& G, int32_t gid, std::vector<Request*>& first, int width,
+                   hipStream_t strm);
+};
+
+struct lg_server::Session : lg::SlotFeed {
+  lg_server* s;
+  int32_t gid;
+  double rtol;
+  int max_iter;
+  std::vector<Request*> initial;
+  std::vector<std::pair<Request*, int>> slot_col;  // request and column in each slot
+  int64_t columns = 0;
+
+  void refill(const std::vector<int>& free_slots, std::vector<Col>& out) override {
+    std::lock_guard<std::mutex> lk(s->mu);
+    size_t next = 0;
+    auto place = [&](Request* r) {
+      r->cols_left = r->k;
+      r->info.assign(r->k, lg_rhs_info{});
+      r->status = LG_OK;
+      for (int j = 0; j < r->k; j++) {
+        const int slot = free_slots[next++];
+        slot_col[slot] = {r, j};
+        out.push_back(Col{slot, r->B + j, r->k, r->X + j, r->k});
+      }
+      columns += r->k;
+    };
+    const bool opening = !initial.empty();
+    for (Request* r : initial) place(r);  // the session's first requests
+    initial.clear();
+    if (s->stop && s->pending.empty()) return;
+    for (auto it = s->pending.begin(); it != s->pending.end();) {
+      Request* r = *it;
+      if (r->gid == gid && r->rtol == rtol && r->max_iter == max_iter &&
+          (size_t)r->k <= free_slots.size() - next && s->may_join(r)) {
+        it = s->pending.erase(it);
+        place(r);
+        if (!opening) s->st.refills += r->k;
+      } else {
+        ++it;
+      }
     }
   }
 
-  // Builds the hierarchy if needed, then one batched solve.  Runs without mu
-  // except for the bookkeeping of resident bytes.
-  void run_batch(GraphEntry& G, int32_t gid, std::vector<Request*>& batch, hipStream_t strm,
-                 double*& stage, size_t& stage_rows, std::vector<lg_rhs_info>& info) {
-    if (G.failed != LG_OK) {
-      fail_batch(batch, G.failed, G.error);
-      return;
-    }
-    if (!G.h) {
-      lg_graph g{G.n, G.nnz, G.rp.data(), G.col.data(), G.w.data(), 0};
-      lg_setup_opts o = opts.setup;
-      o.max_rhs = opts.max_batch_rhs;
-      lg_hierarchy* h = nullptr;
-      const lg_status s = lg_setup(&g, &o, strm, &h);
-      std::lock_guard<std::mutex> lk(mu);
-      reserved -= G.reserved;
-      G.reserved = 0;
-      if (s != LG_OK) {
-        G.failed = s;
-        G.error = lg_last_error();
-        fail_batch(batch, s, G.error);
-        return;
-      }
+  void finished(int slot, const lg_rhs_info& info) override {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto [r, j] = slot_col[slot];
+    slot_col[slot] = {nullptr, 0};
+    r->info[j] = info;
+    if (!(info.rel_residual <= rtol)) r->status = LG_E_NOT_CONVERGED;
+    if (--r->cols_left == 0) s->complete(r);
+  }
+};
+
+void lg_server::run_session(GraphEntry& G, int32_t gid, std::vector<Request*>& first, int width,
+                            hipStream_t strm) {
+  if (G.failed == LG_OK && !G.h) {
+    lg_graph g{G.n, G.nnz, G.rp.data(), G.col.data(), G.w.data(), 0};
+    lg_setup_opts o = opts.setup;
+    o.max_rhs = opts.max_batch_rhs;
+    lg_hierarchy* h = nullptr;
+    const lg_status s = lg_setup(&g, &o, strm, &h);
+    std::lock_guard<std::mutex> lk(mu);
+    reserved -= G.reserved;
+    G.reserved = 0;
+    if (s != LG_OK) {
+      G.failed = s;
+      G.error = lg_last_error();
+    } else {
       G.h = h;
       G.bytes = lg_hierarchy_bytes(h);
       resident += G.bytes;
       st.setups++;
     }
-    int cols = 0;
-    for (Request* r : batch) cols += r->k;
-    const double* B = batch[0]->B;
-    double* X = batch[0]->X;
-    const int64_t n = G.n;
-    if (batch.size() > 1) {
-      if (stage_rows < (size_t)n) {
-        if (stage) (void)hipFree(stage);
-        stage = nullptr;
-        stage_rows = 0;
-        if (hipMalloc((void**)&stage, sizeof(double) * (size_t)n * opts.max_batch_rhs * 2) !=
-            hipSuccess) {
-          stage = nullptr;
-          fail_batch(batch, LG_E_NOMEM, "server: staging allocation failed");
-          return;
-        }
-        stage_rows = (size_t)n;
-      }
-      double* Bs = stage;
-      double* Xs = stage + (size_t)n * opts.max_batch_rhs;
-      int off = 0;
-      for (Request* r : batch) {
-        const unsigned blocks = (unsigned)lg::ceil_div(n * r->k, (int64_t)lg::kBlock);
-        hipLaunchKernelGGL(k_pack_cols, dim3(blocks), dim3(lg::kBlock), 0, strm, r->B, n, r->k, Bs,
-                           cols, off);
-        off += r->k;
-      }
-      B = Bs;
-      X = Xs;
-    }
-    info.assign(cols, lg_rhs_info{});
-    const lg_status s = lg_solve(G.h, B, X, cols, batch[0]->rtol, batch[0]->max_iter, strm,
-                                 info.data());
-    std::string msg = s == LG_OK || s == LG_E_NOT_CONVERGED ? "" : lg_last_error();
-    if (s != LG_OK && s != LG_E_NOT_CONVERGED) {
-      fail_batch(batch, s, msg);
-      return;
-    }
-    int off = 0;
-    for (Request* r : batch) {
-      if (batch.size() > 1) {
-        const unsigned blocks = (unsigned)lg::ceil_div(n * r->k, (int64_t)lg::kBlock);
-        hipLaunchKernelGGL(k_unpack_cols, dim3(blocks), dim3(lg::kBlock), 0, strm, X, n, cols, off,
-                           r->X, r->k);
-      }
-      r->info.assign(info.begin() + off, info.begin() + off + r->k);
-      r->status = LG_OK;
-      for (const lg_rhs_info& c : r->info)
-        if (!(c.rel_residual <= r->rtol)) r->status = LG_E_NOT_CONVERGED;
-      off += r->k;
-    }
-    if (hipStreamSynchronize(strm) != hipSuccess) fail_batch(batch, LG_E_HIP, "server: stream error");
-    std::lock_guard<std::mutex> lk(mu);
-    st.batches++;
-    st.batched_columns += cols;
-    (void)gid;
   }
-};
+  if (G.failed != LG_OK) {
+    std::lock_guard<std::mutex> lk(mu);
+    for (Request* r : first) fail_request(r, G.failed, G.error);
+    return;
+  }
+  Session sess;
+  sess.s = this;
+  sess.gid = gid;
+  sess.rtol = first[0]->rtol;
+  sess.max_iter = first[0]->max_iter;
+  sess.initial = first;
+  sess.slot_col.assign(width, {nullptr, 0});
+  lg_status status = LG_OK;
+  std::string msg;
+  try {
+    status = lg::solve_slots(G.h, width, sess.rtol, sess.max_iter, strm, &sess);
+  } catch (const lg::Error& e) {
+    status = e.code;
+    msg = e.msg;
+  } catch (...) {
+    status = LG_E_HIP;
+    msg = "server: unexpected error in a session";
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if (status != LG_OK) {  // requests still in slots or never placed fail
+    for (auto& [r, j] : sess.slot_col)
+      if (r && !r->done) fail_request(r, status, msg);
+    for (Request* r : sess.initial) fail_request(r, status, msg);
+  }
+  st.batches++;
+  st.batched_columns += sess.columns;
+}
 
 namespace {
 lg_status server_arg_error(const char* msg) {

@@ -609,6 +609,43 @@ __global__ void k_xpby_z(double* __restrict__ p, const T* __restrict__ z,
   }
 }
 
+// Slot mode: column `slot` of the n x K multi-vector b takes B[i * ldb].
+template <int K>
+__global__ void k_load_col(double* __restrict__ b, int slot, const double* __restrict__ B, int ldb,
+                           int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) b[i * K + slot] = B[i * ldb];
+}
+
+// v -= its column mean in the flagged columns only.
+template <int K>
+__global__ void k_sub_mean_flagged(double* __restrict__ v, const double* __restrict__ sums,
+                                   const double* __restrict__ flag, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n * K && flag[i % K] > 0.0) v[i] -= sums[i % K] / (double)n;
+}
+
+// Slot mode, a refilled column: x = 0 and t = b (the restart then takes r = t).
+template <int K>
+__global__ void k_refill_cols(double* __restrict__ x, double* __restrict__ t,
+                              const double* __restrict__ b, const double* __restrict__ flag,
+                              int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < m && flag[i % K] > 0.0) {
+    x[i] = 0.0;
+    t[i] = b[i];
+  }
+}
+
+// Slot mode, a finished column: X[i * ldx] = x_i - mean(x) (the same
+// arithmetic as the projection at the end of a plain solve).
+template <int K>
+__global__ void k_store_col(const double* __restrict__ x, int slot, const double* __restrict__ sums,
+                            int64_t n, double* __restrict__ X, int ldx) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) X[i * ldx] = x[i * K + slot] - sums[slot] / (double)n;
+}
+
 // dst = src in the columns whose flag is set (columns never influence each other)
 template <int K>
 __global__ void k_copy_flagged(double* __restrict__ dst, const double* __restrict__ src,
@@ -969,9 +1006,13 @@ static double cycle_work(const lg_hierarchy* h, int l) {
   return w;
 }
 
+// CG preconditioned by the cycle (flexible CG with the K-cycle) on K columns
+// at once.  Plain mode: the k columns of B, X filled at the end.  Slot mode
+// (feed set, B and X unused): columns enter from the feed and leave to it at
+// iteration boundaries, each with its own iteration cap.
 template <typename T, int K>
 lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, int max_iter,
-              hipStream_t st, lg_rhs_info* info) {
+              hipStream_t st, lg_rhs_info* info, SlotFeed* feed = nullptr) {
   Engine<T, K> eng{h, st};
   const Level& L0 = h->lev[0];
   const int64_t n = L0.n;
@@ -1032,31 +1073,109 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
   std::vector<double> bn(K, 0.0), relres(K, 0.0), work(K, 0.0), active(K, 0.0), zero(K, 0.0);
   std::vector<int> iters(K, 0);
   std::vector<int> converged(K, 0);
+  std::vector<SlotFeed::Col> dst(K);  // slot mode: where each slot's solution goes
 
-  hipLaunchKernelGGL(k_fill<double>, dim3(nblk(S_COUNT * K)), dim3(kBlock), 0, st, sc,
-                     (int64_t)S_COUNT * K, 0.0);
-  hipLaunchKernelGGL(k_pad_in, dim3(g), dim3(kBlock), 0, st, B, k, h->pb, K, n);
-  project64(h->pb);
-  dot64(h->pb, h->pb, S_BN);
-  read_scal();
-  for (int c = 0; c < K; c++) {
-    bn[c] = std::sqrt(hs[S_BN * K + c]);
-    active[c] = (c < k && bn[c] > 0.0) ? 1.0 : 0.0;
-    converged[c] = active[c] == 0.0;
-  }
-  write_slot(S_ACTIVE, active);
-  hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(kBlock), 0, st, h->px, m, 0.0);
-  LG_HIP(hipMemcpyAsync(h->pr, h->pb, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+  auto fill_flags = [&](const std::vector<SlotFeed::Col>& in) {
+    std::vector<double> f(K, 0.0);
+    for (const SlotFeed::Col& c : in) f[c.slot] = 1.0;
+    return f;
+  };
+  // slot mode: load the offered columns into free slots (b projected to mean
+  // zero, x = 0, t = b); returns the refill flags (all zero if none)
+  auto load_cols = [&](const std::vector<int>& free_slots) {
+    std::vector<SlotFeed::Col> in;
+    if (!free_slots.empty()) feed->refill(free_slots, in);
+    std::vector<double> f = fill_flags(in);
+    if (in.empty()) return f;
+    for (const SlotFeed::Col& c : in) {
+      dst[c.slot] = c;
+      hipLaunchKernelGGL((k_load_col<K>), dim3(nblk(n)), dim3(kBlock), 0, st, h->pb, c.slot, c.B,
+                         c.ldb, n);
+    }
+    write_slot(S_FILL, f);
+    hipLaunchKernelGGL((k_dots<double, K, 1>), dim3(nb), dim3(kBlock), 0, st, h->pb,
+                       (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, m,
+                       h->red);
+    final1(S_TMP);
+    hipLaunchKernelGGL((k_sub_mean_flagged<K>), dim3(g), dim3(kBlock), 0, st, h->pb,
+                       (const double*)sl(S_TMP), (const double*)sl(S_FILL), n);
+    dot64(h->pb, h->pb, S_BN);
+    hipLaunchKernelGGL((k_refill_cols<K>), dim3(g), dim3(kBlock), 0, st, h->px, h->pt,
+                       (const double*)h->pb, (const double*)sl(S_FILL), m);
+    read_scal();
+    for (const SlotFeed::Col& c : in) {
+      const int j = c.slot;
+      bn[j] = std::sqrt(hs[S_BN * K + j]);
+      iters[j] = 0;
+      work[j] = 0.0;
+      relres[j] = 0.0;
+      converged[j] = 0;
+      active[j] = bn[j] > 0.0 ? 1.0 : 0.0;
+    }
+    return f;
+  };
+  // slot mode: the finished columns' solutions (projected) to their destinations
+  auto store_cols = [&](const std::vector<int>& done) {
+    if (done.empty()) return;
+    hipLaunchKernelGGL((k_dots<double, K, 1>), dim3(nb), dim3(kBlock), 0, st, h->px,
+                       (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, m,
+                       h->red);
+    final1(S_TMP);
+    for (int c : done)
+      hipLaunchKernelGGL((k_store_col<K>), dim3(nblk(n)), dim3(kBlock), 0, st, (const double*)h->px,
+                         c, (const double*)sl(S_TMP), n, dst[c].X, dst[c].ldx);
+    LG_LAUNCH_CHECK();
+    LG_HIP(hipStreamSynchronize(st));
+    for (int c : done) {
+      lg_rhs_info ci{};
+      ci.iters = iters[c];
+      ci.rel_residual = relres[c];
+      ci.work_units = work[c];
+      ci.wda = (relres[c] > 0.0 && relres[c] < 1.0) ? -work[c] / std::log10(relres[c]) : 0.0;
+      feed->finished(c, ci);
+    }
+  };
   auto any_active = [&]() {
     for (int c = 0; c < K; c++)
       if (active[c] > 0.0) return true;
     return false;
   };
+
+  hipLaunchKernelGGL(k_fill<double>, dim3(nblk(S_COUNT * K)), dim3(kBlock), 0, st, sc,
+                     (int64_t)S_COUNT * K, 0.0);
+  if (feed) {  // empty slots hold zero vectors
+    hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(kBlock), 0, st, h->pb, m, 0.0);
+    hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(kBlock), 0, st, h->px, m, 0.0);
+    hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(kBlock), 0, st, h->pt, m, 0.0);
+    std::vector<int> all(K);
+    for (int c = 0; c < K; c++) all[c] = c;
+    load_cols(all);
+    // empty slots (zero right-hand side) finish at once
+    std::vector<int> done;
+    for (int c = 0; c < K; c++)
+      if (dst[c].X && active[c] == 0.0) done.push_back(c);
+    store_cols(done);
+    for (int c : done) dst[c] = SlotFeed::Col{};
+    LG_HIP(hipMemcpyAsync(h->pr, h->pt, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+  } else {
+    hipLaunchKernelGGL(k_pad_in, dim3(g), dim3(kBlock), 0, st, B, k, h->pb, K, n);
+    project64(h->pb);
+    dot64(h->pb, h->pb, S_BN);
+    read_scal();
+    for (int c = 0; c < K; c++) {
+      bn[c] = std::sqrt(hs[S_BN * K + c]);
+      active[c] = (c < k && bn[c] > 0.0) ? 1.0 : 0.0;
+      converged[c] = active[c] == 0.0;
+    }
+    hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(kBlock), 0, st, h->px, m, 0.0);
+    LG_HIP(hipMemcpyAsync(h->pr, h->pb, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+  }
+  write_slot(S_ACTIVE, active);
   if (any_active()) {
     new_direction(eng.precond(h->pr, false), true, nullptr);
     for (int c = 0; c < K; c++) work[c] += active[c] > 0.0 ? cw : 0.0;
   }
-  for (int it = 1; it <= max_iter && any_active(); it++) {
+  for (int it = 1; (feed || it <= max_iter) && any_active(); it++) {
     lap64<K>(h, 0, h->pp, h->pq, nullptr, st, "spmv");
     if (flex) dot64x2(h->pp, h->pq, h->pp, h->pr, S_PQ, S_PR);
     else dot64(h->pp, h->pq, S_PQ);
@@ -1066,16 +1185,22 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
                        mixed ? (T*)h->cyc_in : (T*)nullptr, h->red);
     final1(S_RR);
     read_scal();
-    std::vector<int> newly;
+    std::vector<int> newly, done;
+    std::vector<int> capped(K, 0);
     for (int c = 0; c < K; c++) {
       if (active[c] == 0.0) continue;
-      iters[c] = it;
+      iters[c]++;
       work[c] += 1.0;
       if (hs[S_ACTIVE * K + c] == 0.0) {  // breakdown flagged on the device
         active[c] = 0.0;
+        if (feed) {  // slot mode: the column finishes with its true residual
+          capped[c] = 1;
+          newly.push_back(c);
+        }
         continue;
       }
-      if (std::sqrt(hs[S_RR * K + c]) / bn[c] <= rtol) newly.push_back(c);
+      capped[c] = feed && iters[c] >= max_iter;
+      if (std::sqrt(hs[S_RR * K + c]) / bn[c] <= rtol || capped[c]) newly.push_back(c);
     }
     bool restart = false;
     std::vector<double> rflag(K, 0.0);
@@ -1086,10 +1211,11 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
       for (int c : newly) {
         work[c] += 1.0;
         const double rel = std::sqrt(hs[S_TR * K + c]) / bn[c];
-        if (rel <= rtol) {
+        if (rel <= rtol || capped[c]) {
           active[c] = 0.0;
-          converged[c] = 1;
+          converged[c] = rel <= rtol;
           relres[c] = rel;
+          if (feed) done.push_back(c);
         } else {
           restart = true;
           rflag[c] = 1.0;
@@ -1097,6 +1223,28 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
       }
       write_slot(S_ACTIVE, active);
       write_slot(S_TR, zero);
+    }
+    if (feed) {  // hand finished columns back, refill their slots
+      std::sort(done.begin(), done.end());
+      store_cols(done);
+      std::vector<int> free_slots;
+      for (int c = 0; c < K; c++)
+        if (active[c] == 0.0) free_slots.push_back(c);
+      for (int c : done) dst[c] = SlotFeed::Col{};
+      std::vector<double> f = load_cols(free_slots);
+      bool any_fill = false;
+      for (int c = 0; c < K; c++)
+        if (f[c] > 0.0 && active[c] > 0.0) {
+          rflag[c] = 1.0;
+          any_fill = true;
+        } else if (f[c] > 0.0) {  // a zero right-hand side: done at once
+          store_cols({c});
+          dst[c] = SlotFeed::Col{};
+        }
+      if (any_fill) {
+        restart = true;
+        write_slot(S_ACTIVE, active);
+      }
     }
     if (!any_active()) break;
     if (restart) {  // those columns continue from the true residual with a fresh direction
@@ -1108,6 +1256,19 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     for (int c = 0; c < K; c++) work[c] += active[c] > 0.0 ? cw : 0.0;
     new_direction(z, false, restart ? (const double*)sl(S_RESTART) : nullptr);
     LG_LAUNCH_CHECK();
+  }
+  if (feed) {
+    std::vector<int> left;  // only after a breakdown ended the loop early
+    for (int c = 0; c < K; c++)
+      if (dst[c].X) left.push_back(c);
+    if (!left.empty()) {
+      lap64<K>(h, 0, h->px, h->pt, h->pb, st, "resid64");
+      dot64(h->pt, h->pt, S_TR);
+      read_scal();
+      for (int c : left) relres[c] = bn[c] > 0.0 ? std::sqrt(hs[S_TR * K + c]) / bn[c] : 0.0;
+      store_cols(left);
+    }
+    return LG_OK;
   }
   lg_status status = LG_OK;
   bool need_true = false;
@@ -1174,6 +1335,26 @@ static lg_status solve_k(lg_hierarchy* h, const double* B, double* X, int k, dou
     case 16: return pcg<T, 16>(h, B, X, k, rtol, max_iter, st, info);
     default: return pcg<T, 32>(h, B, X, k, rtol, max_iter, st, info);
   }
+}
+
+template <typename T>
+static lg_status slots_k(lg_hierarchy* h, int K, double rtol, int max_iter, hipStream_t st,
+                         SlotFeed* feed) {
+  switch (K) {
+    case 1: return pcg<T, 1>(h, nullptr, nullptr, 0, rtol, max_iter, st, nullptr, feed);
+    case 2: return pcg<T, 2>(h, nullptr, nullptr, 0, rtol, max_iter, st, nullptr, feed);
+    case 4: return pcg<T, 4>(h, nullptr, nullptr, 0, rtol, max_iter, st, nullptr, feed);
+    case 8: return pcg<T, 8>(h, nullptr, nullptr, 0, rtol, max_iter, st, nullptr, feed);
+    case 16: return pcg<T, 16>(h, nullptr, nullptr, 0, rtol, max_iter, st, nullptr, feed);
+    default: return pcg<T, 32>(h, nullptr, nullptr, 0, rtol, max_iter, st, nullptr, feed);
+  }
+}
+
+lg_status solve_slots(lg_hierarchy* h, int K, double rtol, int max_iter, hipStream_t st,
+                      SlotFeed* feed) {
+  if (K < 1 || K > h->K || (K & (K - 1)) || !feed) fail(LG_E_ARG, "solve_slots: bad width");
+  if (h->opts.precision == LG_MIXED) return slots_k<float>(h, K, rtol, max_iter, st, feed);
+  return slots_k<double>(h, K, rtol, max_iter, st, feed);
 }
 
 lg_status solve_dispatch(lg_hierarchy* h, const double* B, double* X, int k, double rtol,

@@ -1,15 +1,19 @@
 """The continuous-batching solve server (lg_server_*): every request's result
-is the same alone and in the mix (within the solver's stated tolerance; bit
-for bit at equal batch width), hierarchies are admitted by the HBM budget, and
-a bad graph fails only its own requests.  All calls go through the C ABI.
+is the same alone and in the mix and agrees with the CPU oracle (within the
+solver's stated tolerance; bit for bit at equal batch width), requests join a
+running session as slots free up, hierarchies are admitted by the HBM budget,
+and a bad graph fails only its own requests.  All calls go through the C ABI.
 """
+
+import time
 
 import numpy as np
 import pytest
 
 import graphgen as gg
+import oracle
 import paper_1705_06266_amd.lgmg as lg
-from gpu_util import dense_laplacian_norm, laplacian_apply, say, to_dev
+from gpu_util import dense_laplacian_norm, laplacian_apply, oracle_opts, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -45,6 +49,17 @@ def _same_within_tolerance(g, b, X, infos, Xa, infa):
         assert abs(infos[c]["iters"] - infa[c]["iters"]) <= 1
 
 
+def _matches_oracle(g, ho, b, X, infos):
+    """Each column against the oracle's FP64 solve of the same right-hand side:
+    energy-norm difference <= 1e-6, iteration counts within one."""
+    for c in range(b.shape[1]):
+        xo, sto, ito, relo, _ = ho.solve(b[:, c], 1e-8, 500)
+        assert sto == 0
+        diff = dense_laplacian_norm(g, X[:, c] - xo) / dense_laplacian_norm(g, xo)
+        assert diff <= 1e-6, (c, diff)
+        assert abs(infos[c]["iters"] - ito) <= 1, (c, infos[c]["iters"], ito)
+
+
 def _alone(graphs, max_batch_rhs):
     """One hierarchy per graph built like the server's (max_rhs = max_batch_rhs)."""
     return [lg.lg_setup(g.row_ptr, g.col, g.w, lg.lg_default_opts(max_rhs=max_batch_rhs))
@@ -75,10 +90,46 @@ def test_results_are_the_same_alone_and_in_the_mix(graphs):
     assert st["completed"] == len(reqs) and st["setups"] == len(graphs)
     assert st["batches"] < len(reqs), "requests on one graph should share batches"
     alone = _alone(graphs, 32)
+    ho = [oracle.Hierarchy(g, oracle_opts(lg.lg_default_opts())) for g in graphs]
     for (gid, b), (X, infos, status, lat) in zip(reqs, results):
         Xa, infa, sta = lg.lg_solve(alone[gid], to_dev(b))
         assert status == lg.LG_OK and sta == lg.LG_OK and lat > 0.0
         _same_within_tolerance(graphs[gid], b, X.cpu().numpy(), infos, Xa.cpu().numpy(), infa)
+        _matches_oracle(graphs[gid], ho[gid], b, X.cpu().numpy(), infos)
+
+
+def test_requests_join_a_running_session(graphs):
+    """Slot-level admission: with one worker, requests on a graph submitted
+    while a session on it runs enter that session's free slots at an iteration
+    boundary (no new session), and every result matches the oracle."""
+    import torch
+
+    g = gg.grid3d(16, 16, 16, weights="loguniform", seed=12)  # a few hundred CG iterations
+    srv = lg.Server(workers=1, max_batch_rhs=8)
+    gid = srv.add_graph(g.row_ptr, g.col, g.w)
+    warm = to_dev(gg.rhs(g.n, 1, 40))
+    torch.cuda.synchronize()
+    srv.wait(srv.submit(gid, warm))  # builds the hierarchy
+    before = srv.stats()
+    first = gg.rhs(g.n, 5, 41)  # a session of width 8: three idle slots
+    later = [gg.rhs(g.n, 1, 42 + i) for i in range(3)]
+    dev = [to_dev(first)] + [to_dev(b) for b in later]
+    torch.cuda.synchronize()
+    rid = [srv.submit(gid, dev[0])]
+    time.sleep(0.005)
+    for B in dev[1:]:
+        rid.append(srv.submit(gid, B))
+        time.sleep(0.002)
+    results = [srv.wait(r) for r in rid]
+    after = srv.stats()
+    srv.close()
+    say(f"  stats before {before} after {after}")
+    assert after["batches"] - before["batches"] == 1, "later requests should join the session"
+    assert after["refills"] - before["refills"] == 3
+    ho = oracle.Hierarchy(g, oracle_opts(lg.lg_default_opts()))
+    for b, (X, infos, status, lat) in zip([first] + later, results):
+        assert status == lg.LG_OK
+        _matches_oracle(g, ho, b, X.cpu().numpy(), infos)
 
 
 def test_admission_by_budget_evicts_idle_hierarchies(graphs):
