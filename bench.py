@@ -4,13 +4,18 @@ One step = one pass of the whole path over one batch of input already in HBM:
 setup (validation, elimination, strength of connection, voting aggregation,
 Galerkin products, Lanczos, coarsest pseudo-inverse) followed by the solve of
 the batch's right-hand sides to a 1e-8 relative residual.  The default
-workload is the R-MAT scale-18 graph (edge factor 16, largest component,
-U(0,1] weights) with one Gaussian right-hand side in FP64.
+workload is the largest single-GPU configuration: the 4M-vertex Chung-Lu
+power-law graph (gamma 2.1, mean degree 16, largest degree 1e5, largest
+component, U(0,1] weights) with 16 Gaussian right-hand sides, solved in FP64;
+the mixed form (FP32 hierarchy values and cycle inside FP64 CG) is timed
+beside it on the same inputs, both to the same final residual.
 
 Prints one JSON line.  Besides the headline value it reports the solve-only
 latency distribution on a resident hierarchy, the fp64 SpMV bandwidth of the
-finest level, the dominant kernel against the HBM roofline (HIP events around
-its launches inside the timed region) and the CPU oracle on a bounded sample.
+finest level, the kernel with the largest share of the step's GPU time against
+the HBM roofline (HIP events around its launches inside the timed region), the
+true residual recomputed on the host after the timed steps, and the CPU oracle
+on a bounded sample.
 """
 
 from __future__ import annotations
@@ -35,14 +40,23 @@ KERNEL_SOURCES = ["paper_1705_06266_amd/csrc/common.h", "paper_1705_06266_amd/cs
                   "paper_1705_06266_amd/csrc/solve.hip", "paper_1705_06266_amd/csrc/setup.hip",
                   "paper_1705_06266_amd/csrc/prims.hip"]
 
-# family: the kernel timed for the roofline (one kernel instance per workload);
-# kernel: its symbol as rocprofv3 prints it.
+# family: the profiler families whose launches are the roofline kernel (the
+# kernel instance with the largest share of the step's GPU time in the
+# workload's rocprofv3 summary); kernel: that instance as rocprofv3 prints it;
+# companion: a second workload timed beside this one on the same inputs.
 WORKLOADS = {
+    "chunglu_4m": dict(cfg="chunglu_4m", precision="fp64", k=16,
+                       label="chunglu_4m_g2.1_d16_fp64_16rhs", family="cheb",
+                       kernel="k_rows_col<lg::LapColOp<double, 16, 2, 0> >",
+                       companion="chunglu_4m_mixed"),
+    "chunglu_4m_mixed": dict(cfg="chunglu_4m", precision="mixed", k=16,
+                             label="chunglu_4m_g2.1_d16_mixed_16rhs", family="spmv",
+                             kernel="k_rows_col<lg::LapColOp<double, 16, 0, 0> >"),
     "rmat_s18": dict(cfg="rmat_s18", precision="fp64", k=1,
-                     label="rmat_s18_ef16_lcc_u01_fp64_1rhs", family="spmv",
+                     label="rmat_s18_ef16_lcc_u01_fp64_1rhs", family="spmv,lanczos",
                      kernel="k_rows<lg::LapOp<double, 1, 0, 0> >"),
     "grid2d_64": dict(cfg="grid2d_64", precision="fp64", k=1,
-                      label="grid2d_64x64_unit_fp64_1rhs", family="spmv",
+                      label="grid2d_64x64_unit_fp64_1rhs", family="spmv,lanczos",
                       kernel="k_rows<lg::LapOp<double, 1, 0, 0> >"),
     "grid3d_128_mixed": dict(cfg="grid3d_128_loguniform", precision="mixed", k=32,
                              label="grid3d_128cube_loguniform_mixed_32rhs", family="cheb",
@@ -50,13 +64,13 @@ WORKLOADS = {
     "grid3d_128_fp64": dict(cfg="grid3d_128_loguniform", precision="fp64", k=32,
                             label="grid3d_128cube_loguniform_fp64_32rhs", family="cheb",
                             kernel="k_rows_col<lg::LapColOp<double, 32, 2, 0> >"),
-    "chunglu_4m_mixed": dict(cfg="chunglu_4m", precision="mixed", k=16,
-                             label="chunglu_4m_g2.1_d16_mixed_16rhs", family="cheb",
-                             kernel="k_rows_col<lg::LapColOp<float, 16, 2, 0> >"),
-    "chunglu_4m_fp64": dict(cfg="chunglu_4m", precision="fp64", k=16,
-                            label="chunglu_4m_g2.1_d16_fp64_16rhs", family="cheb",
-                            kernel="k_rows_col<lg::LapColOp<double, 16, 2, 0> >"),
 }
+DEFAULT_WORKLOAD = "chunglu_4m"
+
+
+def _fam_tag(family):
+    """File-name form of a family list."""
+    return family.replace(",", "+")
 
 
 def kernel_source_hash():
@@ -68,7 +82,7 @@ def kernel_source_hash():
 
 
 def pmc_path(family, workload):
-    return os.path.join(PROFILES, f"{family}_{workload}_pmc.txt")
+    return os.path.join(PROFILES, f"{_fam_tag(family)}_{workload}_pmc.txt")
 
 
 def load_traffic(family, workload):
@@ -149,25 +163,98 @@ def stream_roof(dev, elems=128 << 20, reps=8):
     return res
 
 
-def cpu_baseline(g, b, seconds_target=20.0):
-    """The oracle as it stands, single thread, on whole steps of the same
-    workload (setup + one solve), for about `seconds_target` seconds."""
+def host_info():
+    """CPU model (lscpu) and the cores this process may use."""
+    model = None
+    try:
+        import subprocess
+
+        for ln in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if ln.startswith("Model name:"):
+                model = ln.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except Exception:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "nproc": avail, "os_cpu_count": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_baseline(g, B, k, iters, max_sample_iters=30, single_thread_budget_s=25.0):
+    """The oracle as it stands on the same workload: its OpenMP build (row
+    loops on all of the threads OpenMP is given, bit-identical results) times
+    one setup and one right-hand side solved to 1e-8; the oracle has no
+    batching, so a step of k right-hand sides costs setup + k solves.  A solve
+    that needs more than max_sample_iters iterations (the GPU's count, `iters`)
+    is sampled: that many iterations are timed and scaled to the full count.
+    The single-threaded build is timed the same way when the threaded run
+    predicts it fits the budget."""
     import oracle
 
-    oracle.lib()
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        h = oracle.Hierarchy(g, oracle.default_opts())
-        x, st, it, rel, work = h.solve(b[:, 0], 1e-8, 500)
+    cap = min(iters, max_sample_iters)
+
+    def one(threaded):
+        t0 = time.perf_counter()
+        h = oracle.Hierarchy(g, oracle.default_opts(), threaded=threaded)
+        setup_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        x, st, it, rel, work = h.solve(B[:, 0], 1e-8, cap if cap < iters else 500)
+        sampled = st != 0 and cap < iters and it == cap  # stopped at the cap, not converged
+        solve_s = (time.perf_counter() - t0) * (iters / it if sampled else 1.0)
         del h
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds_target or el / steps * (steps + 1) > 2 * seconds_target:
-            break
-    return dict(value=steps / el, unit="solves/s", cores=1, kind="oracle",
-                sample=f"{steps} full step(s) (setup + one solve to 1e-8) of the same "
-                       f"workload, {el:.1f} s single-threaded")
+        return {"threads": oracle.threads(threaded), "setup_s": setup_s, "solve_s_per_rhs": solve_s,
+                "iters_timed": it, "iters_solve": iters if sampled else it,
+                "rel_residual": rel, "status": st,
+                "step_s": setup_s + k * solve_s, "solves_per_s": k / (setup_s + k * solve_s)}
+
+    mt = one(True)
+    print(f"oracle ({mt['threads']} threads): setup {mt['setup_s']:.1f} s, "
+          f"solve {mt['solve_s_per_rhs']:.1f} s per right-hand side", file=sys.stderr, flush=True)
+    st1 = None
+    guess = (mt["setup_s"] + mt["solve_s_per_rhs"]) * min(mt["threads"], 4)
+    if mt["threads"] == 1:
+        st1 = mt
+    elif guess <= single_thread_budget_s:
+        st1 = one(False)
+    solve_txt = (f"one of the {k} right-hand side(s) solved to 1e-8 ({mt['solve_s_per_rhs']:.1f} s, "
+                 f"{mt['iters_solve']} iterations)" if mt["iters_timed"] == mt["iters_solve"] else
+                 f"{mt['iters_timed']} CG iterations of one of the {k} right-hand side(s), scaled to "
+                 f"the {mt['iters_solve']} iterations of a solve to 1e-8 "
+                 f"({mt['solve_s_per_rhs']:.1f} s)")
+    out = dict(value=mt["solves_per_s"], unit="solves/s", cores=mt["threads"], kind="oracle",
+               sample=f"OpenMP oracle on {mt['threads']} threads: one setup ({mt['setup_s']:.1f} s) "
+                      f"and {solve_txt}; value = {k} / (setup + {k} x solve)",
+               setup_s=mt["setup_s"], solve_s_per_rhs=mt["solve_s_per_rhs"],
+               iters=mt["iters_solve"], single_thread=st1, host=host_info())
+    if st1 is None:
+        out["single_thread"] = "not timed: predicted above the sample budget"
+    return out
+
+
+def host_true_residuals(g, B, X):
+    """max over columns of ||b - L x|| / ||b|| (b projected to mean zero),
+    recomputed on the host in fp64 from the input graph."""
+    import scipy.sparse as sp
+
+    A = sp.csr_matrix((g.w, g.col, g.row_ptr), shape=(g.n, g.n))
+    d = np.asarray(A.sum(axis=1)).ravel()
+    Bp = B - B.mean(axis=0)
+    R = Bp - (d[:, None] * X - A @ X)
+    return np.linalg.norm(R, axis=0) / np.linalg.norm(Bp, axis=0)
+
+
+def energy_diff(g, Xa, Xb):
+    """||xa - xb||_L / ||xb||_L per column (sqrt(x^T L x) from the edge list)."""
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    out = []
+    for c in range(Xa.shape[1]):
+        def en(x):
+            dx = x[rows] - x[g.col]
+            return np.sqrt(0.5 * np.dot(g.w, dx * dx))
+        out.append(float(en(Xa[:, c] - Xb[:, c]) / en(Xb[:, c])))
+    return out
 
 
 # ------------------------------------------------------------ profile summaries
@@ -279,7 +366,7 @@ def trace_summary(args):
         lines.append("(kernel tracing adds time to the events that bracket each dispatch; the "
                      "kernel's own duration is the rocprofv3 figure, which the unprofiled events match)")
     os.makedirs(PROFILES, exist_ok=True)
-    path = os.path.join(PROFILES, f"{wl['family']}_{args.workload}_kernel_stats.txt")
+    path = os.path.join(PROFILES, f"{_fam_tag(wl['family'])}_{args.workload}_kernel_stats.txt")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -400,13 +487,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat_s18", choices=list(WORKLOADS) + ["serving"])
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=list(WORKLOADS) + ["serving"])
     ap.add_argument("--pool", type=int, default=64, help="serving: graphs in the pool")
     ap.add_argument("--requests", type=int, default=400, help="serving: requests per run")
     ap.add_argument("--workers", type=int, default=8, help="serving: server workers")
     ap.add_argument("--baseline-requests", type=int, default=120,
                     help="serving: requests replayed as FP64 single-column solves")
-    ap.add_argument("--latency-solves", type=int, default=100)
+    ap.add_argument("--latency-solves", type=int, default=None,
+                    help="solve-only latency samples (default 100, 20 above 2^24 nnz)")
+    ap.add_argument("--no-companion", action="store_true",
+                    help="skip the companion workload (the mixed form beside the FP64 default)")
     ap.add_argument("--family", default=None, help="kernel family timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cycle", type=int, default=None, choices=(1, 2),
@@ -454,13 +544,64 @@ def main():
 
     dev = torch.device("cuda:0")
     wl = WORKLOADS[args.workload]
-    family = args.family or wl["family"]
+    t0 = time.perf_counter()
     g = gg.config_graph(wl["cfg"])
     b_host = gg.config_rhs(wl["cfg"], g.n, wl["k"])
+    say(f"graph {wl['cfg']}: n={g.n} nnz={g.nnz}, generated in {time.perf_counter() - t0:.1f} s")
     rp = torch.as_tensor(g.row_ptr).to(dev)
     col = torch.as_tensor(g.col).to(dev)
     w = torch.as_tensor(g.w).to(dev)
     B = torch.as_tensor(b_host).to(dev)
+    latency_solves = args.latency_solves
+    if latency_solves is None:
+        latency_solves = 100 if g.nnz < (1 << 24) else 20
+
+    out = measure(args, lg, dev, g, b_host, rp, col, w, B, args.workload, args.family,
+                  latency_solves)
+    comp = wl.get("companion")
+    if comp and not args.no_companion:
+        mo = measure(args, lg, dev, g, b_host, rp, col, w, B, comp, None, latency_solves)
+        X64, Xmx = out.pop("_X"), mo.pop("_X")
+        ed = energy_diff(g, Xmx[:, [0, -1]], X64[:, [0, -1]])
+        out["mixed"] = {k: mo[k] for k in ("value", "ms_per_step", "dtype", "setup_ms", "solve_ms",
+                                           "iters", "wda", "roofline", "solve_only",
+                                           "host_true_rel_residual_max", "hierarchy_bytes")
+                        if k in mo}
+        out["mixed"]["workload"] = WORKLOADS[comp]["label"]
+        out["mixed"]["energy_norm_diff_vs_fp64"] = max(ed)
+        out["mixed_speedup_vs_fp64"] = mo["value"] / out["value"]
+    else:
+        out.pop("_X", None)
+    if args.eigs:
+        out["eigs"] = eigs_bench(lg, rp, col, w, out.pop("_opts"), args.eigs)
+    out.pop("_opts", None)
+    if not args.no_stream_roof and not args.calibration_copy:  # (counter runs calibrate on a copy)
+        out["stream_roof"] = stream_roof(dev)
+    if args.calibration_copy:
+        src = torch.empty(64 << 20, dtype=torch.float64, device=dev)  # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if not args.no_cpu_baseline:
+        say("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(g, b_host, wl["k"], out["iters"])
+    print(json.dumps(out), flush=True)
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def measure(args, lg, dev, g, b_host, rp, col, w, B, workload, family, latency_solves):
+    """Warm-up and timed steps of one workload on resident inputs, then
+    (outside the timed region) the host residual check, solve-only latency and
+    the finest-level fp64 SpMV rate."""
+    import torch
+
+    wl = WORKLOADS[workload]
+    family = family or wl["family"]
     opts = lg.lg_default_opts(max_rhs=wl["k"],
                               precision=lg.LG_MIXED if wl["precision"] == "mixed" else lg.LG_FP64)
     if args.graphs is not None:
@@ -472,18 +613,15 @@ def main():
     if args.cycle is not None:
         opts.cycle = args.cycle
     torch.cuda.synchronize()
-
-    def step():
+    for _ in range(args.warmup):
         h = lg.lg_setup(rp, col, w, opts)
         X, info, st = lg.lg_solve(h, B, rtol=1e-8, max_iter=500)
-        return h, info
-
-    for _ in range(args.warmup):
-        h, info = step()
         del h
+    say(f"{workload}: {args.warmup} warm-up step(s) done; timing {args.steps}")
 
     lg.lg_profile_enable(family)
     setup_ms, solve_ms, infos = [], [], []
+    X = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -504,11 +642,17 @@ def main():
     elapsed = t1 - t0
     ms_per_step = elapsed * 1e3 / args.steps
     value = args.steps * wl["k"] / elapsed
+    say(f"{workload}: {ms_per_step:.2f} ms per step, {value:.2f} solves/s")
+
+    # the last timed step's solutions, checked on the host (outside the timed region)
+    Xh = X.cpu().numpy()
+    true_rel = host_true_residuals(g, b_host, Xh)
+    assert np.all(true_rel <= 1e-8 * 1.001), true_rel.max()
 
     # solve-only latency on a resident hierarchy
     h = lg.lg_setup(rp, col, w, opts)
     lat = []
-    for _ in range(args.latency_solves):
+    for _ in range(latency_solves):
         a = time.perf_counter()
         X, info, st = lg.lg_solve(h, B, rtol=1e-8, max_iter=500)
         lat.append((time.perf_counter() - a) * 1e3)
@@ -531,9 +675,10 @@ def main():
     sp_n, sp_ms, sp_bytes = lg.lg_profile_read()
     lg.lg_profile_enable(None)
     spmv_gbs = sp_bytes / (sp_ms * 1e-3) / 1e9 if sp_ms > 0 else None
+    del h, x, y
 
     achieved = fam_bytes / (fam_ms * 1e-3) / 1e9 if fam_ms > 0 else 0.0
-    traffic = load_traffic(family, args.workload) if family == wl["family"] else None
+    traffic = load_traffic(family, workload) if family == wl["family"] else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -565,34 +710,23 @@ def main():
         "setup_ms": float(np.median(setup_ms)),
         "solve_ms": float(np.median(solve_ms)),
         "iters": infos[-1][0]["iters"],
+        "iters_per_rhs": [i["iters"] for i in infos[-1]],
         "wda": infos[-1][0]["wda"],
+        "host_true_rel_residual_max": float(true_rel.max()),
         "spmv_fp64_gbs": spmv_gbs,
         "spmv_fp64_ms": sp_ms / sp_n if sp_n else None,
         "spmv_fp64_rhs": kk,
         "hierarchy_bytes": hier_bytes,
         "levels": [(s["type"], s["n"], s["nnz"], s["lane_shift"], s["col_shift"], s["merge"])
                    for s in stats],
+        "_X": Xh,
+        "_opts": opts,
     }
     if lat.size:
         out["solve_only"] = {"solves_per_s": wl["k"] * 1e3 / float(lat.mean()),
                              "p50_ms": float(np.percentile(lat, 50)),
                              "p99_ms": float(np.percentile(lat, 99)), "solves": int(lat.size)}
-    del h
-    if args.eigs:
-        out["eigs"] = eigs_bench(lg, rp, col, w, opts, args.eigs)
-    if not args.no_stream_roof and not args.calibration_copy:  # (counter runs calibrate on a copy)
-        out["stream_roof"] = stream_roof(dev)
-    if args.calibration_copy:
-        src = torch.empty(64 << 20, dtype=torch.float64, device=dev)  # 512 MiB
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    if not args.no_cpu_baseline and args.workload in ("rmat_s18", "grid2d_64"):
-        out["cpu_baseline"] = cpu_baseline(g, b_host)
-    print(json.dumps(out), flush=True)
-
+    return out
 
 if __name__ == "__main__":
     main()

@@ -45,4 +45,19 @@ def test_every_workload_names_a_graph_recipe():
 
     for name, wl in bench.WORKLOADS.items():
         assert wl["cfg"] in gg.CONFIGS, name
-        assert wl["family"] in ("spmv", "cheb"), name
+        assert set(wl["family"].split(",")) <= {"spmv", "lanczos", "cheb", "cheb0", "cheb1", "resid"}, name
+
+
+def test_cpu_baseline_times_setup_and_solves_apart():
+    import graphgen as gg
+
+    g = gg.grid2d(24, 24)
+    B = gg.rhs(g.n, 2, 1)
+    full = bench.cpu_baseline(g, B, k=2, iters=1000)
+    assert full["kind"] == "oracle" and full["cores"] >= 1 and full["value"] > 0
+    assert full["setup_s"] > 0 and full["solve_s_per_rhs"] > 0
+    assert "solved to 1e-8" in full["sample"]
+    assert full["host"]["nproc"] >= 1
+    # a solve longer than the sample cap is timed for that many iterations and scaled
+    part = bench.cpu_baseline(g, B, k=2, iters=40, max_sample_iters=5)
+    assert "5 CG iterations" in part["sample"] and part["iters"] == 40
