@@ -156,6 +156,21 @@ lg_status lg_solve(lg_hierarchy* h, const double* B, double* X, int32_t k, doubl
 lg_status lg_eigs(lg_hierarchy* h, int32_t nev, double tol, int32_t max_iter, double* X,
                   double* lambda, int32_t* iters, double* resid, void* hip_stream);
 
+/* lg_eigs for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * same computation and results as lg_eigs, but its per-call buffers (the
+ * block vectors and Gram matrices) live in a static 64 MiB device array of
+ * the library, one per GPU, held until the process ends; the call allocates
+ * no device memory and captures no HIP graph (it replays one the hierarchy
+ * already has).  Needs 8 * (3 * n * K + small) bytes for a block of
+ * K = next_pow2(nev + 1) columns on the finest level's n vertices (n up to
+ * about 340,000 at K = 8, 2.7M at K = 2); larger problems return LG_E_ARG
+ * naming the size.  Calls on one GPU share the array: calls that overlap in
+ * time on the same GPU race and must not be made.  The hierarchy must live on
+ * the current device (else LG_E_ARG). */
+lg_status lg_eigs_noalloc(lg_hierarchy* h, int32_t nev, double tol, int32_t max_iter, double* X,
+                          double* lambda, int32_t* iters, double* resid, void* hip_stream);
+
 /* One application of the preconditioner (Algorithm 1 from the finest level
  * with zero initial guess; V- or K-cycle and precision as in setup):
  * X = M B for device n x k fp64 arrays.  No projection.  The columns of B

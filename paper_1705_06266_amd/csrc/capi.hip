@@ -158,6 +158,19 @@ extern "C" lg_status lg_eigs(lg_hierarchy* h, int32_t nev, double tol, int32_t m
   LG_API_END
 }
 
+extern "C" lg_status lg_eigs_noalloc(lg_hierarchy* h, int32_t nev, double tol, int32_t max_iter,
+                                     double* X, double* lambda, int32_t* iters, double* resid,
+                                     void* hip_stream) {
+  if (!h || !X || !lambda) return arg_error("lg_eigs_noalloc: null argument");
+  if (nev < 1 || nev > 7) return arg_error("lg_eigs_noalloc: nev must be in 1..7");
+  if (!(tol > 0.0) || max_iter < 0) return arg_error("lg_eigs_noalloc: need tol > 0 and max_iter >= 0");
+  if (h->lev[0].n < 2 * (nev + 1)) return arg_error("lg_eigs_noalloc: graph too small for nev");
+  LG_API_BEGIN
+  return lg::eigs_noalloc_dispatch(h, nev, tol, max_iter, X, lambda, iters, resid,
+                                   (hipStream_t)hip_stream);
+  LG_API_END
+}
+
 extern "C" lg_status lg_cycle(lg_hierarchy* h, const double* B, double* X, int32_t k,
                               void* hip_stream) {
   if (!h || !B || !X) return arg_error("lg_cycle: null argument");

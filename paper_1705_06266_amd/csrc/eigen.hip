@@ -9,6 +9,8 @@
 // solve).  Eigenvector i converges like (lambda_i / lambda_{b+1})^iteration.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "impl.h"
@@ -233,21 +235,52 @@ struct Eig {
   }
 };
 
+// Workgroups of the Gram reductions for n rows.
+inline int gram_blocks(int64_t n) {
+  return (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(n, (int64_t)kBlock * 8)));
+}
+
+// Doubles of per-call scratch for a block of K columns on n rows: Y, W, Z
+// (n x K), M, G (K x K) and the Gram partials, each rounded up to 256 bytes.
+inline int64_t eig_scratch_doubles(int64_t n, int K) {
+  auto up = [](int64_t v) { return (v + 31) / 32 * 32; };
+  return 3 * up(n * K) + 2 * up((int64_t)K * K) + up((int64_t)gram_blocks(n) * K * K);
+}
+
+// scratch == nullptr: the per-call buffers come from the hierarchy's arena
+// (which may allocate a chunk); else they are carved from scratch, which
+// holds at least eig_scratch_doubles(n, K) doubles.
 template <int K>
 lg_status eigs_k(lg_hierarchy* h, int nev, double tol, int max_iter, double* X, double* lambda,
-                 int* iters, double* resid, hipStream_t st) {
+                 int* iters, double* resid, hipStream_t st, double* scratch) {
   constexpr int b = K;
   const Level& L0 = h->lev[0];
   Eig<K> e{h, st, L0.n, b};
   const int64_t m = e.n * K;
-  e.nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(e.n, (int64_t)kBlock * 8)));
+  e.nb = gram_blocks(e.n);
   Arena::Mark mark = h->mem.mark();
-  e.Y = h->mem.get<double>(m);
-  e.W = h->mem.get<double>(m);
-  e.Z = h->mem.get<double>(m);
-  e.M = h->mem.get<double>(K * K);
-  e.G = h->mem.get<double>(K * K);
-  e.part = h->mem.get<double>((int64_t)e.nb * K * K);
+  if (scratch) {
+    auto up = [](int64_t v) { return (v + 31) / 32 * 32; };
+    double* p = scratch;
+    e.Y = p;
+    p += up(m);
+    e.W = p;
+    p += up(m);
+    e.Z = p;
+    p += up(m);
+    e.M = p;
+    p += up(K * K);
+    e.G = p;
+    p += up(K * K);
+    e.part = p;
+  } else {
+    e.Y = h->mem.get<double>(m);
+    e.W = h->mem.get<double>(m);
+    e.Z = h->mem.get<double>(m);
+    e.M = h->mem.get<double>(K * K);
+    e.G = h->mem.get<double>(K * K);
+    e.part = h->mem.get<double>((int64_t)e.nb * K * K);
+  }
   struct Release {
     lg_hierarchy* h;
     Arena::Mark m;
@@ -313,21 +346,78 @@ lg_status eigs_k(lg_hierarchy* h, int nev, double tol, int max_iter, double* X, 
   return LG_OK;
 }
 
+
+// The allocation-free variant's scratch: a file-scope device array, one copy
+// per GPU the library runs on, held until the process ends.  Host code uses
+// its device address from hipGetSymbolAddress (kept per device), never the
+// array's name.  Every lg_eigs_noalloc call on a GPU shares that GPU's copy.
+constexpr int64_t kEigScratchBytes = (int64_t)64 << 20;
+__device__ __align__(256) double scratch[kEigScratchBytes / 8];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+double* scratch_on(int device) {
+  if (device < 0 || device >= kMaxDevices) fail(LG_E_ARG, "lg_eigs_noalloc: device index out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      fail(LG_E_HIP, std::string("lg_eigs_noalloc: hipGetSymbolAddress failed: ") + hipGetErrorString(e));
+    g_scratch[device] = (double*)p;
+  }
+  return g_scratch[device];
+}
+
+int eig_width(lg_hierarchy* h, int nev) {
+  int K = 2;
+  while (K < nev + 1) K <<= 1;
+  if (K > 8 || K > h->opts.max_rhs)
+    fail(LG_E_ARG, "lg_eigs: needs nev + 1 <= 8 and a block of next_pow2(nev + 1) <= max_rhs");
+  return K;
+}
+
+lg_status eigs_run(lg_hierarchy* h, int nev, double tol, int max_iter, double* X, double* lambda,
+                   int* iters, double* resid, hipStream_t st, double* scr) {
+  switch (eig_width(h, nev)) {
+    case 2: return eigs_k<2>(h, nev, tol, max_iter, X, lambda, iters, resid, st, scr);
+    case 4: return eigs_k<4>(h, nev, tol, max_iter, X, lambda, iters, resid, st, scr);
+    default: return eigs_k<8>(h, nev, tol, max_iter, X, lambda, iters, resid, st, scr);
+  }
+}
+
 }  // namespace
 
 // Block width: the next power of two above nev (one guard vector at least),
 // at most 8 and at most the hierarchy's max_rhs.
 lg_status eigs_dispatch(lg_hierarchy* h, int nev, double tol, int max_iter, double* X,
                         double* lambda, int* iters, double* resid, hipStream_t st) {
-  int K = 2;
-  while (K < nev + 1) K <<= 1;
-  if (K > 8 || K > h->opts.max_rhs)
-    fail(LG_E_ARG, "lg_eigs: needs nev + 1 <= 8 and a block of next_pow2(nev + 1) <= max_rhs");
-  switch (K) {
-    case 2: return eigs_k<2>(h, nev, tol, max_iter, X, lambda, iters, resid, st);
-    case 4: return eigs_k<4>(h, nev, tol, max_iter, X, lambda, iters, resid, st);
-    default: return eigs_k<8>(h, nev, tol, max_iter, X, lambda, iters, resid, st);
-  }
+  return eigs_run(h, nev, tol, max_iter, X, lambda, iters, resid, st, nullptr);
+}
+
+// As eigs_dispatch, with the per-call buffers in the static scratch array and
+// no cycle graph captured during the call (an existing one is replayed).
+lg_status eigs_noalloc_dispatch(lg_hierarchy* h, int nev, double tol, int max_iter, double* X,
+                                double* lambda, int* iters, double* resid, hipStream_t st) {
+  int dev = -1;
+  LG_HIP(hipGetDevice(&dev));
+  if (dev != h->device) fail(LG_E_ARG, "lg_eigs_noalloc: the hierarchy lives on another device");
+  const int K = eig_width(h, nev);
+  const int64_t need = eig_scratch_doubles(h->lev[0].n, K) * 8;
+  if (need > kEigScratchBytes)
+    fail(LG_E_ARG, "lg_eigs_noalloc: a block of " + std::to_string(K) + " columns on " +
+                       std::to_string(h->lev[0].n) + " vertices needs " + std::to_string(need) +
+                       " bytes of scratch; the static buffer holds " +
+                       std::to_string(kEigScratchBytes));
+  double* scr = scratch_on(dev);
+  struct NoCapture {
+    lg_hierarchy* h;
+    ~NoCapture() { h->no_capture = false; }
+  } guard{h};
+  h->no_capture = true;
+  return eigs_run(h, nev, tol, max_iter, X, lambda, iters, resid, st, scr);
 }
 
 }  // namespace lg

@@ -94,6 +94,7 @@ struct lg_hierarchy {
   };
   CycleGraph cycle_graph[6];
   hipStream_t capture_stream = nullptr;
+  bool no_capture = false;  // set during an allocation-free call: replay only, never capture
   ~lg_hierarchy() {
     for (CycleGraph& g : cycle_graph)
       if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -146,4 +147,6 @@ void spmv_dispatch(lg_hierarchy* h, int level, const double* X, double* Y, int k
 void autotune(lg_hierarchy* h, hipStream_t st);
 lg_status eigs_dispatch(lg_hierarchy* h, int nev, double tol, int max_iter, double* X,
                         double* lambda, int* iters, double* resid, hipStream_t st);
+lg_status eigs_noalloc_dispatch(lg_hierarchy* h, int nev, double tol, int max_iter, double* X,
+                                double* lambda, int* iters, double* resid, hipStream_t st);
 }  // namespace lg

@@ -923,7 +923,7 @@ struct Engine {
       LG_HIP(hipGraphLaunch(cg.exec, st));
       return (const T*)cg.out;
     }
-    if (cg.exec || cg.uses++ == 0) return level(0, in);
+    if (cg.exec || cg.uses++ == 0 || h->no_capture) return level(0, in);
     if (!h->capture_stream) LG_HIP(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     LG_HIP(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));

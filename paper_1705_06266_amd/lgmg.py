@@ -23,7 +23,7 @@ LG_CYCLE_V, LG_CYCLE_K = 1, 2
 LG_FP64, LG_MIXED = 0, 1
 
 EXPORTS = [
-    "lg_default_opts", "lg_setup", "lg_solve", "lg_eigs", "lg_cycle", "lg_spmv", "lg_hierarchy_stats",
+    "lg_default_opts", "lg_setup", "lg_solve", "lg_eigs", "lg_eigs_noalloc", "lg_cycle", "lg_spmv", "lg_hierarchy_stats",
     "lg_export_level", "lg_export_setup_data", "lg_export_coarsest", "lg_hierarchy_bytes",
     "lg_setup_ms", "lg_free", "lg_profile_enable", "lg_profile_read", "lg_profile_names",
     "lg_status_str", "lg_last_error",
@@ -99,6 +99,7 @@ def load():
         "lg_solve": (_I32, [_P, _P, _P, _I32, _D, _I32, _P, _P]),
         "lg_cycle": (_I32, [_P, _P, _P, _I32, _P]),
         "lg_eigs": (_I32, [_P, _I32, _D, _I32, _P, _P, _P, _P, _P]),
+        "lg_eigs_noalloc": (_I32, [_P, _I32, _D, _I32, _P, _P, _P, _P, _P]),
         "lg_spmv": (_I32, [_P, _I32, _P, _P, _I32, _P]),
         "lg_hierarchy_stats": (_I32, [_P, _P, _I32, _P]),
         "lg_export_level": (_I32, [_P, _I32, _P, _P, _P, _P, _P]),
@@ -242,6 +243,19 @@ def lg_eigs(h, nev=1, tol=1e-8, max_iter=200, stream=None, allow_unconverged=Fal
     st = _check(load().lg_eigs(h.handle, nev, tol, max_iter, _ptr(X), _ptr(lam), C.byref(it),
                                _ptr(res), _stream(stream)), "lg_eigs", ok)
     return lam, X, it.value, res, st
+
+
+def lg_eigs_noalloc(h, nev, X, tol=1e-8, max_iter=200, stream=None, allow_unconverged=False):
+    """lg_eigs without device allocation inside the call: X (device float64,
+    shape (n, nev)) is the caller's output; returns (lambda, iters, resid, status)."""
+    lam = np.zeros(nev)
+    res = np.zeros(nev)
+    it = C.c_int32()
+    ok = (LG_OK, LG_E_NOT_CONVERGED) if allow_unconverged else (LG_OK,)
+    st = _check(load().lg_eigs_noalloc(h.handle, nev, tol, max_iter, _ptr(X), _ptr(lam),
+                                       C.byref(it), _ptr(res), _stream(stream)),
+                "lg_eigs_noalloc", ok)
+    return lam, it.value, res, st
 
 
 def lg_cycle(h, B, X=None, stream=None):
