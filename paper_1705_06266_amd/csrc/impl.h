@@ -46,6 +46,10 @@ struct Level {
   Sched ptsched;
   int64_t nF = 0, nnzP = 0;
   double lmax = 0.0;
+  // column-split smoothing from a zero guess: 1 = the first iterate stored by
+  // an elementwise pass, then one product (no D^-1 gather per entry); 0 = both
+  // steps in one product.  The same arithmetic either way; set by the autotuner.
+  bool cheb0_split = false;
   // setup data kept for export
   double* X = nullptr;
   double* S = nullptr;

@@ -11,7 +11,10 @@ struct VecAcc {
   T v[K];
 };
 
-enum { LAP_SPMV = 0, LAP_RESID = 1, LAP_CHEB = 2, LAP_CHEB_FIRST = 3, LAP_CHEB_ZERO = 4, LAP_CHEB_X1 = 5 };
+enum {
+  LAP_SPMV = 0, LAP_RESID = 1, LAP_CHEB = 2, LAP_CHEB_FIRST = 3, LAP_CHEB_ZERO = 4, LAP_CHEB_X1 = 5,
+  LAP_CHEB_FIRST_CC = 6
+};
 
 // Row i: s = sum_j w_ij x_j (k columns), (L x)_i = d_i x_i - s.  The Chebyshev
 // modes use the three-term recurrence on iterates (Section 3.6 smoother):
@@ -26,6 +29,14 @@ enum { LAP_SPMV = 0, LAP_RESID = 1, LAP_CHEB = 2, LAP_CHEB_FIRST = 3, LAP_CHEB_Z
 //  LAP_CHEB_X1:    the second step from a zero guess with x1 stored in x:
 //                  y = x + c1 x + c2 dinv (b - L x).  (CHEB_ZERO gathers dinv
 //                  with every neighbour, which pays off only for wide rows.)
+//  LAP_CHEB_FIRST_CC (column-split form only): the coarse correction and the
+//                  first post-smoothing step in one pass.  On entry y holds the
+//                  pre-smoothed iterate x, b its residual r = b - L x, and x
+//                  points at the coarse solution x_c with agg the aggregate
+//                  map; with x' = x + P x_c (written back to y) the step is
+//                  p = x' + c2 dinv (r - L P x_c), which equals
+//                  x' + c2 dinv (b - L x') in exact arithmetic.  Row i's gathers
+//                  read x_c[agg_j], a vector the size of the coarse level.
 // TAG only separates kernel instances (lg_spmv's own launches from the
 // solver's) so that profiles attribute time per call site.
 template <typename T, int K, int MODE, int TAG = 0>
@@ -122,6 +133,7 @@ struct LapColOp {
   const T* __restrict__ b;
   T* __restrict__ p;
   T c1, c2, c0;
+  const int32_t* __restrict__ agg = nullptr;  // LAP_CHEB_FIRST_CC: aggregate of each row
 
   __device__ __forceinline__ Acc identity() const {
     Acc a;
@@ -132,7 +144,7 @@ struct LapColOp {
   __device__ __forceinline__ bool active(int64_t) const { return true; }
   // keep = false: a padding slot of an unrolled loop (e is a valid index, weight 0)
   __device__ __forceinline__ void accum(Acc& a, int64_t, int e, int part, bool keep = true) const {
-    const int j = col[e];
+    const int j = MODE == LAP_CHEB_FIRST_CC ? agg[col[e]] : col[e];
     const T wv = keep ? w[e] : T(0);
     const vec_t xv = *reinterpret_cast<const vec_t*>(x + (int64_t)j * K + part * V);
     if (MODE == LAP_CHEB_ZERO) {
@@ -158,10 +170,13 @@ struct LapColOp {
     Pre q;
     const int64_t base = row * K + part * V;
     q.di = d[row];
-    q.xv = *reinterpret_cast<const vec_t*>(x + base);
+    // CC: xv is the row's own coarse value x_c[agg_row]
+    q.xv = *reinterpret_cast<const vec_t*>(
+        x + (MODE == LAP_CHEB_FIRST_CC ? (int64_t)agg[row] * K + part * V : base));
     if (MODE != LAP_SPMV) q.bv = MODE == LAP_CHEB_ZERO ? q.xv : *reinterpret_cast<const vec_t*>(b + base);
     if (MODE >= LAP_CHEB) q.dv = dinv[row];
-    if (MODE == LAP_CHEB) q.yv = *reinterpret_cast<const vec_t*>(y + base);
+    if (MODE == LAP_CHEB || MODE == LAP_CHEB_FIRST_CC)
+      q.yv = *reinterpret_cast<const vec_t*>(y + base);
     return q;
   }
   __device__ __forceinline__ void finish(int64_t row, const Acc& a, int part) const {
@@ -176,6 +191,18 @@ struct LapColOp {
       for (int v = 0; v < V; v++) xv[v] = (q.dv * xv[v]) * c0;
     }
     vec_t out;
+    if (MODE == LAP_CHEB_FIRST_CC) {
+      vec_t xn;
+#pragma unroll
+      for (int v = 0; v < V; v++) {
+        xn[v] = q.yv[v] + xv[v];                            // x' = x + P x_c
+        const T r = q.dv * (q.bv[v] - (di * xv[v] - a.v[v]));  // dinv (r - L P x_c)
+        out[v] = xn[v] + c2 * r;
+      }
+      *reinterpret_cast<vec_t*>(y + base) = xn;
+      *reinterpret_cast<vec_t*>(p + base) = out;
+      return;
+    }
     if (MODE == LAP_SPMV) {
 #pragma unroll
       for (int v = 0; v < V; v++) out[v] = di * xv[v] - a.v[v];

@@ -731,14 +731,16 @@ struct Engine {
   // vecs: n x K vectors streamed (reads and writes); the smoother modes also read D^-1
   template <int MODE>
   void lap(const Level& L, const T* x, T* y, const T* b, T* p, T c1, T c2, T c0, const char* fam,
-           int vecs) {
+           int vecs, const int32_t* agg = nullptr) {
     Vals<T> v = vals_of<T>(L);
-    const double bytes =
+    double bytes =
         spmm_bytes(L, K, (int)sizeof(T), vecs) + (MODE >= LAP_CHEB ? (double)sizeof(T) * L.n : 0);
+    if (MODE == LAP_CHEB_FIRST_CC)  // the coarse vector replaces x, plus the map
+      bytes += ((double)L.nc - (double)L.n) * K * sizeof(T) + 4.0 * L.n;
     if constexpr (use_col_split<T, K>()) {
       run_rows_col(L.sched, L.rp,
-                   LapColOp<T, K, MODE>{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2, c0}, st, fam,
-                   bytes);
+                   LapColOp<T, K, MODE>{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2, c0, agg}, st,
+                   fam, bytes);
     } else {
       const LapOp<T, K, MODE> op{L.col, v.w, v.d, v.dinv, x, y, b, p, c1, c2, c0};
       if constexpr (K == 1) {
@@ -806,12 +808,14 @@ struct Engine {
     } else if (smooth) {
       double rho = 1.0 / sigma;
       double rho1 = 1.0 / (2.0 * sigma - rho);
-      if constexpr (use_col_split<T, K>()) {
+      bool one_pass = false;
+      if constexpr (use_col_split<T, K>()) one_pass = !L.cheb0_split;
+      if (one_pass) {
         // steps 0 and 1 in one pass; step 0's iterate is stored only if more follow
         lap<LAP_CHEB_ZERO>(L, b, cur, b, deg > 2 ? nxt : nullptr, (T)(rho1 * rho),
                            (T)(2.0 * rho1 / delta), (T)(1.0 / theta), "cheb0", deg > 2 ? 3 : 2);
       } else {
-        // narrow rows: store step 0's iterate, then step 1 without a D^-1 gather
+        // store step 0's iterate, then step 1 without a D^-1 gather per entry
         hipLaunchKernelGGL((k_cheb_zero<T, K>), dim3(vec_blocks<T, K>(n)), dim3(kBlock), 0, st, b,
                            v.dinv, nxt, n, (T)(1.0 / theta));
         lap<LAP_CHEB_X1>(L, nxt, cur, b, nullptr, (T)(rho1 * rho), (T)(2.0 * rho1 / delta), T(0),
@@ -839,16 +843,30 @@ struct Engine {
     }
     const T* xc = (o.cycle == LG_CYCLE_K && C.type != LG_LEVEL_COARSEST) ? fcg2(l + 1, bc)
                                                                           : level(l + 1, bc);
-    {
-      ProfScope ps("prolong", st, 4.0 * n + 3.0 * K * n * sizeof(T));
-      hipLaunchKernelGGL((k_agg_prolong<T, K>), dim3(vec_blocks<T, K>(n)), dim3(kBlock), 0, st, cur,
-                         xc, L.agg, nxt, n);
-      std::swap(cur, nxt);
+    bool fused_cc = false;
+    if constexpr (use_col_split<T, K>()) fused_cc = smooth;
+    if (fused_cc) {
+      if constexpr (use_col_split<T, K>()) {
+        // x += P x_c in place and the first post-smoothing step in one pass,
+        // its residual r - L P x_c gathered from the coarse vector, which is a
+        // fraction of the fine iterate's size and stays in cache
+        lap<LAP_CHEB_FIRST_CC>(L, xc, cur, r, nxt, T(0), (T)(1.0 / theta), T(0), "cheb1", 4, L.agg);
+        std::swap(cur, nxt);
+      }
+    } else {
+      {
+        ProfScope ps("prolong", st, 4.0 * n + 3.0 * K * n * sizeof(T));
+        hipLaunchKernelGGL((k_agg_prolong<T, K>), dim3(vec_blocks<T, K>(n)), dim3(kBlock), 0, st,
+                           cur, xc, L.agg, nxt, n);
+        std::swap(cur, nxt);
+      }
+      // nxt keeps the previous iterate, which each further step overwrites
+      if (smooth) {
+        lap<LAP_CHEB_FIRST>(L, cur, nxt, b, nullptr, T(0), (T)(1.0 / theta), T(0), "cheb1", 3);
+        std::swap(cur, nxt);
+      }
     }
     if (smooth) {
-      // nxt keeps the previous iterate, which each further step overwrites
-      lap<LAP_CHEB_FIRST>(L, cur, nxt, b, nullptr, T(0), (T)(1.0 / theta), T(0), "cheb1", 3);
-      std::swap(cur, nxt);
       double rho = 1.0 / sigma;
       for (int s = 1; s < deg; s++) {
         const double rho1 = 1.0 / (2.0 * sigma - rho);
@@ -1410,6 +1428,44 @@ std::mutex g_tune_mu;
 std::map<std::vector<int64_t>, int> g_tune;
 }  // namespace
 
+// Smoothing from a zero guess on a column-split aggregation level: time the
+// one-pass form against the stored-iterate form (identical arithmetic) and
+// keep the faster.  Cached under the level's key with a trailing -1.
+template <typename T, int K>
+static void tune_cheb0(Engine<T, K>& eng, Level& L, const std::vector<int64_t>& key, hipEvent_t e0,
+                       hipEvent_t e1) {
+  if constexpr (use_col_split<T, K>()) {
+    const hipStream_t st = eng.st;
+    T* b = (T*)L.vb;
+    T* x = (T*)L.vx;
+    T* x2 = (T*)L.vx2;
+    const Vals<T> v = vals_of<T>(L);
+    auto run = [&](bool split) {
+      if (split) {
+        hipLaunchKernelGGL((k_cheb_zero<T, K>), dim3(vec_blocks<T, K>(L.n)), dim3(kBlock), 0, st, b,
+                           v.dinv, x2, L.n, T(1));
+        eng.template lap<LAP_CHEB_X1>(L, x2, x, b, nullptr, T(0), T(1), T(0), "", 3);
+      } else {
+        eng.template lap<LAP_CHEB_ZERO>(L, b, x, b, nullptr, T(0), T(1), T(1), "", 2);
+      }
+    };
+    float ms[2] = {0.0f, 0.0f};
+    for (int split = 0; split < 2; split++) {
+      run(split);  // warm-up
+      LG_HIP(hipEventRecord(e0, st));
+      for (int r = 0; r < 3; r++) run(split);
+      LG_HIP(hipEventRecord(e1, st));
+      LG_HIP(hipEventSynchronize(e1));
+      LG_HIP(hipEventElapsedTime(&ms[split], e0, e1));
+    }
+    L.cheb0_split = ms[1] < ms[0];
+    std::vector<int64_t> k2 = key;
+    k2.push_back(-1);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[k2] = L.cheb0_split ? 1 : 0;
+  }
+}
+
 template <typename T, int K>
 static void autotune_k(lg_hierarchy* h, hipStream_t st) {
   Engine<T, K> eng{h, st};
@@ -1435,6 +1491,10 @@ static void autotune_k(lg_hierarchy* h, hipStream_t st) {
       if (it != g_tune.end()) {
         L.sched.merge = it->second < 0;
         if (it->second >= 0) shift = it->second;
+        std::vector<int64_t> k2 = key;
+        k2.push_back(-1);
+        auto it2 = g_tune.find(k2);
+        if (it2 != g_tune.end()) L.cheb0_split = it2->second != 0;
         continue;
       }
     }
@@ -1473,8 +1533,11 @@ static void autotune_k(lg_hierarchy* h, hipStream_t st) {
     }
     L.sched.merge = best < 0;
     if (best >= 0) shift = best;
-    std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune[key] = best;
+    {
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      g_tune[key] = best;
+    }
+    if (agg && col) tune_cheb0(eng, L, key, e0, e1);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -84,12 +84,15 @@ def test_fullsize_hierarchy_bit_exact(case):
 
 
 def test_fullsize_fp64_cycle(case):
+    """One FP64 cycle at the benchmark's width of 16 columns (column-split
+    kernels, the fused coarse-correction step), two columns against the
+    oracle's cycle."""
     name, g, ho = case
-    hg = gpu_setup(g, max_rhs=2)
-    B = gg.rhs(g.n, 2, 17)
+    hg = gpu_setup(g, max_rhs=16)
+    B = gg.rhs(g.n, 16, 17)
     B -= B.mean(axis=0)
     X = lg.lg_cycle(hg, to_dev(B)).cpu().numpy()
-    for c in range(2):
+    for c in (0, 15):
         xo = ho.cycle(B[:, c])
         err = np.linalg.norm(X[:, c] - xo) / np.linalg.norm(xo)
         say(f"  column {c}: relative difference {err:.2e}")
