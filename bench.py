@@ -46,24 +46,24 @@ KERNEL_SOURCES = ["paper_1705_06266_amd/csrc/common.h", "paper_1705_06266_amd/cs
 # companion: a second workload timed beside this one on the same inputs.
 WORKLOADS = {
     "chunglu_4m": dict(cfg="chunglu_4m", precision="fp64", k=16,
-                       label="chunglu_4m_g2.1_d16_fp64_16rhs", family="cheb",
-                       kernel="k_rows_col<lg::LapColOp<double, 16, 2, 0> >",
+                       label="chunglu_4m_g2.1_d16_fp64_16rhs", family="resid,resid64",
+                       kernel="k_rows_col<lg::LapColOp<double, 16, 1, 0> >",
                        companion="chunglu_4m_mixed"),
     "chunglu_4m_mixed": dict(cfg="chunglu_4m", precision="mixed", k=16,
                              label="chunglu_4m_g2.1_d16_mixed_16rhs", family="spmv",
                              kernel="k_rows_col<lg::LapColOp<double, 16, 0, 0> >"),
     "rmat_s18": dict(cfg="rmat_s18", precision="fp64", k=1,
-                     label="rmat_s18_ef16_lcc_u01_fp64_1rhs", family="spmv,lanczos",
-                     kernel="k_rows<lg::LapOp<double, 1, 0, 0> >"),
+                     label="rmat_s18_ef16_lcc_u01_fp64_1rhs", family="resid,resid64",
+                     kernel="k_rows<lg::LapOp<double, 1, 1, 0> >"),
     "grid2d_64": dict(cfg="grid2d_64", precision="fp64", k=1,
-                      label="grid2d_64x64_unit_fp64_1rhs", family="spmv,lanczos",
+                      label="grid2d_64x64_unit_fp64_1rhs", family="spmv",
                       kernel="k_rows<lg::LapOp<double, 1, 0, 0> >"),
     "grid3d_128_mixed": dict(cfg="grid3d_128_loguniform", precision="mixed", k=32,
-                             label="grid3d_128cube_loguniform_mixed_32rhs", family="cheb",
-                             kernel="k_rows_col<lg::LapColOp<float, 32, 2, 0> >"),
+                             label="grid3d_128cube_loguniform_mixed_32rhs", family="cg_update",
+                             kernel="k_update_xr<32, float>"),
     "grid3d_128_fp64": dict(cfg="grid3d_128_loguniform", precision="fp64", k=32,
-                            label="grid3d_128cube_loguniform_fp64_32rhs", family="cheb",
-                            kernel="k_rows_col<lg::LapColOp<double, 32, 2, 0> >"),
+                            label="grid3d_128cube_loguniform_fp64_32rhs", family="resid,resid64",
+                            kernel="k_rows_col<lg::LapColOp<double, 32, 1, 0> >"),
 }
 DEFAULT_WORKLOAD = "chunglu_4m"
 
@@ -357,7 +357,8 @@ def trace_summary(args):
             continue
         with open(log) as f:
             rec = json.loads([ln for ln in f if ln.startswith("{")][-1])
-        r = rec["roofline"]
+        # the workload's own line, or the companion object of the default run
+        r = rec["roofline"] if rec["config"]["workload"] == wl["label"] else rec["mixed"]["roofline"]
         lines.append(f"{what}, HIP events in bench.py over the timed steps: {r['launches']} launches, "
                      f"average {r['avg_launch_ms'] * 1e3:.2f} us, "
                      f"{r['algorithmic_bytes_per_launch'] / 1e6:.2f} MB algorithmic per launch, "

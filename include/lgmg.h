@@ -242,12 +242,13 @@ void lg_free(lg_hierarchy* h);
  * lg_profile_names, or several separated by commas), recorded around each of
  * their launches on the launch stream while enabled.  Families of the sparse
  * products time the row kernel alone: "spmv" the CG iteration's fp64 L x,
- * "lanczos" the fp64 L x of setup's Lanczos steps (one column: the same kernel
- * instance as a one-column "spmv"),
- * "spmm" lg_spmv's own launches, "cheb0" the zero-start smoother step, "cheb1"
- * the first step from a nonzero iterate, "cheb" the later steps, "resid" the
- * cycle's residual, "resid64" the CG's true residual, "spmm_inner" the
- * K-cycle's coarse-level FCG products; "restrict", "prolong" and "coarse" time those
+ * "lanczos" the exact-sum L x of setup's Lanczos steps,
+ * "spmm" lg_spmv's own launches, "cheb0" the zero-start smoother steps, "cheb1"
+ * the coarse correction with the first post-smoothing step (or that step
+ * alone), "cheb" the later steps, "resid" the cycle's residual, "resid64" the
+ * CG's true residual (in FP64 the same kernel instance as "resid"), "spmm_inner" the
+ * K-cycle's coarse-level FCG products, "cg_update" the CG's x and r update
+ * (a vector pass); "restrict", "prolong" and "coarse" time those
  * cycle steps.  The setup families ("jacobi_xsum", "row_xsum", "affinity",
  * "vote", "elim_select", "galerkin_reduce") time the span of each call of
  * that setup step, "radix" each radix sort.  lg_profile_read returns

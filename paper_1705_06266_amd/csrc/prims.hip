@@ -241,7 +241,7 @@ extern "C" lg_status lg_profile_read(int64_t* launches, double* total_ms, double
 }
 
 extern "C" const char* lg_profile_names(void) {
-  return "spmv,lanczos,spmm,resid64,cheb0,cheb1,cheb,resid,spmm_inner,restrict,prolong,coarse,"
+  return "spmv,lanczos,spmm,resid64,cg_update,cheb0,cheb1,cheb,resid,spmm_inner,restrict,prolong,coarse,"
          "jacobi_xsum,row_xsum,affinity,vote,elim_select,radix,galerkin_reduce";
 }
 

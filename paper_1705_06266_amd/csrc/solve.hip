@@ -1198,9 +1198,13 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     if (flex) dot64x2(h->pp, h->pq, h->pp, h->pr, S_PQ, S_PR);
     else dot64(h->pp, h->pq, S_PQ);
     hipLaunchKernelGGL((k_alpha<K>), dim3(1), dim3(64), 0, st, sc, flex ? 1 : 0);
-    hipLaunchKernelGGL((k_update_xr<K, T>), dim3(nb), dim3(kBlock), 0, st, h->px, h->pr,
-                       (const double*)h->pp, (const double*)h->pq, (const double*)sc, m,
-                       mixed ? (T*)h->cyc_in : (T*)nullptr, h->red);
+    {
+      // reads x, r, p, q and writes x, r (fp64), plus r in the cycle's precision
+      ProfScope ps("cg_update", st, 48.0 * m + (mixed ? (double)sizeof(T) * m : 0.0));
+      hipLaunchKernelGGL((k_update_xr<K, T>), dim3(nb), dim3(kBlock), 0, st, h->px, h->pr,
+                         (const double*)h->pp, (const double*)h->pq, (const double*)sc, m,
+                         mixed ? (T*)h->cyc_in : (T*)nullptr, h->red);
+    }
     final1(S_RR);
     read_scal();
     std::vector<int> newly, done;

@@ -45,7 +45,7 @@ def test_every_workload_names_a_graph_recipe():
 
     for name, wl in bench.WORKLOADS.items():
         assert wl["cfg"] in gg.CONFIGS, name
-        assert set(wl["family"].split(",")) <= {"spmv", "lanczos", "cheb", "cheb0", "cheb1", "resid"}, name
+        assert set(wl["family"].split(",")) <= {"spmv", "lanczos", "cheb", "cheb0", "cheb1", "resid", "resid64", "cg_update"}, name
 
 
 def test_cpu_baseline_times_setup_and_solves_apart():
