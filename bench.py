@@ -275,13 +275,23 @@ def pmc_summary(args):
     kernel: every counter is scaled by what it reads for a copy of known size."""
     import sqlite3
 
+    import csv
+
     wl = WORKLOADS[args.workload]
     out = {}
     for counter in ("FETCH_SIZE", "WRITE_SIZE"):
-        path = os.path.join(args.pmc_summary, counter.lower(), "run_results.db")
-        db = sqlite3.connect(path)
-        rows = list(db.execute(
-            "select kernel_name, value from counters_collection where counter_name = ?", (counter,)))
+        base = os.path.join(args.pmc_summary, counter.lower())
+        path = os.path.join(base, "run_counter_collection.csv")
+        if os.path.exists(path):  # --output-format csv
+            with open(path) as f:
+                rows = [(r["Kernel_Name"], float(r["Counter_Value"])) for r in csv.DictReader(f)
+                        if r["Counter_Name"] == counter]
+        else:
+            path = os.path.join(base, "run_results.db")
+            db = sqlite3.connect(path)
+            rows = list(db.execute(
+                "select kernel_name, value from counters_collection where counter_name = ?",
+                (counter,)))
         copy_kib = [v for n, v in rows if "copyBuffer" in n or "elementwise" in n]
         # the calibration copy moves 512 MiB each way: its largest dispatch
         cal = max(copy_kib)
@@ -368,6 +378,63 @@ def trace_summary(args):
                      "kernel's own duration is the rocprofv3 figure, which the unprofiled events match)")
     os.makedirs(PROFILES, exist_ok=True)
     path = os.path.join(PROFILES, f"{_fam_tag(wl['family'])}_{args.workload}_kernel_stats.txt")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def setup_summary(args):
+    """Per-kernel breakdown of one setup from a rocprofv3 --kernel-trace run of
+    this script: kernels from a setup's validation kernel up to the solve's
+    first input kernel, the median setup of the run (by span)."""
+    import csv
+
+    wl = WORKLOADS[args.workload]
+    trace = None
+    for root, _, files in os.walk(args.setup_summary):
+        for f in files:
+            if f.endswith("kernel_trace.csv"):
+                trace = os.path.join(root, f)
+    if trace is None:
+        raise SystemExit("no kernel_trace.csv under " + args.setup_summary)
+    with open(trace) as f:
+        rows = sorted(csv.DictReader(f), key=lambda r: int(r["Start_Timestamp"]))
+    names = [_short(r["Kernel_Name"]) for r in rows]
+    starts = [i for i, nm in enumerate(names) if nm == "k_validate"]
+    setups = []
+    for i0 in starts:
+        ends = [i for i in range(i0, len(rows)) if names[i] == "k_pad_in"]
+        if not ends:
+            continue
+        i1 = ends[0]
+        span = (int(rows[i1 - 1]["End_Timestamp"]) - int(rows[i0]["Start_Timestamp"])) / 1e3
+        setups.append((span, i0, i1))
+    if not setups:
+        raise SystemExit("no setup found in " + trace)
+    setups.sort()
+    span, i0, i1 = setups[len(setups) // 2]
+    per, calls, busy = {}, {}, 0.0
+    for i in range(i0, i1):
+        d = (int(rows[i]["End_Timestamp"]) - int(rows[i]["Start_Timestamp"])) / 1e3
+        busy += d
+        per[names[i]] = per.get(names[i], 0.0) + d
+        calls[names[i]] = calls.get(names[i], 0) + 1
+    lines = [f"# rocprofv3 kernel breakdown of one setup, workload {wl['label']}", "",
+             "command:", "  " + args.command, "",
+             f"median of {len(setups)} setups in the trace: span {span:.1f} us from the first "
+             f"kernel to the last, {i1 - i0} kernels, {busy:.1f} us of summed kernel time "
+             "(the Lanczos steps run on a side stream, so kernels overlap; kernel tracing "
+             "adds time between dispatches, so the span exceeds an unprofiled setup)", "",
+             f"{'total us':>10} {'share':>6} {'calls':>6}  kernel"]
+    for nm, t in sorted(per.items(), key=lambda x: -x[1])[:40]:
+        lines.append(f"{t:10.1f} {100 * t / busy:5.1f}% {calls[nm]:6d}  {nm}")
+    if args.plain_log:
+        with open(args.plain_log) as f:
+            rec = json.loads([ln for ln in f if ln.startswith("{")][-1])
+        lines += ["", f"unprofiled run ({args.plain_log.split('/')[-1]}): setup median "
+                      f"{rec['setup_ms']:.2f} ms per step"]
+    os.makedirs(PROFILES, exist_ok=True)
+    path = os.path.join(PROFILES, f"setup_{args.workload}_kernel_breakdown.txt")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -514,6 +581,9 @@ def main():
                          "traffic summary and exit (no GPU)")
     ap.add_argument("--trace-summary", default=None,
                     help="directory of a rocprofv3 --stats csv run: write the summary and exit")
+    ap.add_argument("--setup-summary", default=None,
+                    help="directory of a rocprofv3 --kernel-trace csv run: write the per-kernel "
+                         "breakdown of one setup and exit")
     ap.add_argument("--graphs", type=int, default=None, choices=[0, 1],
                     help="replay the cycle as a captured HIP graph (default: the library's)")
     ap.add_argument("--autotune", type=int, default=None, choices=[0, 1],
@@ -529,6 +599,8 @@ def main():
         return pmc_summary(args)
     if args.trace_summary:
         return trace_summary(args)
+    if args.setup_summary:
+        return setup_summary(args)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
