@@ -20,9 +20,11 @@ residual recomputed on the host, and against the oracle's FP64 solve where the
 oracle finishes in seconds (energy norm 1e-6 for FP64, 1e-5 for the mixed
 form, the stated bound).
 
-The 4M-vertex Chung-Lu workload itself is represented by the same generator
-at 2^20 vertices (15.3M nnz, largest degree 5.6e4): the oracle's setup of the
-full graph takes minutes of host time.
+The 4M-vertex Chung-Lu workload (the benchmark's default, 63.9M nnz, largest
+degree 6.9e4) runs in full, and the same generator at 2^20 vertices as a second
+power-law case.  The oracle here is its OpenMP build, which computes the same
+bits as the single-threaded one (test_oracle_threads.py) in a fraction of the
+host time.
 """
 
 import numpy as np
@@ -43,6 +45,8 @@ FULL = {
                                   seed=5, precision=lg.LG_MIXED, oracle_solve=False),
     "chunglu_1m": dict(graph=lambda: gg.chung_lu(1 << 20, seed=6), k=16, seed=6,
                        precision=lg.LG_MIXED, oracle_solve=True),
+    "chunglu_4m": dict(graph=lambda: gg.config_graph("chunglu_4m"), k=16, seed=6,
+                       precision=lg.LG_FP64, oracle_solve=True),
 }
 
 
@@ -62,7 +66,7 @@ def case(request, built):
     name = request.param
     g = FULL[name]["graph"]()
     say(f"[full] {name}: n={g.n} nnz={g.nnz} max degree={int(np.diff(g.row_ptr).max())}")
-    ho = oracle.Hierarchy(g, oracle_opts(lg.lg_default_opts()))
+    ho = oracle.Hierarchy(g, oracle_opts(lg.lg_default_opts()), threaded=True)
     yield name, g, ho
     del ho
 
