@@ -488,6 +488,40 @@ def test_lanczos_estimate_on_bipartite_grid():
     assert 1.8 < lm <= 2.0 + 1e-12
 
 
+def test_lanczos_estimate_does_not_depend_on_summation_order():
+    """lambda_max is a stored hierarchy value, so its sums are exact: a level
+    with every row's entries in another order gives the same bits.  The
+    levels of a 65,536-vertex Chung-Lu hierarchy are sensitive enough that
+    plain fp64 sums change the estimate's last bits under such a shuffle (the
+    coarse level 3 by 7e-16)."""
+    g = gg.chung_lu(1 << 16, seed=6)
+    ho = oracle.Hierarchy(g)
+    rng = np.random.default_rng(2)
+    checked = 0
+    for l, L in enumerate(ho.levels()):
+        if L.type != oracle.AGG:
+            continue
+        G, d = ho.csr(l)
+        col, w = G.col.copy(), G.w.copy()
+        for i in range(G.n):
+            a, b = G.row_ptr[i], G.row_ptr[i + 1]
+            p = a + rng.permutation(b - a)
+            col[a:b], w[a:b] = G.col[p], G.w[p]
+        shuffled = gg.Graph(G.n, G.row_ptr, col, w)
+        lm = oracle.lanczos_lmax(G, steps=10, level=l, d=d)
+        assert lm == L.lmax
+        assert oracle.lanczos_lmax(shuffled, steps=10, level=l, d=d) == lm, l
+        if G.n <= 2000:  # and it is an estimate from below of the true lambda_max
+            rows = np.repeat(np.arange(G.n), np.diff(G.row_ptr))
+            Ld = np.zeros((G.n, G.n))
+            Ld[rows, G.col] = -G.w
+            Ld[np.arange(G.n), np.arange(G.n)] = d
+            true = np.linalg.eigvals(Ld / d[:, None]).real.max()
+            assert 0.8 * true < lm <= true * (1 + 1e-12), (l, lm, true)
+        checked += 1
+    assert checked >= 2
+
+
 # -------------------------------------------------------------- smoother
 
 def test_chebyshev_damps_eigenvectors_by_the_chebyshev_ratio():
