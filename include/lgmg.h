@@ -268,11 +268,12 @@ const char* lg_last_error(void);
  * A worker thread, each with its own HIP stream, opens a session on the graph
  * of the oldest waiting request: one batched CG (as lg_solve) whose columns
  * are slots, as wide as the columns then queued for that graph (a power of
- * two, at most max_batch_rhs).  At every CG iteration boundary the columns
- * that have converged leave, a request completes when all its columns have,
- * and freed or idle slots take the next queued requests for the same graph,
- * tolerance and iteration cap (a request's columns enter together), unless a
- * request of another graph has waited longer and no worker is free.  Each
+ * two, at most max_batch_rhs), opened with every queued request of the graph
+ * that fits.  At every CG iteration boundary the columns that have converged
+ * leave, a request completes when all its columns have, and freed or idle
+ * slots take the next queued requests for the same graph, tolerance and
+ * iteration cap (a request's columns enter together), unless a request of
+ * another graph has waited longer and no worker is free.  Each
  * column runs its own CG (iteration cap, restarts, convergence test).
  * Sessions on different graphs overlap on the device.  A graph's hierarchy is
  * built on its first request and cached; it is admitted when it fits

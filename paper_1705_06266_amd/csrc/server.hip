@@ -252,8 +252,11 @@ struct lg_server::Session : lg::SlotFeed {
     if (s->stop && s->pending.empty()) return;
     for (auto it = s->pending.begin(); it != s->pending.end();) {
       Request* r = *it;
+      // opening: every queued request of the graph that fits (batch formation);
+      // later, a request joins unless another graph has waited longer with no
+      // worker free to take it
       if (r->gid == gid && r->rtol == rtol && r->max_iter == max_iter &&
-          (size_t)r->k <= free_slots.size() - next && s->may_join(r)) {
+          (size_t)r->k <= free_slots.size() - next && (opening || s->may_join(r))) {
         it = s->pending.erase(it);
         place(r);
         if (!opening) s->st.refills += r->k;
