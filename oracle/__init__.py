@@ -222,7 +222,8 @@ def elim_build(g, F, d=None):
     F8 = np.ascontiguousarray(F, dtype=np.uint8)
     nf = int(F8.sum())
     nc = g.n - nf
-    cap = g.nnz + 12 * nf + 1
+    deg = np.diff(rp)[F8.astype(bool)].astype(np.int64)
+    cap = g.nnz + int(np.sum(deg * (deg - 1))) + 1  # an eliminated vertex of degree k adds <= k(k-1) entries
     cidx = np.empty(g.n, dtype=np.int32)
     crp = np.zeros(nc + 1, dtype=np.int64)
     ccol = np.empty(cap, dtype=np.int32)

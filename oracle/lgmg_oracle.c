@@ -927,7 +927,9 @@ int lgo_setup(int64_t n, const int64_t* rp, const int32_t* col, const double* w,
                                    z, F);
       if ((double)nf > o->elim_min_fraction * (double)nl) {
         olevel* nxt = &h->lev[l + 1];
-        int64_t cap = cur->A.nnz + 12 * nf + 1;
+        /* an eliminated vertex of degree k adds at most k (k - 1) fill entries */
+        const int64_t kmax = o->elim_max_degree > 1 ? o->elim_max_degree : 1;
+        int64_t cap = cur->A.nnz + kmax * (kmax - 1) * nf + 1;
         nxt->A.rp = (int64_t*)xmalloc(sizeof(int64_t) * (size_t)(nl - nf + 1));
         nxt->A.col = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)cap);
         nxt->A.w = (double*)xmalloc(sizeof(double) * (size_t)cap);

@@ -429,3 +429,23 @@ def test_forced_row_shifts_match(built, name, shift):
             f"oracle {ito}; energy differences {d64:.1e} / {dmx:.1e}")
         assert abs(info[c]["iters"] - ito) <= 1 and d64 <= 1e-6
         assert infm[c]["rel_residual"] <= 1e-8 and dmx <= 1e-5
+
+
+@pytest.mark.parametrize("max_degree", [6, 10])
+@pytest.mark.parametrize("name", ["path_333", "chunglu_30k_hubs", "grid2d_64x64", "rmat_s12",
+                                  "grid3d_12_loguniform"])
+def test_elimination_of_higher_degree_matches(built, name, max_degree):
+    """Low-degree elimination with a larger degree bound (Section 3.4's
+    candidates of degree <= k for k > 4), one pass and repeated passes: the
+    hierarchy bit for bit (elimination products, Schur complements and every
+    level after them), a solve at the FP64 bar."""
+    for passes in (1, 3):
+        g, hg, ho = _pair(name, elim_max_degree=max_degree, elim_passes=passes)
+        sg = compare_hierarchies(hg, ho, setup_data=True)
+        say(f"  k={max_degree} passes={passes} levels={[(s['type'], s['n']) for s in sg]}")
+        b = gg.rhs(g.n, 1, 19)[:, 0]
+        X, info, st = lg.lg_solve(hg, to_dev(b[:, None]), rtol=1e-8, max_iter=300)
+        xo, sto, ito, relo, _ = ho.solve(b, 1e-8, 300)
+        xg = X.cpu().numpy()[:, 0]
+        assert st == 0 and sto == 0 and abs(info[0]["iters"] - ito) <= 1
+        assert dense_laplacian_norm(g, xg - xo) / dense_laplacian_norm(g, xo) <= 1e-6

@@ -243,12 +243,16 @@ def test_schur_degree_two_vertex_gives_series_edge():
     assert np.allclose(gc.w, 2.0 * 6.0 / 8.0, rtol=0, atol=1e-15)
 
 
-def test_schur_matches_dense_block_formula_and_two_level_identity():
+@pytest.mark.parametrize("max_degree", [4, 6, 10])
+def test_schur_matches_dense_block_formula_and_two_level_identity(max_degree):
+    top = 0  # highest degree eliminated over the graphs
     for mk in SMALL_GRAPHS:
         g = mk()
-        cnt, z, F = oracle.elim_select(g)
+        cnt, z, F = oracle.elim_select(g, max_degree=max_degree)
         if cnt == 0:
             continue
+        assert np.all(g.degrees()[F] <= max_degree)
+        top = max(top, int(g.degrees()[F].max()))
         cidx, gc, cd = oracle.elim_build(g, F)
         L = dense_L(g)
         Fi = np.nonzero(F)[0]
@@ -271,6 +275,7 @@ def test_schur_matches_dense_block_formula_and_two_level_identity():
         x = P @ np.linalg.pinv(schur) @ P.T @ b
         x[Fi] += b[Fi] / np.diag(LFF)
         assert np.linalg.norm(L @ x - b) <= 1e-9 * np.linalg.norm(b)
+    assert top > 4 or max_degree == 4, "the degree bound above 4 eliminated nothing above 4"
 
 
 # ------------------------------------------------------------------- SoC
