@@ -748,7 +748,32 @@ def measure(args, lg, dev, g, b_host, rp, col, w, B, workload, family, latency_s
     sp_n, sp_ms, sp_bytes = lg.lg_profile_read()
     lg.lg_profile_enable(None)
     spmv_gbs = sp_bytes / (sp_ms * 1e-3) / 1e9 if sp_ms > 0 else None
-    del h, x, y
+    del x, y
+    # the same product on every level (hub rows are processed in the same launch
+    # as the other rows), and the fraction each elimination level removes
+    by_level = []
+    for l, s in enumerate(stats):
+        if s["type"] == lg.LG_LEVEL_COARSEST:
+            continue
+        xl = torch.randn(s["n"], kk, dtype=torch.float64, device=dev)
+        yl = torch.empty_like(xl)
+        for _ in range(3):
+            lg.lg_spmv(h, l, xl, yl)
+        lg.lg_profile_enable("spmm")
+        for _ in range(20):
+            lg.lg_spmv(h, l, xl, yl)
+        torch.cuda.synchronize()
+        ln, lms, lbytes = lg.lg_profile_read()
+        lg.lg_profile_enable(None)
+        row = {"level": l, "type": "elim" if s["type"] == lg.LG_LEVEL_ELIM else "agg",
+               "n": s["n"], "nnz": s["nnz"], "hub_rows": s["n_hub"],
+               "spmm_us": lms / ln * 1e3 if ln else None,
+               "spmm_gbs": lbytes / (lms * 1e-3) / 1e9 if lms > 0 else None}
+        if s["type"] == lg.LG_LEVEL_ELIM:
+            row["eliminated_fraction"] = 1.0 - s["nc"] / s["n"]
+        by_level.append(row)
+        del xl, yl
+    del h
 
     achieved = fam_bytes / (fam_ms * 1e-3) / 1e9 if fam_ms > 0 else 0.0
     traffic = load_traffic(family, workload) if family == wl["family"] else None
@@ -789,6 +814,7 @@ def measure(args, lg, dev, g, b_host, rp, col, w, B, workload, family, latency_s
         "spmv_fp64_gbs": spmv_gbs,
         "spmv_fp64_ms": sp_ms / sp_n if sp_n else None,
         "spmv_fp64_rhs": kk,
+        "spmv_fp64_by_level": by_level,
         "hierarchy_bytes": hier_bytes,
         "levels": [(s["type"], s["n"], s["nnz"], s["lane_shift"], s["col_shift"], s["merge"])
                    for s in stats],

@@ -453,15 +453,16 @@ __global__ void k_alpha(double* __restrict__ scal, int flexible) {
   scal[S_ALPHA * K + c] = a;
 }
 
-// x += alpha p, r -= alpha q per column, with the column sums of r . r of the
-// new r, and rc = r in the cycle's precision when rc is set (one pass).
+// r -= alpha q per column, with the column sums of r . r of the new r, and
+// rc = r in the cycle's precision when rc is set.  The matching x += alpha p
+// is deferred to the next direction update (k_xpby_z), which reads p anyway,
+// or to k_update_x where x is needed before then.
 template <int K, typename TC>
-__global__ __launch_bounds__(kBlock) void k_update_xr(double* __restrict__ x, double* __restrict__ r,
-                                                      const double* __restrict__ p,
-                                                      const double* __restrict__ q,
-                                                      const double* __restrict__ scal, int64_t m,
-                                                      TC* __restrict__ rc,
-                                                      double* __restrict__ partial) {
+__global__ __launch_bounds__(kBlock) void k_update_r(double* __restrict__ r,
+                                                     const double* __restrict__ q,
+                                                     const double* __restrict__ scal, int64_t m,
+                                                     TC* __restrict__ rc,
+                                                     double* __restrict__ partial) {
   constexpr int V = 2;
   double s[1][V] = {{0.0, 0.0}};
   double a[V];
@@ -470,29 +471,24 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(double* __restrict__ x, do
   typedef TC tc2 __attribute__((ext_vector_type(2)));
   const int64_t nvec = m / V;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  // two vectors per trip (t and t + stride) so that eight loads are in flight
-  for (int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x; t0 < nvec; t0 += 2 * stride) {
-    typename Vec16<double>::type xv[2], rv[2], pv[2], qv[2];
-    const bool two = t0 + stride < nvec;
+  // four vectors per trip so that eight loads are in flight
+  for (int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x; t0 < nvec; t0 += 4 * stride) {
+    typename Vec16<double>::type rv[4], qv[4];
 #pragma unroll
-    for (int h = 0; h < 2; h++) {
-      const int64_t t = h && two ? t0 + stride : t0;
-      xv[h] = ld16(x + t * V);
+    for (int h = 0; h < 4; h++) {
+      const int64_t t = t0 + h * stride < nvec ? t0 + h * stride : t0;
       rv[h] = ld16(r + t * V);
-      pv[h] = ld16(p + t * V);
       qv[h] = ld16(q + t * V);
     }
 #pragma unroll
-    for (int h = 0; h < 2; h++) {
-      if (h && !two) break;
+    for (int h = 0; h < 4; h++) {
       const int64_t t = t0 + h * stride;
+      if (t >= nvec) break;
 #pragma unroll
       for (int v = 0; v < V; v++) {
-        xv[h][v] += a[v] * pv[h][v];
         rv[h][v] -= a[v] * qv[h][v];
         s[0][v] += rv[h][v] * rv[h][v];
       }
-      st16(x + t * V, xv[h]);
       st16(r + t * V, rv[h]);
       if (rc) {
         tc2 o;
@@ -504,14 +500,21 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(double* __restrict__ x, do
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {  // odd m (K = 1): last entry, column 0
     for (int64_t i = nvec * V; i < m; i++) {
-      const double al = scal[S_ALPHA * K + (int)(i % K)];
-      x[i] += al * p[i];
-      r[i] -= al * q[i];
+      r[i] -= scal[S_ALPHA * K + (int)(i % K)] * q[i];
       s[0][i % V] += r[i] * r[i];
       if (rc) rc[i] = (TC)r[i];
     }
   }
   col_partials<K, V, 1>(s, partial);
+}
+
+// x += alpha p per column: the deferred solution update where x is read
+// before the next direction update.
+template <int K>
+__global__ void k_update_x(double* __restrict__ x, const double* __restrict__ p,
+                           const double* __restrict__ scal, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < m) x[i] += scal[S_ALPHA * K + (int)(i % K)] * p[i];
 }
 
 // Column sums of z (the cycle's output, precision T), of z . y and of y, with
@@ -582,17 +585,24 @@ __global__ void k_beta_z(double* __restrict__ scal, double inv_n, int flexible, 
 }
 
 // p = (z - mean) + beta p, or p = z - mean where every column restarts
-// (all = 1) or the column's restart flag is set.
+// (all = 1) or the column's restart flag is set.  When x is set, first the
+// deferred x += alpha p with the direction being replaced.
 template <typename T, int K>
 __global__ void k_xpby_z(double* __restrict__ p, const T* __restrict__ z,
                          const double* __restrict__ scal, const double* __restrict__ flag,
-                         int all, int64_t m) {
+                         int all, int64_t m, double* __restrict__ x) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i0 = t * 2;
   if (i0 >= m) return;
   if (i0 + 1 < m) {
     typename Vec16<double>::type pv;
-    if (!all) pv = ld16(p + i0);
+    if (!all || x) pv = ld16(p + i0);
+    if (x) {
+      typename Vec16<double>::type xv = ld16(x + i0);
+#pragma unroll
+      for (int e = 0; e < 2; e++) xv[e] += scal[S_ALPHA * K + (int)((i0 + e) % K)] * pv[e];
+      st16(x + i0, xv);
+    }
 #pragma unroll
     for (int e = 0; e < 2; e++) {
       const int c = (int)((i0 + e) % K);
@@ -603,6 +613,7 @@ __global__ void k_xpby_z(double* __restrict__ p, const T* __restrict__ z,
     st16(p + i0, pv);
   } else {
     const int c = (int)(i0 % K);
+    if (x) x[i0] += scal[S_ALPHA * K + c] * p[i0];
     const double zp = (double)z[i0] - scal[S_MEAN * K + c];
     const bool fresh = all || (flag && flag[c] > 0.0);
     p[i0] = fresh ? zp : zp + scal[S_BETA * K + c] * p[i0];
@@ -1076,6 +1087,15 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
   };
   // z = M r, projected to mean zero, enters p = z + beta p without being stored
   const int nbz = dot_blocks<T>(m);
+  // The solution update x += alpha p of an iteration is deferred (see
+  // k_update_r): pending until the next direction update or a flush.
+  bool x_pending = false;
+  auto flush_x = [&]() {
+    if (!x_pending) return;
+    hipLaunchKernelGGL((k_update_x<K>), dim3(g), dim3(kBlock), 0, st, h->px, (const double*)h->pp,
+                       (const double*)sc, m);
+    x_pending = false;
+  };
   auto new_direction = [&](const T* z, bool first, const double* flags) {
     hipLaunchKernelGGL((k_zstats<T, K>), dim3(nbz), dim3(kBlock), 0, st, z,
                        (const double*)(flex && !first ? h->pq : h->pr), m, h->red);
@@ -1084,7 +1104,8 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     hipLaunchKernelGGL((k_beta_z<K>), dim3(1), dim3(64), 0, st, sc, 1.0 / (double)n, flex ? 1 : 0,
                        first ? 1 : 0);
     hipLaunchKernelGGL((k_xpby_z<T, K>), dim3(g2), dim3(kBlock), 0, st, h->pp, z, (const double*)sc,
-                       flags, first ? 1 : 0, m);
+                       flags, first ? 1 : 0, m, x_pending ? h->px : (double*)nullptr);
+    x_pending = false;
   };
 
   const double cw = cycle_work(h, 0);
@@ -1199,11 +1220,12 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     else dot64(h->pp, h->pq, S_PQ);
     hipLaunchKernelGGL((k_alpha<K>), dim3(1), dim3(64), 0, st, sc, flex ? 1 : 0);
     {
-      // reads x, r, p, q and writes x, r (fp64), plus r in the cycle's precision
-      ProfScope ps("cg_update", st, 48.0 * m + (mixed ? (double)sizeof(T) * m : 0.0));
-      hipLaunchKernelGGL((k_update_xr<K, T>), dim3(nb), dim3(kBlock), 0, st, h->px, h->pr,
-                         (const double*)h->pp, (const double*)h->pq, (const double*)sc, m,
+      // reads r, q and writes r (fp64), plus r in the cycle's precision
+      ProfScope ps("cg_update", st, 24.0 * m + (mixed ? (double)sizeof(T) * m : 0.0));
+      hipLaunchKernelGGL((k_update_r<K, T>), dim3(nb), dim3(kBlock), 0, st, h->pr,
+                         (const double*)h->pq, (const double*)sc, m,
                          mixed ? (T*)h->cyc_in : (T*)nullptr, h->red);
+      x_pending = true;
     }
     final1(S_RR);
     read_scal();
@@ -1227,6 +1249,7 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     bool restart = false;
     std::vector<double> rflag(K, 0.0);
     if (!newly.empty()) {
+      flush_x();
       lap64<K>(h, 0, h->px, h->pt, h->pb, st, "resid64");
       dot64(h->pt, h->pt, S_TR);
       read_scal();
@@ -1247,6 +1270,7 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
       write_slot(S_TR, zero);
     }
     if (feed) {  // hand finished columns back, refill their slots
+      flush_x();
       std::sort(done.begin(), done.end());
       store_cols(done);
       std::vector<int> free_slots;
@@ -1279,6 +1303,7 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     new_direction(z, false, restart ? (const double*)sl(S_RESTART) : nullptr);
     LG_LAUNCH_CHECK();
   }
+  flush_x();
   if (feed) {
     std::vector<int> left;  // only after a breakdown ended the loop early
     for (int c = 0; c < K; c++)
