@@ -97,6 +97,14 @@ typedef struct {
                                summation order inside a row, so a solve is bit-reproducible
                                given the shifts in lg_level_stats, and a tuned run can differ
                                from another process's in the last bits */
+  int32_t reorder;          /* 1: after setup, levels of at least 2^14 vertices whose largest
+                               degree is at least 8x their mean, and whose mean degree is at
+                               most 128, are stored in a solve-time
+                               vertex order (higher degree classes first, the setup's order
+                               kept within a class), so that the rows most entries gather
+                               share cache lines.  Every row keeps its entries in order, so
+                               each row's sum is unchanged; inputs, outputs and exports use
+                               the setup's numbering.  0: the setup's numbering throughout */
 } lg_setup_opts;
 
 typedef struct lg_hierarchy lg_hierarchy;
@@ -110,6 +118,7 @@ typedef struct {
   int64_t n_hub;   /* rows split across workgroups by the row scheduler */
   int32_t lane_shift, col_shift; /* row lanes 2^(class - shift) in use (set by the autotuner) */
   int32_t merge;                 /* 1: one-column products use the merge-path traversal */
+  int32_t reordered;             /* 1: stored in the solve-time vertex order (reorder option) */
 } lg_level_stats;
 
 typedef struct {

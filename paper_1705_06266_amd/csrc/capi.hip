@@ -60,6 +60,7 @@ extern "C" lg_status lg_default_opts(lg_setup_opts* o) {
   o->elim_passes = 1;
   o->merge_path = 0;
   o->row_shift = -1;
+  o->reorder = 1;
   return LG_OK;
 }
 
@@ -80,6 +81,7 @@ static const char* check_opts(const lg_setup_opts& o) {
   if (o.elim_passes < 1 || o.elim_passes > 16) return "elim_passes must be in 1..16";
   if (o.merge_path < 0 || o.merge_path > 2) return "merge_path must be 0, 1 or 2";
   if (o.row_shift < -1 || o.row_shift > 2) return "row_shift must be -1, 0, 1 or 2";
+  if (o.reorder < 0 || o.reorder > 1) return "reorder must be 0 or 1";
   return nullptr;
 }
 
@@ -208,6 +210,7 @@ extern "C" lg_status lg_hierarchy_stats(const lg_hierarchy* h, lg_level_stats* o
     out[l].lane_shift = L.sched.lane_shift;
     out[l].col_shift = L.sched.col_shift;
     out[l].merge = L.sched.merge ? 1 : 0;
+    out[l].reordered = L.perm ? 1 : 0;
   }
   return LG_OK;
 }
@@ -218,18 +221,61 @@ extern "C" lg_status lg_export_level(const lg_hierarchy* h, int32_t level, int64
   if (level < 0 || level >= (int)h->lev.size()) return arg_error("lg_export_level: bad level");
   LG_API_BEGIN
   const Level& L = h->lev[level];
-  if (row_ptr) {
-    std::vector<int32_t> rp(L.n + 1);
-    LG_HIP(hipMemcpy(rp.data(), L.rp, sizeof(int32_t) * (L.n + 1), hipMemcpyDeviceToHost));
-    for (int64_t i = 0; i <= L.n; i++) row_ptr[i] = rp[i];
+  const int64_t n = L.n;
+  const int32_t* src = L.type == LG_LEVEL_AGG ? L.agg : L.type == LG_LEVEL_ELIM ? L.cidx : nullptr;
+  if (map && !src) return arg_error("lg_export_level: the coarsest level has no map");
+  // Levels stored in the solve-time order are returned in the setup's
+  // numbering: row i of the solve order is row perm[i], its entries in
+  // their order (column perm[j] for stored column j).
+  auto fetch_perm = [](const int32_t* p, int64_t len) {
+    std::vector<int32_t> v;
+    if (p) {
+      v.resize(len);
+      LG_HIP(hipMemcpy(v.data(), p, sizeof(int32_t) * len, hipMemcpyDeviceToHost));
+    }
+    return v;
+  };
+  const std::vector<int32_t> perm = fetch_perm(L.perm, n);
+  std::vector<int32_t> rp(n + 1);
+  LG_HIP(hipMemcpy(rp.data(), L.rp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+  if (perm.empty()) {
+    if (row_ptr)
+      for (int64_t i = 0; i <= n; i++) row_ptr[i] = rp[i];
+    if (col && L.nnz) LG_HIP(hipMemcpy(col, L.col, sizeof(int32_t) * L.nnz, hipMemcpyDeviceToHost));
+    if (w && L.nnz) LG_HIP(hipMemcpy(w, L.w, sizeof(double) * L.nnz, hipMemcpyDeviceToHost));
+    if (d) LG_HIP(hipMemcpy(d, L.d, sizeof(double) * n, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<int64_t> orp(n + 1, 0);
+    for (int64_t i = 0; i < n; i++) orp[perm[i] + 1] = rp[i + 1] - rp[i];
+    for (int64_t i = 0; i < n; i++) orp[i + 1] += orp[i];
+    if (row_ptr)
+      for (int64_t i = 0; i <= n; i++) row_ptr[i] = orp[i];
+    if ((col || w) && L.nnz) {
+      std::vector<int32_t> cs(L.nnz);
+      std::vector<double> ws(L.nnz);
+      LG_HIP(hipMemcpy(cs.data(), L.col, sizeof(int32_t) * L.nnz, hipMemcpyDeviceToHost));
+      LG_HIP(hipMemcpy(ws.data(), L.w, sizeof(double) * L.nnz, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < n; i++)
+        for (int64_t k = 0; k < rp[i + 1] - rp[i]; k++) {
+          const int64_t to = orp[perm[i]] + k, from = rp[i] + k;
+          if (col) col[to] = perm[cs[from]];
+          if (w) w[to] = ws[from];
+        }
+    }
+    if (d) {
+      std::vector<double> ds(n);
+      LG_HIP(hipMemcpy(ds.data(), L.d, sizeof(double) * n, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < n; i++) d[perm[i]] = ds[i];
+    }
   }
-  if (col && L.nnz) LG_HIP(hipMemcpy(col, L.col, sizeof(int32_t) * L.nnz, hipMemcpyDeviceToHost));
-  if (w && L.nnz) LG_HIP(hipMemcpy(w, L.w, sizeof(double) * L.nnz, hipMemcpyDeviceToHost));
-  if (d) LG_HIP(hipMemcpy(d, L.d, sizeof(double) * L.n, hipMemcpyDeviceToHost));
   if (map) {
-    const int32_t* src = L.type == LG_LEVEL_AGG ? L.agg : L.type == LG_LEVEL_ELIM ? L.cidx : nullptr;
-    if (!src) return arg_error("lg_export_level: the coarsest level has no map");
-    LG_HIP(hipMemcpy(map, src, sizeof(int32_t) * L.n, hipMemcpyDeviceToHost));
+    const std::vector<int32_t> cperm = fetch_perm(h->lev[level + 1].perm, h->lev[level + 1].n);
+    std::vector<int32_t> ms(n);
+    LG_HIP(hipMemcpy(ms.data(), src, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; i++) {
+      const int32_t v = ms[i];
+      map[perm.empty() ? i : perm[i]] = (v >= 0 && !cperm.empty()) ? cperm[v] : v;
+    }
   }
   return LG_OK;
   LG_API_END

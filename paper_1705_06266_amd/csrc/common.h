@@ -860,6 +860,7 @@ void build_sched(Sched& s, const int32_t* rp, int64_t n, int64_t nnz, Arena& kee
 int* sched_stats(const int32_t* rp, int64_t n, const int64_t* n_dev, Arena& tmp, hipStream_t st);
 void sched_layout(Sched& s, const int* t, const int32_t* rp, int64_t n, int64_t nnz, bool tiles,
                   Arena& keep, Arena& tmp, hipStream_t st);
+void sched_fill(Sched& s, const int32_t* rp, Arena& tmp, hipStream_t st);
 // out[i] = sum_{j<i} in[j] for i <= n (out has n+1 entries); returns out[n] on the host
 // when want_total (synchronises the stream).
 int64_t scan_i64(const int64_t* in, int64_t* out, int64_t n, Arena& tmp, hipStream_t st,

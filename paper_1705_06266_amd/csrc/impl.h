@@ -45,6 +45,10 @@ struct Level {
   float* ptcf = nullptr;
   Sched ptsched;
   int64_t nF = 0, nnzP = 0;
+  // solve-time vertex order (null: the setup's numbering): perm[new] = old
+  // and iperm[old] = new; every array above is stored in the new numbering
+  int32_t* perm = nullptr;
+  int32_t* iperm = nullptr;
   double lmax = 0.0;
   // column-split smoothing from a zero guess: 1 = the first iterate stored by
   // an elementwise pass, then one product (no D^-1 gather per entry); 0 = both
@@ -148,6 +152,7 @@ lg_status solve_dispatch(lg_hierarchy* h, const double* B, double* X, int k, dou
                          int max_iter, hipStream_t st, lg_rhs_info* info);
 void cycle_dispatch(lg_hierarchy* h, const double* B, double* X, int k, hipStream_t st);
 void spmv_dispatch(lg_hierarchy* h, int level, const double* X, double* Y, int k, hipStream_t st);
+void spmv_ordered(lg_hierarchy* h, int level, const double* X, double* Y, int k, hipStream_t st);
 void autotune(lg_hierarchy* h, hipStream_t st);
 lg_status eigs_dispatch(lg_hierarchy* h, int nev, double tol, int max_iter, double* X,
                         double* lambda, int* iters, double* resid, hipStream_t st);

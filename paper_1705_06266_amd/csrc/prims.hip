@@ -980,38 +980,50 @@ void sched_layout(Sched& s, const int* t, const int32_t* rp, int64_t n, int64_t 
   }
   s.ct.cls_start[kClasses] = (int32_t)pos;
   s.ct.blk_start[kClasses] = (int32_t)blk;
-  // rows grouped by class, hubs and split rows listed: one pass (k_class_perm)
-  {
-    int* ctr = tmp.get<int>(kClasses + 2);
-    hipLaunchKernelGGL(k_zero_i32n, dim3(1), dim3(kBlock), 0, st, (int32_t*)ctr,
-                       (int64_t)(kClasses + 2));
-    s.perm = keep.get<int32_t>(pos);
-    s.hub_rows = s.nhub ? keep.get<int32_t>(s.nhub) : nullptr;
-    s.split_rows = s.nsplit ? keep.get<int32_t>(s.nsplit) : nullptr;
-    int32_t* nch = s.nsplit ? tmp.get<int32_t>(s.nsplit) : nullptr;
-    const int ipt = perm_ipt(n);
-    hipLaunchKernelGGL(k_class_perm, dim3((unsigned)ceil_div(n, (int64_t)ipt * kBlock)), dim3(kBlock),
-                       0, st, rp, n, ipt, s.hub_deg, s.ct, ctr, s.perm, s.hub_rows, s.split_rows, nch);
-    LG_LAUNCH_CHECK();
-    if (s.nsplit) {
-      int64_t* start = tmp.get<int64_t>(s.nsplit + 1);
-      scan_i32_to_i64(nch, start, s.nsplit, tmp, st, false);
-      s.split_cptr = keep.get<int32_t>(s.nsplit + 1);
-      s.chunk_split = keep.get<int32_t>(s.nchunk);
-      s.partial = keep.alloc((size_t)s.nchunk * kPartialBytes);
-      hipLaunchKernelGGL(k_split_chunk_owner, dim3((unsigned)ceil_div(s.nsplit + 1, kBlock)),
-                         dim3(kBlock), 0, st, (const int32_t*)nch, (const int64_t*)start, s.nsplit,
-                         s.split_cptr, s.chunk_split);
-      LG_LAUNCH_CHECK();
-    }
+  s.perm = keep.get<int32_t>(pos);
+  s.hub_rows = s.nhub ? keep.get<int32_t>(s.nhub) : nullptr;
+  s.split_rows = s.nsplit ? keep.get<int32_t>(s.nsplit) : nullptr;
+  if (s.nsplit) {
+    s.split_cptr = keep.get<int32_t>(s.nsplit + 1);
+    s.chunk_split = keep.get<int32_t>(s.nchunk);
+    s.partial = keep.alloc((size_t)s.nchunk * kPartialBytes);
   }
   if (tiles) {  // merge-path tiles
     s.ntile = ceil_div(n + nnz, kMergeTile);
     s.tile_row = keep.get<int32_t>(s.ntile + 1);
     s.carry_row = keep.get<int32_t>(s.ntile);
     s.carry_val = keep.get<double>(s.ntile);
+  }
+  sched_fill(s, rp, tmp, st);
+  tmp.rewind(m);
+}
+
+// The row lists of a laid-out schedule from rp: rows grouped by class, hubs
+// and split rows listed (one pass, k_class_perm), the split rows' chunk
+// owners and the merge-path tiles.  Rerun after the rows are renumbered with
+// their degrees kept.
+void sched_fill(Sched& s, const int32_t* rp, Arena& tmp, hipStream_t st) {
+  if (s.n == 0) return;
+  Arena::Mark m = tmp.mark();
+  int* ctr = tmp.get<int>(kClasses + 2);
+  hipLaunchKernelGGL(k_zero_i32n, dim3(1), dim3(kBlock), 0, st, (int32_t*)ctr,
+                     (int64_t)(kClasses + 2));
+  int32_t* nch = s.nsplit ? tmp.get<int32_t>(s.nsplit) : nullptr;
+  const int ipt = perm_ipt(s.n);
+  hipLaunchKernelGGL(k_class_perm, dim3((unsigned)ceil_div(s.n, (int64_t)ipt * kBlock)), dim3(kBlock),
+                     0, st, rp, s.n, ipt, s.hub_deg, s.ct, ctr, s.perm, s.hub_rows, s.split_rows, nch);
+  LG_LAUNCH_CHECK();
+  if (s.nsplit) {
+    int64_t* start = tmp.get<int64_t>(s.nsplit + 1);
+    scan_i32_to_i64(nch, start, s.nsplit, tmp, st, false);
+    hipLaunchKernelGGL(k_split_chunk_owner, dim3((unsigned)ceil_div(s.nsplit + 1, kBlock)),
+                       dim3(kBlock), 0, st, (const int32_t*)nch, (const int64_t*)start, s.nsplit,
+                       s.split_cptr, s.chunk_split);
+    LG_LAUNCH_CHECK();
+  }
+  if (s.tile_row) {
     hipLaunchKernelGGL(k_merge_split, dim3((unsigned)ceil_div(s.ntile + 1, kBlock)), dim3(kBlock), 0,
-                       st, rp, n, nnz, s.ntile, s.tile_row);
+                       st, rp, s.n, s.nnz, s.ntile, s.tile_row);
     LG_LAUNCH_CHECK();
   }
   tmp.rewind(m);

@@ -1018,6 +1018,83 @@ __global__ void k_copy_f64(const double* __restrict__ in, double* __restrict__ o
   if (i < n) out[i] = in[i];
 }
 
+
+// ------------------------------------------------ solve-time vertex order
+// Key of a row in the solve order: split rows, hub rows, then degree classes
+// from the highest down (ties keep the setup's order: the sort is stable).
+__global__ void k_order_keys(const int32_t* __restrict__ rp, int64_t n, int hub_deg,
+                             uint64_t* __restrict__ keys, uint64_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int d = rp[i + 1] - rp[i];
+  const int c = degree_class(d, hub_deg);
+  keys[i] = c >= kClasses ? (d > kSplitDeg ? 0u : 1u) : (uint64_t)(2 + (kClasses - 1 - c));
+  vals[i] = (uint64_t)i;
+}
+
+// perm[new] = old from the sorted pairs, and iperm[old] = new.
+__global__ void k_order_perm(const uint64_t* __restrict__ vals, int64_t n, int32_t* __restrict__ perm,
+                             int32_t* __restrict__ iperm) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int32_t o = (int32_t)vals[i];
+  perm[i] = o;
+  iperm[o] = (int32_t)i;
+}
+
+// deg[new] = length of old row perm[new].
+__global__ void k_perm_degrees(const int32_t* __restrict__ ptr, const int32_t* __restrict__ perm,
+                               int64_t nr, int32_t* __restrict__ deg) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nr) return;
+  const int64_t r = perm ? perm[i] : i;
+  deg[i] = ptr[r + 1] - ptr[r];
+}
+
+__global__ void k_i64_to_i32(const int64_t* __restrict__ in, int64_t n, int32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] = (int32_t)in[i];
+}
+
+// Entry e of old row r moves to new row rmap[r] at the same offset; its index
+// maps through emap and its value follows (run over the old rows).
+struct PermEntriesOp {
+  using Acc = NoAcc;
+  const int32_t* __restrict__ ptr0;
+  const int32_t* __restrict__ idx0;
+  const double* __restrict__ val0;
+  const int32_t* __restrict__ rmap;
+  const int32_t* __restrict__ emap;
+  const int32_t* __restrict__ ptr;
+  int32_t* __restrict__ idx;
+  double* __restrict__ val;
+  __device__ Acc identity() const { return {0}; }
+  __device__ bool active(int64_t) const { return true; }
+  __device__ void accum(Acc&, int64_t row, int e) const {
+    const int64_t dst = (int64_t)ptr[rmap ? rmap[row] : row] + (e - ptr0[row]);
+    const int32_t j = idx0[e];
+    idx[dst] = emap ? emap[j] : j;
+    if (val) val[dst] = val0[e];
+  }
+  __device__ void combine(Acc&, const Acc&) const {}
+  __device__ void finish(int64_t, const Acc&, int, int) const {}
+};
+
+// dst[new] = src[perm[new]], mapped through map where it is an index (>= 0).
+__global__ void k_perm_index(const int32_t* __restrict__ src, const int32_t* __restrict__ perm,
+                             const int32_t* __restrict__ map, int64_t n, int32_t* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int32_t v = src[perm ? perm[i] : i];
+  dst[i] = (v >= 0 && map) ? map[v] : v;
+}
+
+__global__ void k_perm_f64(const double* __restrict__ src, const int32_t* __restrict__ perm, int64_t n,
+                           double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) dst[i] = src[perm[i]];
+}
+
 // ===================================================================== host
 namespace {
 
@@ -1027,6 +1104,7 @@ namespace {
 struct SideStream {
   hipStream_t s = nullptr;
   hipEvent_t ready = nullptr, done = nullptr;
+  std::vector<hipEvent_t> level_done;  // per level: its Lanczos steps are done
   SideStream() = default;
   SideStream(const SideStream&) = delete;
   SideStream& operator=(const SideStream&) = delete;
@@ -1034,6 +1112,8 @@ struct SideStream {
     if (s) (void)hipStreamSynchronize(s);
     if (ready) (void)hipEventDestroy(ready);
     if (done) (void)hipEventDestroy(done);
+    for (hipEvent_t e : level_done)
+      if (e) (void)hipEventDestroy(e);
   }
 };
 
@@ -1383,6 +1463,9 @@ void lanczos(Ctx& c, Level& L, int level, double* out) {
   hipLaunchKernelGGL(k_lz_init_scalars, dim3(1), dim3(64), 0, st, lz);
   if (n < 2 || steps < 1) {
     hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(64), 0, st, lz, out);
+    if ((int)c.side.level_done.size() <= level) c.side.level_done.resize(level + 1, nullptr);
+    LG_HIP(hipEventCreateWithFlags(&c.side.level_done[level], hipEventDisableTiming));
+    LG_HIP(hipEventRecord(c.side.level_done[level], st));
     return;
   }
   const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, ceil_div(n, kBlock)));
@@ -1413,6 +1496,10 @@ void lanczos(Ctx& c, Level& L, int level, double* out) {
   }
   hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(64), 0, st, lz, out);
   LG_LAUNCH_CHECK();
+  // the point after which the level may be rewritten (solve order)
+  if ((int)c.side.level_done.size() <= level) c.side.level_done.resize(level + 1, nullptr);
+  LG_HIP(hipEventCreateWithFlags(&c.side.level_done[level], hipEventDisableTiming));
+  LG_HIP(hipEventRecord(c.side.level_done[level], st));
 }
 
 void coarsest(Ctx& c, Level& L) {
@@ -1443,6 +1530,129 @@ void coarsest(Ctx& c, Level& L) {
   hipLaunchKernelGGL(k_sub_shift, dim3(nblk(n * n)), dim3(kBlock), 0, c.st, h->Lplus, n * n, n,
                      shift);
   LG_LAUNCH_CHECK();
+}
+
+
+// A CSR (nr rows, ne entries; val optional) renumbered in place: the new row
+// i holds the old row rperm[i] (rmap is its inverse; both null: rows keep
+// their places), entries keep their order within the row, and their indices
+// map through emap (null: unchanged).  sched is the old row schedule (for the
+// entries' rows); its row lists are rebuilt for the new numbering.
+void permute_csr(Ctx& c, Sched& sched, int32_t* ptr, int32_t* idx, double* val, int64_t nr,
+                 int64_t ne, const int32_t* rperm, const int32_t* rmap, const int32_t* emap) {
+  Arena& tmp = c.tmp;
+  Arena::Mark m = tmp.mark();
+  if (nr == 0) return;
+  int32_t* ptr0 = tmp.get<int32_t>(nr + 1);
+  LG_HIP(hipMemcpyAsync(ptr0, ptr, sizeof(int32_t) * (nr + 1), hipMemcpyDeviceToDevice, c.st));
+  if (ne > 0) {
+    int32_t* idx0 = tmp.get<int32_t>(ne);
+    LG_HIP(hipMemcpyAsync(idx0, idx, sizeof(int32_t) * ne, hipMemcpyDeviceToDevice, c.st));
+    double* val0 = nullptr;
+    if (val) {
+      val0 = tmp.get<double>(ne);
+      LG_HIP(hipMemcpyAsync(val0, val, sizeof(double) * ne, hipMemcpyDeviceToDevice, c.st));
+    }
+    if (rperm) {
+      int32_t* deg = tmp.get<int32_t>(nr);
+      int64_t* p64 = tmp.get<int64_t>(nr + 1);
+      hipLaunchKernelGGL(k_perm_degrees, dim3(nblk(nr)), dim3(kBlock), 0, c.st, ptr0, rperm, nr, deg);
+      scan_i32_to_i64(deg, p64, nr, tmp, c.st, false);
+      hipLaunchKernelGGL(k_i64_to_i32, dim3(nblk(nr + 1)), dim3(kBlock), 0, c.st, p64, nr + 1, ptr);
+    }
+    // over the old rows (the old schedule still describes ptr0)
+    run_rows(sched, ptr0,
+             PermEntriesOp{ptr0, idx0, val0, rmap, emap, (const int32_t*)ptr, idx, val}, c.st);
+    LG_LAUNCH_CHECK();
+  } else if (rperm) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblk(nr + 1)), dim3(kBlock), 0, c.st, ptr, nr + 1, 0);
+  }
+  if (rperm) sched_fill(sched, ptr, tmp, c.st);
+  tmp.rewind(m);
+}
+
+// Levels of at least this many vertices whose degrees are skewed and whose
+// mean degree is moderate get the solve order.  Smaller levels are cache
+// resident; near-regular ones, such as grids, keep the locality of their own
+// numbering; on dense levels every row gathers from most of the vector
+// whatever the order.
+constexpr int64_t kReorderMinRows = (int64_t)1 << 14;
+constexpr int64_t kReorderSkew = 8;       // largest degree >= kReorderSkew x mean degree
+constexpr int64_t kReorderMaxMean = 128;  // mean degree at most this
+
+bool wants_order(const Level& L) {
+  if (L.type == LG_LEVEL_COARSEST || L.n < kReorderMinRows || L.nnz == 0) return false;
+  return (int64_t)L.sched.max_deg * L.n >= kReorderSkew * L.nnz && L.nnz <= kReorderMaxMean * L.n;
+}
+
+// The solve-time vertex order of every level that wants one: computed in the
+// setup's numbering, then the level's matrix, diagonal, transfer maps and
+// row schedules are renumbered.  Each row keeps its entries in their order,
+// so every row's sum (products, restriction, elimination transfers) is formed
+// exactly as in the setup's numbering.
+void reorder_levels(Ctx& c) {
+  lg_hierarchy* h = c.h;
+  Arena& tmp = c.tmp;
+  const int nl = (int)h->lev.size();
+  for (Level& L : h->lev) {
+    if (!wants_order(L)) continue;
+    Arena::Mark m = tmp.mark();
+    uint64_t* keys = tmp.get<uint64_t>(L.n);
+    uint64_t* vals = tmp.get<uint64_t>(L.n);
+    hipLaunchKernelGGL(k_order_keys, dim3(nblk(L.n)), dim3(kBlock), 0, c.st, L.rp, L.n,
+                       L.sched.hub_deg, keys, vals);
+    const SortedPairs sp = radix_sort_pairs(keys, vals, L.n, {0}, tmp, c.st);
+    L.perm = h->mem.get<int32_t>(L.n);
+    L.iperm = h->mem.get<int32_t>(L.n);
+    hipLaunchKernelGGL(k_order_perm, dim3(nblk(L.n)), dim3(kBlock), 0, c.st, (const uint64_t*)sp.vals,
+                       L.n, L.perm, L.iperm);
+    LG_LAUNCH_CHECK();
+    tmp.rewind(m);
+  }
+  for (int l = 0; l + 1 < nl; l++) {
+    Level& L = h->lev[l];
+    const Level& C = h->lev[l + 1];
+    if (!L.perm && !C.perm) continue;
+    const int64_t n = L.n;
+    // the level's matrix and diagonal, once its Lanczos steps (which read
+    // them on the side stream) are done
+    if (L.perm) {
+      if (l < (int)c.side.level_done.size() && c.side.level_done[l])
+        LG_HIP(hipStreamWaitEvent(c.st, c.side.level_done[l], 0));
+      permute_csr(c, L.sched, L.rp, L.col, L.w, n, L.nnz, L.perm, L.iperm, L.iperm);
+      Arena::Mark m = tmp.mark();
+      double* t = tmp.get<double>(n);
+      for (double* v : {L.d, L.dinv}) {
+        LG_HIP(hipMemcpyAsync(t, v, sizeof(double) * n, hipMemcpyDeviceToDevice, c.st));
+        hipLaunchKernelGGL(k_perm_f64, dim3(nblk(n)), dim3(kBlock), 0, c.st, (const double*)t,
+                           (const int32_t*)L.perm, n, v);
+      }
+      LG_LAUNCH_CHECK();
+      tmp.rewind(m);
+    }
+    Arena::Mark m = tmp.mark();
+    int32_t* t = tmp.get<int32_t>(std::max<int64_t>(n, L.nc));
+    if (L.type == LG_LEVEL_AGG) {
+      // aggregate of each (new) vertex, in the coarse level's new numbering
+      LG_HIP(hipMemcpyAsync(t, L.agg, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.st));
+      hipLaunchKernelGGL(k_perm_index, dim3(nblk(n)), dim3(kBlock), 0, c.st, (const int32_t*)t,
+                         (const int32_t*)L.perm, (const int32_t*)C.iperm, n, L.agg);
+      // members of each coarse vertex (restriction), in their order
+      permute_csr(c, L.msched, L.mptr, L.mem, nullptr, L.nc, n, C.perm, C.iperm, L.iperm);
+    } else {
+      // coarse index of each fine vertex, fine vertex of each coarse one
+      LG_HIP(hipMemcpyAsync(t, L.cidx, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.st));
+      hipLaunchKernelGGL(k_perm_index, dim3(nblk(n)), dim3(kBlock), 0, c.st, (const int32_t*)t,
+                         (const int32_t*)L.perm, (const int32_t*)C.iperm, n, L.cidx);
+      LG_HIP(hipMemcpyAsync(t, L.cvert, sizeof(int32_t) * L.nc, hipMemcpyDeviceToDevice, c.st));
+      hipLaunchKernelGGL(k_perm_index, dim3(nblk(L.nc)), dim3(kBlock), 0, c.st, (const int32_t*)t,
+                         (const int32_t*)C.perm, (const int32_t*)L.iperm, L.nc, L.cvert);
+      // the F part of P^T over coarse rows
+      permute_csr(c, L.ptsched, L.ptrp, L.ptf, L.ptc, L.nc, L.nnzP - L.nc, C.perm, C.iperm, L.iperm);
+    }
+    LG_LAUNCH_CHECK();
+    tmp.rewind(m);
+  }
 }
 
 void make_f32(Ctx& c, Level& L) {
@@ -1592,6 +1802,8 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
   h->lev[l].type = LG_LEVEL_COARSEST;
   h->lev[l].nc = 0;
   coarsest(c, h->lev[l]);
+  // the solve order rewrites a level after its own Lanczos steps (side stream)
+  if (o.reorder) reorder_levels(c);
   if (o.precision == LG_MIXED)
     for (int i = 0; i < l; i++) make_f32(c, h->lev[i]);
   LG_HIP(hipEventRecord(c.side.done, c.side.s));

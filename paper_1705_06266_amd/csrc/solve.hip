@@ -326,22 +326,25 @@ __global__ void k_fill(T* __restrict__ p, int64_t m, T v) {
   if (i < m) p[i] = v;
 }
 
+// The caller's n x k block into the solve's n x K workspace (zero padded),
+// row i of the solve order taking the caller's row perm[i] (perm null: i).
 __global__ void k_pad_in(const double* __restrict__ B, int k, double* __restrict__ out, int K,
-                         int64_t n) {
+                         int64_t n, const int32_t* __restrict__ perm) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n * K) return;
   const int64_t row = i / K;
   const int c = (int)(i - row * K);
-  out[i] = c < k ? B[row * k + c] : 0.0;
+  out[i] = c < k ? B[(perm ? (int64_t)perm[row] : row) * k + c] : 0.0;
 }
 
+// Back: the caller's row i from the solve order's row iperm[i].
 __global__ void k_pad_out(const double* __restrict__ in, int K, double* __restrict__ X, int k,
-                          int64_t n) {
+                          int64_t n, const int32_t* __restrict__ iperm) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n * k) return;
   const int64_t row = i / k;
   const int c = (int)(i - row * k);
-  X[i] = in[row * K + c];
+  X[i] = in[(iperm ? (int64_t)iperm[row] : row) * K + c];
 }
 
 // Deterministic column reductions.  A pass over an n x K multi-vector runs a
@@ -623,9 +626,9 @@ __global__ void k_xpby_z(double* __restrict__ p, const T* __restrict__ z,
 // Slot mode: column `slot` of the n x K multi-vector b takes B[i * ldb].
 template <int K>
 __global__ void k_load_col(double* __restrict__ b, int slot, const double* __restrict__ B, int ldb,
-                           int64_t n) {
+                           int64_t n, const int32_t* __restrict__ perm) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) b[i * K + slot] = B[i * ldb];
+  if (i < n) b[i * K + slot] = B[(perm ? (int64_t)perm[i] : i) * ldb];
 }
 
 // v -= its column mean in the flagged columns only.
@@ -652,9 +655,10 @@ __global__ void k_refill_cols(double* __restrict__ x, double* __restrict__ t,
 // arithmetic as the projection at the end of a plain solve).
 template <int K>
 __global__ void k_store_col(const double* __restrict__ x, int slot, const double* __restrict__ sums,
-                            int64_t n, double* __restrict__ X, int ldx) {
+                            int64_t n, double* __restrict__ X, int ldx,
+                            const int32_t* __restrict__ iperm) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) X[i * ldx] = x[i * K + slot] - sums[slot] / (double)n;
+  if (i < n) X[i * ldx] = x[(iperm ? (int64_t)iperm[i] : i) * K + slot] - sums[slot] / (double)n;
 }
 
 // dst = src in the columns whose flag is set (columns never influence each other)
@@ -1129,7 +1133,7 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     for (const SlotFeed::Col& c : in) {
       dst[c.slot] = c;
       hipLaunchKernelGGL((k_load_col<K>), dim3(nblk(n)), dim3(kBlock), 0, st, h->pb, c.slot, c.B,
-                         c.ldb, n);
+                         c.ldb, n, (const int32_t*)L0.perm);
     }
     write_slot(S_FILL, f);
     hipLaunchKernelGGL((k_dots<double, K, 1>), dim3(nb), dim3(kBlock), 0, st, h->pb,
@@ -1162,7 +1166,8 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     final1(S_TMP);
     for (int c : done)
       hipLaunchKernelGGL((k_store_col<K>), dim3(nblk(n)), dim3(kBlock), 0, st, (const double*)h->px,
-                         c, (const double*)sl(S_TMP), n, dst[c].X, dst[c].ldx);
+                         c, (const double*)sl(S_TMP), n, dst[c].X, dst[c].ldx,
+                         (const int32_t*)L0.iperm);
     LG_LAUNCH_CHECK();
     LG_HIP(hipStreamSynchronize(st));
     for (int c : done) {
@@ -1197,7 +1202,8 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     for (int c : done) dst[c] = SlotFeed::Col{};
     LG_HIP(hipMemcpyAsync(h->pr, h->pt, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
   } else {
-    hipLaunchKernelGGL(k_pad_in, dim3(g), dim3(kBlock), 0, st, B, k, h->pb, K, n);
+    hipLaunchKernelGGL(k_pad_in, dim3(g), dim3(kBlock), 0, st, B, k, h->pb, K, n,
+                       (const int32_t*)L0.perm);
     project64(h->pb);
     dot64(h->pb, h->pb, S_BN);
     read_scal();
@@ -1333,7 +1339,7 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
   }
   project64(h->px);
   hipLaunchKernelGGL(k_pad_out, dim3(nblk(n * k)), dim3(kBlock), 0, st, (const double*)h->px, K, X,
-                     k, n);
+                     k, n, (const int32_t*)L0.iperm);
   LG_LAUNCH_CHECK();
   LG_HIP(hipStreamSynchronize(st));
   if (info) {
@@ -1351,7 +1357,9 @@ template <typename T, int K>
 void cycle_once(lg_hierarchy* h, const double* B, double* X, int k, hipStream_t st) {
   Engine<T, K> eng{h, st};
   const int64_t n = h->lev[0].n;
-  hipLaunchKernelGGL(k_pad_in, dim3(nblk(n * K)), dim3(kBlock), 0, st, B, k, h->pb, K, n);
+  const Level& L0 = h->lev[0];
+  hipLaunchKernelGGL(k_pad_in, dim3(nblk(n * K)), dim3(kBlock), 0, st, B, k, h->pb, K, n,
+                     (const int32_t*)L0.perm);
   const T* z = eng.precond(h->pb, false);
   const double* z64 = (const double*)z;
   if (sizeof(T) != sizeof(double)) {
@@ -1359,7 +1367,8 @@ void cycle_once(lg_hierarchy* h, const double* B, double* X, int k, hipStream_t 
                        n * K);
     z64 = h->pz;
   }
-  hipLaunchKernelGGL(k_pad_out, dim3(nblk(n * k)), dim3(kBlock), 0, st, z64, K, X, k, n);
+  hipLaunchKernelGGL(k_pad_out, dim3(nblk(n * k)), dim3(kBlock), 0, st, z64, K, X, k, n,
+                     (const int32_t*)L0.iperm);
   LG_LAUNCH_CHECK();
 }
 
@@ -1428,6 +1437,31 @@ void cycle_dispatch(lg_hierarchy* h, const double* B, double* X, int k, hipStrea
 }
 
 void spmv_dispatch(lg_hierarchy* h, int level, const double* X, double* Y, int k, hipStream_t st) {
+  if (k < 1 || k > 32 || (k & (k - 1))) fail(LG_E_ARG, "lg_spmv: k must be 1, 2, 4, 8, 16 or 32");
+  const Level& L = h->lev[level];
+  if (L.perm) {
+    // X and Y are in the setup's numbering: the product runs on copies in the
+    // level's solve order (the solve workspace when it is large enough)
+    const int64_t m = L.n * k;
+    Arena::Mark mark = h->mem.mark();
+    const bool fits = m <= h->lev[0].n * (int64_t)h->K;
+    double* xs = fits ? h->pt : h->mem.get<double>(m);
+    double* ys = fits ? h->pz : h->mem.get<double>(m);
+    hipLaunchKernelGGL(k_pad_in, dim3(nblk(m)), dim3(kBlock), 0, st, X, k, xs, k, L.n,
+                       (const int32_t*)L.perm);
+    spmv_ordered(h, level, xs, ys, k, st);
+    hipLaunchKernelGGL(k_pad_out, dim3(nblk(m)), dim3(kBlock), 0, st, (const double*)ys, k, Y, k, L.n,
+                       (const int32_t*)L.iperm);
+    LG_LAUNCH_CHECK();
+    if (!fits) LG_HIP(hipStreamSynchronize(st));  // before the arena reuses the copies
+    h->mem.rewind(mark);
+    return;
+  }
+  spmv_ordered(h, level, X, Y, k, st);
+}
+
+// Y = L_level X with X and Y in the level's stored (solve) order.
+void spmv_ordered(lg_hierarchy* h, int level, const double* X, double* Y, int k, hipStream_t st) {
   switch (k) {
     case 1: lap64<1, 1>(h, level, X, Y, nullptr, st, "spmm"); break;
     case 2: lap64<2, 1>(h, level, X, Y, nullptr, st, "spmm"); break;
@@ -1513,7 +1547,7 @@ static void autotune_k(lg_hierarchy* h, hipStream_t st) {
     const bool try_merge = K == 1 && h->opts.merge_path == 1;
     const std::vector<int64_t> key{L.n, L.nnz, L.sched.min_deg, L.sched.max_deg, L.sched.nhub,
                                    L.sched.nsplit, agg ? (int64_t)sizeof(T) : 8, K, col ? 1 : 0,
-                                   h->opts.merge_path};
+                                   h->opts.merge_path, L.perm ? 1 : 0};
     {
       std::lock_guard<std::mutex> g(g_tune_mu);
       auto it = g_tune.find(key);

@@ -38,10 +38,11 @@ def test_struct_layouts_match_the_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "lgmg.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(lg_setup_opts),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(lg_setup_opts),"
         " offsetof(lg_setup_opts, seed), offsetof(lg_setup_opts, merge_path),"
-        " offsetof(lg_setup_opts, row_shift), sizeof(lg_graph),"
-        " sizeof(lg_level_stats), sizeof(lg_rhs_info), sizeof(lg_server_opts),"
+        " offsetof(lg_setup_opts, row_shift), offsetof(lg_setup_opts, reorder), sizeof(lg_graph),"
+        " sizeof(lg_level_stats), offsetof(lg_level_stats, reordered), sizeof(lg_rhs_info),"
+        " sizeof(lg_server_opts),"
         " offsetof(lg_server_opts, setup), sizeof(lg_server_stats),"
         " offsetof(lg_server_stats, resident_graphs), offsetof(lg_server_stats, refills));"
         " return 0;}\n")
@@ -50,8 +51,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(lg.lg_setup_opts), lg.lg_setup_opts.seed.offset,
             lg.lg_setup_opts.merge_path.offset, lg.lg_setup_opts.row_shift.offset,
-            C.sizeof(lg.lg_graph), C.sizeof(lg.lg_level_stats),
-            C.sizeof(lg.lg_rhs_info), C.sizeof(lg.lg_server_opts), lg.lg_server_opts.setup.offset,
+            lg.lg_setup_opts.reorder.offset, C.sizeof(lg.lg_graph), C.sizeof(lg.lg_level_stats),
+            lg.lg_level_stats.reordered.offset, C.sizeof(lg.lg_rhs_info), C.sizeof(lg.lg_server_opts), lg.lg_server_opts.setup.offset,
             C.sizeof(lg.lg_server_stats), lg.lg_server_stats.resident_graphs.offset,
             lg.lg_server_stats.refills.offset]
     assert got == want

@@ -449,3 +449,68 @@ def test_elimination_of_higher_degree_matches(built, name, max_degree):
         xg = X.cpu().numpy()[:, 0]
         assert st == 0 and sto == 0 and abs(info[0]["iters"] - ito) <= 1
         assert dense_laplacian_norm(g, xg - xo) / dense_laplacian_norm(g, xo) <= 1e-6
+
+
+REORDER_CASES = {
+    "chunglu_30k_hubs": CASES["chunglu_30k_hubs"],
+    "rmat_s15": lambda: gg.rmat(15, 16, seed=2),
+    "star_40000_split_hub": CASES["star_40000_split_hub"],
+}
+
+
+@pytest.mark.parametrize("name", list(REORDER_CASES))
+def test_solve_order_keeps_every_row_sum(built, name):
+    """The solve-time vertex order (reorder option) renumbers the large levels
+    with skewed degrees but keeps each row's entries in their order.  So, at
+    one lane shift, the exported levels are identical to those of a hierarchy
+    kept in the setup's numbering, every level's product and a V-cycle (fp64
+    and mixed) are bit-identical, and the solves (whose dot products sum in
+    another order) agree at the FP64 bar; the eigensolver's pairs stay
+    eigenpairs to its tolerance."""
+    import torch
+
+    g = REORDER_CASES[name]()
+    say(f"[case] {name}: n={g.n} nnz={g.nnz}")
+    B = to_dev(gg.rhs(g.n, 4, 7))
+    for prec in (lg.LG_FP64, lg.LG_MIXED):
+        h0 = gpu_setup(g, reorder=0, row_shift=1, max_rhs=4, precision=prec)
+        h1 = gpu_setup(g, reorder=1, row_shift=1, max_rhs=4, precision=prec)
+        s0, s1 = lg.lg_hierarchy_stats(h0), lg.lg_hierarchy_stats(h1)
+        say(f"  precision {prec}: reordered levels {[l for l, s in enumerate(s1) if s['reordered']]}")
+        assert not any(s["reordered"] for s in s0) and any(s["reordered"] for s in s1)
+        assert [(s["type"], s["n"], s["nnz"]) for s in s0] == [(s["type"], s["n"], s["nnz"]) for s in s1]
+        for l in range(len(s0)):
+            for a, b in zip(lg.lg_export_level(h0, l), lg.lg_export_level(h1, l)):
+                assert (a is None and b is None) or np.array_equal(bits(a) if a.dtype == np.float64 else a,
+                                                                   bits(b) if b.dtype == np.float64 else b)
+        rng = np.random.default_rng(1)
+        for l, s in enumerate(s0):
+            for k in (1, 4, 32):
+                X = to_dev(rng.standard_normal((s["n"], k)))
+                Y0, Y1 = torch.empty_like(X), torch.empty_like(X)
+                lg.lg_spmv(h0, l, X, Y0)
+                lg.lg_spmv(h1, l, X, Y1)
+                torch.cuda.synchronize()
+                assert np.array_equal(bits(Y0.cpu().numpy()), bits(Y1.cpu().numpy())), (l, k)
+        for _ in range(2):  # eager, then the captured graph's replay
+            C0, C1 = lg.lg_cycle(h0, B), lg.lg_cycle(h1, B)
+            assert np.array_equal(bits(C0.cpu().numpy()), bits(C1.cpu().numpy()))
+        X0, i0, st0 = lg.lg_solve(h0, B)
+        X1, i1, st1 = lg.lg_solve(h1, B)
+        assert st0 == lg.LG_OK and st1 == lg.LG_OK
+        b = B.cpu().numpy()
+        for c in range(4):
+            x0, x1 = X0.cpu().numpy()[:, c], X1.cpu().numpy()[:, c]
+            bp = b[:, c] - b[:, c].mean()
+            rel = np.linalg.norm(bp - laplacian_apply(g, x1)) / np.linalg.norm(bp)
+            diff = dense_laplacian_norm(g, x1 - x0) / dense_laplacian_norm(g, x0)
+            say(f"    column {c}: iterations {i0[c]['iters']} / {i1[c]['iters']}, "
+                f"true residual {rel:.2e}, energy difference {diff:.1e}")
+            assert rel <= 1e-8 * 1.001 and abs(i0[c]["iters"] - i1[c]["iters"]) <= 1
+            assert diff <= (1e-6 if prec == lg.LG_FP64 else 1e-5)
+    lam, V, it, res, st = lg.lg_eigs(gpu_setup(g, max_rhs=4), 2, tol=1e-8, max_iter=500)
+    assert st == lg.LG_OK
+    V = V.cpu().numpy()
+    for i in range(2):
+        r = np.linalg.norm(laplacian_apply(g, V[:, i]) - lam[i] * V[:, i])
+        assert r <= 1e-8 * lam[i] * 1.001

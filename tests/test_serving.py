@@ -24,6 +24,7 @@ POOL = [
     lambda: gg.grid3d(10, 10, 10, weights="loguniform", seed=9),
     lambda: gg.path(600),
     lambda: gg.gnp(800, 0.01, seed=10),
+    lambda: gg.rmat(15, 16, seed=6),  # stored in the solve-time vertex order
 ]
 
 

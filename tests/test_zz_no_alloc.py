@@ -29,8 +29,11 @@ def built():
 def test_noalloc_eigs_match_lg_eigs_on_two_calls(built):
     import torch
 
-    cases = [(gg.grid2d(48, 48), 3), (gg.grid3d(9, 9, 9, weights="loguniform", seed=4), 2)]
-    for g, nev in cases:  # the second graph is smaller: the scratch keeps stale values
+    # a graph stored in the solve-time vertex order, then smaller ones: the
+    # scratch keeps the previous call's values
+    cases = [(gg.chung_lu(30000, seed=6, max_deg=9000), 2), (gg.grid2d(48, 48), 3),
+             (gg.grid3d(9, 9, 9, weights="loguniform", seed=4), 2)]
+    for g, nev in cases:
         say(f"[case] lg_eigs_noalloc n={g.n} nev={nev}")
         h = gpu_setup(g, max_rhs=8)
         lam, X, it, res, st = lg.lg_eigs(h, nev, tol=1e-8, max_iter=500)
