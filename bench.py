@@ -59,8 +59,8 @@ WORKLOADS = {
                       label="grid2d_64x64_unit_fp64_1rhs", family="spmv",
                       kernel="k_rows<lg::LapOp<double, 1, 0, 0> >"),
     "grid3d_128_mixed": dict(cfg="grid3d_128_loguniform", precision="mixed", k=32,
-                             label="grid3d_128cube_loguniform_mixed_32rhs", family="cg_update",
-                             kernel="k_update_xr<32, float>"),
+                             label="grid3d_128cube_loguniform_mixed_32rhs", family="spmv",
+                             kernel="k_rows_col<lg::LapColOp<double, 32, 0, 0> >"),
     "grid3d_128_fp64": dict(cfg="grid3d_128_loguniform", precision="fp64", k=32,
                             label="grid3d_128cube_loguniform_fp64_32rhs", family="resid,resid64",
                             kernel="k_rows_col<lg::LapColOp<double, 32, 1, 0> >"),
