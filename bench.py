@@ -51,7 +51,7 @@ WORKLOADS = {
                        companion="chunglu_4m_mixed"),
     "chunglu_4m_mixed": dict(cfg="chunglu_4m", precision="mixed", k=16,
                              label="chunglu_4m_g2.1_d16_mixed_16rhs", family="spmv",
-                             kernel="k_rows_col<lg::LapColOp<double, 16, 0, 0> >"),
+                             kernel="k_rows_col<lg::LapColOp<double, 16, 0, 2> >"),
     "rmat_s18": dict(cfg="rmat_s18", precision="fp64", k=1,
                      label="rmat_s18_ef16_lcc_u01_fp64_1rhs", family="resid,resid64",
                      kernel="k_rows<lg::LapOp<double, 1, 1, 0> >"),
@@ -60,7 +60,7 @@ WORKLOADS = {
                       kernel="k_rows<lg::LapOp<double, 1, 0, 0> >"),
     "grid3d_128_mixed": dict(cfg="grid3d_128_loguniform", precision="mixed", k=32,
                              label="grid3d_128cube_loguniform_mixed_32rhs", family="spmv",
-                             kernel="k_rows_col<lg::LapColOp<double, 32, 0, 0> >"),
+                             kernel="k_rows_col<lg::LapColOp<double, 32, 0, 2> >"),
     "grid3d_128_fp64": dict(cfg="grid3d_128_loguniform", precision="fp64", k=32,
                             label="grid3d_128cube_loguniform_fp64_32rhs", family="resid,resid64",
                             kernel="k_rows_col<lg::LapColOp<double, 32, 1, 0> >"),

@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <atomic>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "lgmg.h"
@@ -217,6 +218,8 @@ struct Sched {
   int32_t* carry_row = nullptr;  // [ntile] row cut by the tile's end, or -1
   double* carry_val = nullptr;   // [ntile] its partial sum in the tile
   bool merge = false;            // one-column Laplacian products use the merge path
+  bool stable = false;           // row lists in increasing row order (not only grouped):
+                                 // workgroups then see the same rows on every build
 };
 
 // Merge path: the rows' entries and end markers form one list of n + nnz
@@ -502,12 +505,45 @@ void run_rows(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st,
 // groups of a workgroup; a split row by one workgroup per chunk plus a second
 // pass.  Op interface: kL, Acc, identity(), active(row),
 // accum(acc, row, e, part), combine(a, b), finish(row, acc, part).
+//
+// Ops with kDot = true also form a dot product per column in the epilogue:
+// finish_dot(row, acc, part, pre, d) adds the row's terms for the lane's V
+// columns to d[V]; each workgroup sums its lanes' shares in a fixed order
+// (dot_store), and split rows keep theirs per row (k_split_fix_col).
+template <class Op, class = void>
+struct op_dot : std::false_type {};
+template <class Op>
+struct op_dot<Op, std::void_t<decltype(Op::kDot)>> : std::integral_constant<bool, Op::kDot> {};
+template <class Op>
+constexpr int dot_width() {
+  if constexpr (op_dot<Op>::value) return Op::V;
+  else return 1;
+}
+
+// Per workgroup: column c = (lane & (kL - 1)) * V + v of the lanes' shares d,
+// summed over the workgroup in a fixed order, to out[blockIdx.x * kL * V + c].
+template <class Op>
+__device__ __forceinline__ void dot_store(const double (&d)[dot_width<Op>()], double* __restrict__ out) {
+  if constexpr (op_dot<Op>::value) {
+    constexpr int V = Op::V, K = Op::kL * Op::V;
+    __shared__ double sm[kBlock * V];
+#pragma unroll
+    for (int v = 0; v < V; v++) sm[threadIdx.x * V + v] = d[v];
+    __syncthreads();
+    if ((int)threadIdx.x < K) {
+      double t = 0.0;
+      for (int q = threadIdx.x; q < kBlock * V; q += K) t += sm[q];
+      out[(int64_t)blockIdx.x * K + threadIdx.x] = t;
+    }
+  }
+}
+
 // M groups of kL lanes per row for the rows perm[p0, p1): group g takes entries
 // beg + g, beg + g + M, ...; the groups' sums are combined by a butterfly.
 template <class Op, int M>
 __device__ __forceinline__ void col_rows(const Op& op, const int32_t* __restrict__ rp,
                                          const int32_t* __restrict__ perm, int64_t p0, int64_t p1,
-                                         int64_t lb) {
+                                         int64_t lb, double (&dacc)[dot_width<Op>()]) {
   constexpr int L = Op::kL, T = L * M;
   const int64_t pos = p0 + (lb * kBlock + threadIdx.x) / T;
   const int part = threadIdx.x & (L - 1);
@@ -531,7 +567,10 @@ __device__ __forceinline__ void col_rows(const Op& op, const int32_t* __restrict
 #pragma unroll
     for (int m = T / 2; m >= L; m >>= 1) op.combine(acc, shfl_xor_any(acc, m));
   }
-  if (grp == 0) op.finish(row, acc, part, pre);
+  if (grp == 0) {
+    if constexpr (op_dot<Op>::value) op.finish_dot(row, acc, part, pre, dacc);
+    else op.finish(row, acc, part, pre);
+  }
 }
 
 // Entries [beg, end) of `row` by all kBlock / kL groups of the workgroup; the
@@ -567,6 +606,8 @@ __device__ __forceinline__ typename Op::Acc col_block_reduce(const Op& op, int64
   return t;
 }
 
+// dotp (ops with kDot): each workgroup's column sums of the epilogue's dot
+// terms, kL * V per workgroup (zero for chunk and padding workgroups).
 template <class Op>
 __global__ __launch_bounds__(kBlock) void k_rows_col(Op op, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ perm,
@@ -577,8 +618,9 @@ __global__ __launch_bounds__(kBlock) void k_rows_col(Op op, const int32_t* __res
                                                      const int32_t* __restrict__ split_cptr,
                                                      const int32_t* __restrict__ chunk_split,
                                                      typename Op::Acc* __restrict__ partial,
-                                                     int shift) {
+                                                     int shift, double* __restrict__ dotp) {
   constexpr int L = Op::kL;
+  double dacc[dot_width<Op>()] = {};
   int64_t b = blockIdx.x;
   if (b < nchunk) {
     const int h = chunk_split[b];
@@ -587,46 +629,63 @@ __global__ __launch_bounds__(kBlock) void k_rows_col(Op op, const int32_t* __res
     const int end = min(rp[row + 1], beg + kHubChunk);
     const typename Op::Acc t = col_block_reduce(op, row, beg, end);
     if (threadIdx.x < L) partial[b * L + threadIdx.x] = t;
+    dot_store<Op>(dacc, dotp);
     return;
   }
   b -= nchunk;
   if (b < nhub) {
     const int64_t row = hub_rows[b];
     const typename Op::Acc t = col_block_reduce(op, row, rp[row], rp[row + 1]);
-    if (threadIdx.x < L) op.finish(row, t, (int)threadIdx.x);
+    if (threadIdx.x < L) {
+      if constexpr (op_dot<Op>::value)
+        op.finish_dot(row, t, (int)threadIdx.x, op.prefetch(row, (int)threadIdx.x), dacc);
+      else
+        op.finish(row, t, (int)threadIdx.x);
+    }
+    dot_store<Op>(dacc, dotp);
     return;
   }
   b -= nhub;
   const int64_t pad = round_up8(nchunk + nhub) - nchunk - nhub;
-  if (b < pad) return;
+  if (b < pad) {
+    dot_store<Op>(dacc, dotp);
+    return;
+  }
   b -= pad;
   const int64_t slots = ((int64_t)gridDim.x - nchunk - nhub - pad) / kXcds;
   constexpr int MM = 64 / L;  // most groups a row may span inside one wavefront
   for_class_blocks(ct, b, slots, [&](int c, int64_t lb) {
     const int64_t p0 = ct.cls_start[c], p1 = ct.cls_start[c + 1];
     switch (c >= kClasses - 1 ? 0 : min(class_lanes(c, shift), MM)) {
-      case 1: col_rows<Op, 1>(op, rp, perm, p0, p1, lb); break;
-      case 2: col_rows<Op, (2 < MM ? 2 : MM)>(op, rp, perm, p0, p1, lb); break;
-      case 4: col_rows<Op, (4 < MM ? 4 : MM)>(op, rp, perm, p0, p1, lb); break;
-      case 8: col_rows<Op, (8 < MM ? 8 : MM)>(op, rp, perm, p0, p1, lb); break;
-      case 16: col_rows<Op, (16 < MM ? 16 : MM)>(op, rp, perm, p0, p1, lb); break;
-      case 32: col_rows<Op, (32 < MM ? 32 : MM)>(op, rp, perm, p0, p1, lb); break;
+      case 1: col_rows<Op, 1>(op, rp, perm, p0, p1, lb, dacc); break;
+      case 2: col_rows<Op, (2 < MM ? 2 : MM)>(op, rp, perm, p0, p1, lb, dacc); break;
+      case 4: col_rows<Op, (4 < MM ? 4 : MM)>(op, rp, perm, p0, p1, lb, dacc); break;
+      case 8: col_rows<Op, (8 < MM ? 8 : MM)>(op, rp, perm, p0, p1, lb, dacc); break;
+      case 16: col_rows<Op, (16 < MM ? 16 : MM)>(op, rp, perm, p0, p1, lb, dacc); break;
+      case 32: col_rows<Op, (32 < MM ? 32 : MM)>(op, rp, perm, p0, p1, lb, dacc); break;
       default: {  // one workgroup per row (class 7)
         const int64_t row = perm[p0 + lb];
         const typename Op::Acc t = col_block_reduce(op, row, rp[row], rp[row + 1]);
-        if (threadIdx.x < L) op.finish(row, t, (int)threadIdx.x);
+        if (threadIdx.x < L) {
+          if constexpr (op_dot<Op>::value)
+            op.finish_dot(row, t, (int)threadIdx.x, op.prefetch(row, (int)threadIdx.x), dacc);
+          else
+            op.finish(row, t, (int)threadIdx.x);
+        }
         __syncthreads();  // the next row reuses the reduction buffer
         break;
       }
     }
   });
+  dot_store<Op>(dacc, dotp);
 }
 
+// dotp (ops with kDot): the dot terms of split row h at dotp[h * kL * V + ...].
 template <class Op>
 __global__ __launch_bounds__(64) void k_split_fix_col(Op op, const int32_t* __restrict__ split_rows,
                                                       const int32_t* __restrict__ split_cptr,
                                                       const typename Op::Acc* __restrict__ partial,
-                                                      int64_t nsplit) {
+                                                      int64_t nsplit, double* __restrict__ dotp) {
   constexpr int L = Op::kL;
   const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (t >= nsplit * L) return;
@@ -634,15 +693,25 @@ __global__ __launch_bounds__(64) void k_split_fix_col(Op op, const int32_t* __re
   const int part = (int)(t % L);
   typename Op::Acc acc = op.identity();
   for (int c = split_cptr[h]; c < split_cptr[h + 1]; c++) op.combine(acc, partial[(int64_t)c * L + part]);
-  op.finish((int64_t)split_rows[h], acc, part);
+  const int64_t row = split_rows[h];
+  if constexpr (op_dot<Op>::value) {
+    double d[Op::V] = {};
+    op.finish_dot(row, acc, part, op.prefetch(row, part), d);
+#pragma unroll
+    for (int v = 0; v < Op::V; v++) dotp[(h * L + part) * Op::V + v] = d[v];
+  } else {
+    op.finish(row, acc, part);
+  }
 }
 
+// Returns the workgroups launched.  dotp (ops with kDot): their dot partials,
+// followed by those of the split rows (see dot_partials).
 template <class Op>
-void run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st,
-                  const char* fam = "", double bytes = 0.0) {
+int64_t run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st,
+                     const char* fam = "", double bytes = 0.0, double* dotp = nullptr) {
   constexpr int L = Op::kL;
   static_assert(sizeof(typename Op::Acc) * L <= kPartialBytes, "partial slot too small");
-  if (s.n == 0) return;
+  if (s.n == 0) return 0;
   ClassTable ct = s.ct;
   int64_t blk = 0;
   for (int c = 0; c < kClasses; c++) {
@@ -654,22 +723,30 @@ void run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_t s
   ct.blk_start[kClasses] = (int32_t)blk;
   const int64_t blocks =
       round_up8(s.nchunk + s.nhub) + round_up8(std::min<int64_t>(blk, resident_grid(k_rows_col<Op>)));
-  if (blocks == 0) return;
+  if (blocks == 0) return 0;
   {
     ProfScope ps(fam, st, bytes, true);
     hipExtLaunchKernelGGL((k_rows_col<Op>), dim3((unsigned)blocks), dim3(kBlock), 0, st, ps.start(),
                           ps.stop(), 0, op, rp, (const int32_t*)s.perm, ct, s.nhub,
                           (const int32_t*)s.hub_rows, s.nchunk, (const int32_t*)s.split_rows,
                           (const int32_t*)s.split_cptr, (const int32_t*)s.chunk_split,
-                          reinterpret_cast<typename Op::Acc*>(s.partial), s.col_shift);
+                          reinterpret_cast<typename Op::Acc*>(s.partial), s.col_shift, dotp);
   }
   LG_LAUNCH_CHECK();
   if (s.nsplit) {
     hipLaunchKernelGGL((k_split_fix_col<Op>), dim3((unsigned)ceil_div(s.nsplit * L, 64)), dim3(64), 0,
                        st, op, (const int32_t*)s.split_rows, (const int32_t*)s.split_cptr,
-                       (const typename Op::Acc*)s.partial, s.nsplit);
+                       (const typename Op::Acc*)s.partial, s.nsplit,
+                       dotp ? dotp + blocks * (int64_t)L * dot_width<Op>() : nullptr);
     LG_LAUNCH_CHECK();
   }
+  return blocks;
+}
+
+// Dot partials of one run_rows_col launch on schedule s: at most this many
+// rows of k columns (workgroups, then split rows).
+inline int64_t dot_partials(const Sched& s, int64_t resident) {
+  return round_up8(s.nchunk + s.nhub) + round_up8(resident) + s.nsplit;
 }
 
 // ------------------------------------------------------------ merge path
@@ -852,14 +929,14 @@ constexpr int kStat = 16;
 // layout.  tiles: also the merge-path tiles (level matrices whose one-column
 // products may take the merge path).
 void build_sched(Sched& s, const int32_t* rp, int64_t n, int64_t nnz, Arena& keep, Arena& tmp,
-                 hipStream_t st, bool tiles = false);
+                 hipStream_t st, bool tiles = false, bool stable = false);
 // The two halves, for callers that read the statistics together with other
 // values: sched_stats launches the kernels that fill kStat ints (returned, on
 // the device, in tmp; n_dev optionally holds the actual row count <= n) and
 // sched_layout builds the schedule from those ints once they are on the host.
 int* sched_stats(const int32_t* rp, int64_t n, const int64_t* n_dev, Arena& tmp, hipStream_t st);
 void sched_layout(Sched& s, const int* t, const int32_t* rp, int64_t n, int64_t nnz, bool tiles,
-                  Arena& keep, Arena& tmp, hipStream_t st);
+                  Arena& keep, Arena& tmp, hipStream_t st, bool stable = false);
 void sched_fill(Sched& s, const int32_t* rp, Arena& tmp, hipStream_t st);
 // out[i] = sum_{j<i} in[j] for i <= n (out has n+1 entries); returns out[n] on the host
 // when want_total (synchronises the stream).

@@ -89,6 +89,8 @@ struct lg_hierarchy {
   void* cyc_in = nullptr;   // level-0 cycle input in the cycle precision (mixed)
   double* scal = nullptr;   // device scalars, 32 x K
   double* red = nullptr;    // reduction partials
+  double* dotp = nullptr;   // partials of the CG product's fused p . q (dot_partials x K)
+  int64_t dotp_rows = 0;
   double* host_scal = nullptr;  // pinned mirror of scal
   double setup_ms = 0.0;
   double* lmax_dev = nullptr;

@@ -134,6 +134,9 @@ struct LapColOp {
   T* __restrict__ p;
   T c1, c2, c0;
   const int32_t* __restrict__ agg = nullptr;  // LAP_CHEB_FIRST_CC: aggregate of each row
+  // TAG 2 with LAP_SPMV: the CG's product, whose epilogue also forms p . q
+  // (p = x, q = y) per column; see finish_dot and the row kernels' dot_store
+  static constexpr bool kDot = MODE == LAP_SPMV && TAG == 2;
 
   __device__ __forceinline__ Acc identity() const {
     Acc a;
@@ -181,6 +184,17 @@ struct LapColOp {
   }
   __device__ __forceinline__ void finish(int64_t row, const Acc& a, int part) const {
     finish(row, a, part, prefetch(row, part));
+  }
+  // y = L x as LAP_SPMV, and the lane's terms x_row * y_row added to d (kDot)
+  __device__ __forceinline__ void finish_dot(int64_t row, const Acc& a, int part, const Pre& q,
+                                             double (&d)[V]) const {
+    const int64_t base = row * K + part * V;
+    vec_t out;
+#pragma unroll
+    for (int v = 0; v < V; v++) out[v] = q.di * q.xv[v] - a.v[v];
+    *reinterpret_cast<vec_t*>(y + base) = out;
+#pragma unroll
+    for (int v = 0; v < V; v++) d[v] += (double)q.xv[v] * (double)out[v];
   }
   __device__ __forceinline__ void finish(int64_t row, const Acc& a, int part, const Pre& q) const {
     const T di = q.di;

@@ -947,20 +947,51 @@ int* sched_stats(const int32_t* rp, int64_t n, const int64_t* n_dev, Arena& tmp,
   return tot;
 }
 
+// Stable row lists: key 0 split rows, 1 hub rows, 2 + c class c; a stable
+// sort then lays them out as [split | hub | class 0 | ... | class 7], each in
+// increasing row order.
+__global__ void k_sched_keys(const int32_t* __restrict__ rp, int64_t n, int hub_deg,
+                             uint64_t* __restrict__ keys, uint64_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int d = rp[i + 1] - rp[i];
+  const int c = degree_class(d, hub_deg);
+  keys[i] = c >= kClasses ? (d > kSplitDeg ? 0u : 1u) : (uint64_t)(2 + c);
+  vals[i] = (uint64_t)i;
+}
+
+__global__ void k_sched_lists(const int32_t* __restrict__ rp, const uint64_t* __restrict__ sorted,
+                              int64_t n, int64_t nsplit, int64_t nhub, int32_t* __restrict__ split_rows,
+                              int32_t* __restrict__ split_nch, int32_t* __restrict__ hub_rows,
+                              int32_t* __restrict__ perm) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int32_t r = (int32_t)sorted[i];
+  if (i < nsplit) {
+    split_rows[i] = r;
+    split_nch[i] = (rp[r + 1] - rp[r] + kHubChunk - 1) / kHubChunk;
+  } else if (i < nsplit + nhub) {
+    hub_rows[i - nsplit] = r;
+  } else {
+    perm[i - nsplit - nhub] = r;
+  }
+}
+
 void build_sched(Sched& s, const int32_t* rp, int64_t n, int64_t nnz, Arena& keep, Arena& tmp,
-                 hipStream_t st, bool tiles) {
+                 hipStream_t st, bool tiles, bool stable) {
   int t[kStat] = {};
   Arena::Mark m = tmp.mark();
   if (n > 0) read_dev(t, sched_stats(rp, n, nullptr, tmp, st), sizeof(t), st);
-  sched_layout(s, t, rp, n, nnz, tiles, keep, tmp, st);
+  sched_layout(s, t, rp, n, nnz, tiles, keep, tmp, st, stable);
   tmp.rewind(m);
 }
 
 void sched_layout(Sched& s, const int* t, const int32_t* rp, int64_t n, int64_t nnz, bool tiles,
-                  Arena& keep, Arena& tmp, hipStream_t st) {
+                  Arena& keep, Arena& tmp, hipStream_t st, bool stable) {
   s = Sched();
   s.n = n;
   s.nnz = nnz;
+  s.stable = stable;
   if (n == 0) return;
   s.hub_deg = LG_HUB_DEG;
   Arena::Mark m = tmp.mark();
@@ -1005,13 +1036,26 @@ void sched_layout(Sched& s, const int* t, const int32_t* rp, int64_t n, int64_t 
 void sched_fill(Sched& s, const int32_t* rp, Arena& tmp, hipStream_t st) {
   if (s.n == 0) return;
   Arena::Mark m = tmp.mark();
-  int* ctr = tmp.get<int>(kClasses + 2);
-  hipLaunchKernelGGL(k_zero_i32n, dim3(1), dim3(kBlock), 0, st, (int32_t*)ctr,
-                     (int64_t)(kClasses + 2));
   int32_t* nch = s.nsplit ? tmp.get<int32_t>(s.nsplit) : nullptr;
-  const int ipt = perm_ipt(s.n);
-  hipLaunchKernelGGL(k_class_perm, dim3((unsigned)ceil_div(s.n, (int64_t)ipt * kBlock)), dim3(kBlock),
-                     0, st, rp, s.n, ipt, s.hub_deg, s.ct, ctr, s.perm, s.hub_rows, s.split_rows, nch);
+  if (s.stable) {
+    // one stable radix pass over the group keys: split rows, hubs, classes
+    uint64_t* keys = tmp.get<uint64_t>(s.n);
+    uint64_t* vals = tmp.get<uint64_t>(s.n);
+    hipLaunchKernelGGL(k_sched_keys, dim3((unsigned)ceil_div(s.n, (int64_t)kBlock)), dim3(kBlock), 0,
+                       st, rp, s.n, s.hub_deg, keys, vals);
+    const SortedPairs sp = radix_sort_pairs(keys, vals, s.n, {0}, tmp, st);
+    hipLaunchKernelGGL(k_sched_lists, dim3((unsigned)ceil_div(s.n, (int64_t)kBlock)), dim3(kBlock), 0,
+                       st, rp, (const uint64_t*)sp.vals, s.n, s.nsplit, s.nhub, s.split_rows, nch,
+                       s.hub_rows, s.perm);
+  } else {
+    int* ctr = tmp.get<int>(kClasses + 2);
+    hipLaunchKernelGGL(k_zero_i32n, dim3(1), dim3(kBlock), 0, st, (int32_t*)ctr,
+                       (int64_t)(kClasses + 2));
+    const int ipt = perm_ipt(s.n);
+    hipLaunchKernelGGL(k_class_perm, dim3((unsigned)ceil_div(s.n, (int64_t)ipt * kBlock)),
+                       dim3(kBlock), 0, st, rp, s.n, ipt, s.hub_deg, s.ct, ctr, s.perm, s.hub_rows,
+                       s.split_rows, nch);
+  }
   LG_LAUNCH_CHECK();
   if (s.nsplit) {
     int64_t* start = tmp.get<int64_t>(s.nsplit + 1);

@@ -1709,7 +1709,9 @@ void setup_hierarchy(lg_hierarchy* h, const lg_graph* g, hipStream_t st) {
     check_flags(c);  // row pointers must be sane before any row pass
     c.tmp.rewind(m);
   }
-  build_sched(L0->sched, L0->rp, n, nnz, h->mem, c.tmp, st, o.merge_path != 0);
+  // level 0's schedule is stable: the CG product's fused dot then sums its
+  // terms in the same order on every setup of a graph
+  build_sched(L0->sched, L0->rp, n, nnz, h->mem, c.tmp, st, o.merge_path != 0, true);
   check_isolated(*L0);
   if (o.validate && nnz) {
     Arena::Mark m = c.tmp.mark();

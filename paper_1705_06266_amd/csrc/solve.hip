@@ -1020,6 +1020,29 @@ void lap64(lg_hierarchy* h, int l, const double* x, double* y, const double* b, 
   }
 }
 
+// q = L_0 p and p . q per column into out (K columns, the column-split
+// widths): the product's epilogue forms the terms, each workgroup sums its
+// share, and one fixed tree adds the partials.  false: not available (the
+// caller takes the separate product and dot).
+template <int K>
+bool lap64_dot(lg_hierarchy* h, const double* p, double* q, double* out, hipStream_t st) {
+  if constexpr (use_col_split<double, K>()) {
+    const Level& L = h->lev[0];
+    using Op = LapColOp<double, K, LAP_SPMV, 2>;
+    if (dot_partials(L.sched, resident_grid(k_rows_col<Op>)) > h->dotp_rows) return false;
+    const int64_t nb = run_rows_col(L.sched, L.rp,
+                                    Op{L.col, L.w, L.d, L.dinv, p, q, nullptr, nullptr, 0.0, 0.0, 0.0},
+                                    st, "spmv", spmm_bytes(L, K, 8, 2), h->dotp);
+    hipLaunchKernelGGL((k_dots_final<K, 1>), dim3(K), dim3(kBlock), 0, st, (const double*)h->dotp,
+                       (int)(nb + L.sched.nsplit), out, (double*)nullptr, (double*)nullptr);
+    LG_LAUNCH_CHECK();
+    return true;
+  } else {
+    (void)h, (void)p, (void)q, (void)out, (void)st;
+    return false;
+  }
+}
+
 // Work of one cycle in finest-residual units, following the same recursion
 // as Engine::level / fcg2 (Section 2.3.1: operator nonzeros per application).
 static double cycle_work(const lg_hierarchy* h, int l) {
@@ -1221,9 +1244,13 @@ lg_status pcg(lg_hierarchy* h, const double* B, double* X, int k, double rtol, i
     for (int c = 0; c < K; c++) work[c] += active[c] > 0.0 ? cw : 0.0;
   }
   for (int it = 1; (feed || it <= max_iter) && any_active(); it++) {
-    lap64<K>(h, 0, h->pp, h->pq, nullptr, st, "spmv");
-    if (flex) dot64x2(h->pp, h->pq, h->pp, h->pr, S_PQ, S_PR);
-    else dot64(h->pp, h->pq, S_PQ);
+    if (flex) {
+      lap64<K>(h, 0, h->pp, h->pq, nullptr, st, "spmv");
+      dot64x2(h->pp, h->pq, h->pp, h->pr, S_PQ, S_PR);
+    } else if (!lap64_dot<K>(h, h->pp, h->pq, sl(S_PQ), st)) {
+      lap64<K>(h, 0, h->pp, h->pq, nullptr, st, "spmv");
+      dot64(h->pp, h->pq, S_PQ);
+    }
     hipLaunchKernelGGL((k_alpha<K>), dim3(1), dim3(64), 0, st, sc, flex ? 1 : 0);
     {
       // reads r, q and writes r (fp64), plus r in the cycle's precision
@@ -1659,6 +1686,14 @@ void alloc_solve_workspace(lg_hierarchy* h, hipStream_t st) {
   if (h->opts.precision == LG_MIXED) h->cyc_in = h->mem.alloc((size_t)m * s);
   h->scal = h->mem.get<double>(S_COUNT * K);
   h->red = h->mem.get<double>((int64_t)kDotPartials * 3 * K);
+  {
+    // the fused p . q of the CG product on level 0 (column-split widths)
+    int dev = 0, cus = 0;
+    LG_HIP(hipGetDevice(&dev));
+    LG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    h->dotp_rows = dot_partials(h->lev[0].sched, (int64_t)cus * 16);
+    h->dotp = h->mem.get<double>(h->dotp_rows * K);
+  }
   LG_HIP(hipHostMalloc((void**)&h->host_scal, sizeof(double) * S_COUNT * K, hipHostMallocDefault));
   (void)st;
 }
