@@ -97,7 +97,8 @@ typedef struct {
                                summation order inside a row, so a solve is bit-reproducible
                                given the shifts in lg_level_stats, and a tuned run can differ
                                from another process's in the last bits */
-  int32_t reorder;          /* 1: after setup, levels of at least 2^14 vertices whose largest
+  int32_t reorder;          /* 1: after setup, aggregation levels (and an elimination level 0
+                               when max_rhs >= 4) of at least 2^14 vertices whose largest
                                degree is at least 8x their mean, and whose mean degree is at
                                most 128, are stored in a solve-time
                                vertex order (higher degree classes first, the setup's order

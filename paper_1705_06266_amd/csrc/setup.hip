@@ -1575,13 +1575,21 @@ void permute_csr(Ctx& c, Sched& sched, int32_t* ptr, int32_t* idx, double* val, 
 // mean degree is moderate get the solve order.  Smaller levels are cache
 // resident; near-regular ones, such as grids, keep the locality of their own
 // numbering; on dense levels every row gathers from most of the vector
-// whatever the order.
+// whatever the order.  Among elimination levels only level 0 runs a product
+// (one per CG iteration), and only when the solve is at least kReorderMinK
+// columns wide does that product gain more than the renumbering pass (one
+// gather per stored entry, whatever the width) costs: measured, C4's level 0
+// gains about 2 ms per 16-column solve for a 2 ms pass, and R-MAT's level 0
+// 0.08 ms per one-column solve for a 0.4 ms pass.
 constexpr int64_t kReorderMinRows = (int64_t)1 << 14;
 constexpr int64_t kReorderSkew = 8;       // largest degree >= kReorderSkew x mean degree
 constexpr int64_t kReorderMaxMean = 128;  // mean degree at most this
+constexpr int kReorderMinK = 4;
 
-bool wants_order(const Level& L) {
-  if (L.type == LG_LEVEL_COARSEST || L.n < kReorderMinRows || L.nnz == 0) return false;
+bool wants_order(const Level& L, int level, int K) {
+  if (L.n < kReorderMinRows || L.nnz == 0) return false;
+  if (!(L.type == LG_LEVEL_AGG || (L.type == LG_LEVEL_ELIM && level == 0 && K >= kReorderMinK)))
+    return false;
   return (int64_t)L.sched.max_deg * L.n >= kReorderSkew * L.nnz && L.nnz <= kReorderMaxMean * L.n;
 }
 
@@ -1594,8 +1602,9 @@ void reorder_levels(Ctx& c) {
   lg_hierarchy* h = c.h;
   Arena& tmp = c.tmp;
   const int nl = (int)h->lev.size();
-  for (Level& L : h->lev) {
-    if (!wants_order(L)) continue;
+  for (int l = 0; l < nl; l++) {
+    Level& L = h->lev[l];
+    if (!wants_order(L, l, h->K)) continue;
     Arena::Mark m = tmp.mark();
     uint64_t* keys = tmp.get<uint64_t>(L.n);
     uint64_t* vals = tmp.get<uint64_t>(L.n);

@@ -452,9 +452,11 @@ def test_elimination_of_higher_degree_matches(built, name, max_degree):
 
 
 REORDER_CASES = {
+    # elimination first, then an aggregation level
     "chunglu_30k_hubs": CASES["chunglu_30k_hubs"],
-    "rmat_s15": lambda: gg.rmat(15, 16, seed=2),
-    "star_40000_split_hub": CASES["star_40000_split_hub"],
+    "rmat_s16": lambda: gg.rmat(16, 16, seed=2),
+    # few low-degree vertices: aggregation from level 0
+    "chunglu_30k_dense": lambda: gg.chung_lu(30000, mean_deg=48, max_deg=5000, seed=6),
 }
 
 
@@ -478,6 +480,10 @@ def test_solve_order_keeps_every_row_sum(built, name):
         s0, s1 = lg.lg_hierarchy_stats(h0), lg.lg_hierarchy_stats(h1)
         say(f"  precision {prec}: reordered levels {[l for l, s in enumerate(s1) if s['reordered']]}")
         assert not any(s["reordered"] for s in s0) and any(s["reordered"] for s in s1)
+        assert s1[0]["reordered"]  # level 0: aggregation, or elimination at 4 columns
+        # one column: an elimination level 0 keeps the setup's numbering
+        s_one = lg.lg_hierarchy_stats(gpu_setup(g, max_rhs=1, precision=prec))
+        assert s_one[0]["reordered"] == (name == "chunglu_30k_dense")
         assert [(s["type"], s["n"], s["nnz"]) for s in s0] == [(s["type"], s["n"], s["nnz"]) for s in s1]
         for l in range(len(s0)):
             for a, b in zip(lg.lg_export_level(h0, l), lg.lg_export_level(h1, l)):

@@ -24,7 +24,8 @@ POOL = [
     lambda: gg.grid3d(10, 10, 10, weights="loguniform", seed=9),
     lambda: gg.path(600),
     lambda: gg.gnp(800, 0.01, seed=10),
-    lambda: gg.rmat(15, 16, seed=6),  # stored in the solve-time vertex order
+    # level 0 stored in the solve-time vertex order
+    lambda: gg.chung_lu(30000, mean_deg=48, max_deg=5000, seed=11),
 ]
 
 
