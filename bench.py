@@ -733,6 +733,22 @@ def measure(args, lg, dev, g, b_host, rp, col, w, B, workload, family, latency_s
     stats = lg.lg_hierarchy_stats(h)
     hier_bytes = lg.lg_hierarchy_bytes(h)
 
+    # hub and split rows (a workgroup or more per row), timed as launches of
+    # their own in one more solve; every row is reduced as in the timed steps
+    hub = None
+    if any(s["n_hub"] for s in stats):
+        lg.lg_profile_enable("hubs")
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        lg.lg_solve(h, B, rtol=1e-8, max_iter=500)
+        torch.cuda.synchronize()
+        solve_ms_h = (time.perf_counter() - a) * 1e3
+        hn, hms, _ = lg.lg_profile_read()
+        lg.lg_profile_enable(None)
+        hub = {"launches": hn, "ms_per_solve": hms, "solve_ms": solve_ms_h,
+               "share_of_solve": hms / solve_ms_h if solve_ms_h > 0 else None,
+               "rows_per_level": [s["n_hub"] for s in stats]}
+
     # fp64 SpMV bandwidth on the finest level (algorithmic bytes), lg_spmv's own kernels
     n0 = stats[0]["n"]
     kk = 1 if wl["k"] == 1 else min(32, 1 << (wl["k"] - 1).bit_length())
@@ -815,6 +831,7 @@ def measure(args, lg, dev, g, b_host, rp, col, w, B, workload, family, latency_s
         "spmv_fp64_ms": sp_ms / sp_n if sp_n else None,
         "spmv_fp64_rhs": kk,
         "spmv_fp64_by_level": by_level,
+        "hub_rows": hub,
         "hierarchy_bytes": hier_bytes,
         "levels": [(s["type"], s["n"], s["nnz"], s["lane_shift"], s["col_shift"], s["merge"])
                    for s in stats],

@@ -257,9 +257,12 @@ void lg_free(lg_hierarchy* h);
  * the coarse correction with the first post-smoothing step (or that step
  * alone), "cheb" the later steps, "resid" the cycle's residual, "resid64" the
  * CG's true residual (in FP64 the same kernel instance as "resid"), "spmm_inner" the
- * K-cycle's coarse-level FCG products, "cg_update" the CG's x and r update
+ * K-cycle's coarse-level FCG products, "cg_update" the CG's residual update
  * (a vector pass); "restrict", "prolong" and "coarse" time those
- * cycle steps.  The setup families ("jacobi_xsum", "row_xsum", "affinity",
+ * cycle steps.  "hubs" times the hub and split rows of every row kernel: while
+ * it is enabled their workgroups run as a launch of their own before the
+ * other rows' (each row is reduced as in the single launch; the other
+ * families then exclude them).  The setup families ("jacobi_xsum", "row_xsum", "affinity",
  * "vote", "elim_select", "galerkin_reduce") time the span of each call of
  * that setup step, "radix" each radix sort.  lg_profile_read returns
  * the launch count, the summed event time and the summed algorithmic bytes of

@@ -243,6 +243,7 @@ __host__ __device__ constexpr int class_lanes(int c, int shift = 1) {
 // (hipExtLaunchKernelGGL), so the time is the kernel's alone; otherwise the
 // events are recorded on the stream around the enclosed work.
 bool prof_active();  // true while a kernel family is being timed
+bool prof_wants(const char* family);  // that family is being timed
 
 struct ProfScope {
   ProfScope(const char* family, hipStream_t st, double bytes, bool attached = false);
@@ -477,10 +478,28 @@ void run_rows(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st,
                       (int64_t)kBlock);
   }
   ct.blk_start[kClasses] = (int32_t)total;
-  const int64_t blocks =
-      round_up8(s.nchunk + s.nhub) + round_up8(std::min<int64_t>(total, resident_grid(k_rows<Op>)));
+  const int64_t head = round_up8(s.nchunk + s.nhub);
+  const int64_t blocks = head + round_up8(std::min<int64_t>(total, resident_grid(k_rows<Op>)));
   if (blocks == 0) return;
-  {
+  if (head > 0 && prof_wants("hubs")) {
+    // hub and split rows timed as a launch of their own (see run_rows_col)
+    {
+      ProfScope ps("hubs", st, 0.0, true);
+      hipExtLaunchKernelGGL((k_rows<Op>), dim3((unsigned)head), dim3(kBlock), 0, st, ps.start(),
+                            ps.stop(), 0, op, rp, (const int32_t*)s.perm, ct, s.nhub,
+                            (const int32_t*)s.hub_rows, s.nchunk, (const int32_t*)s.split_rows,
+                            (const int32_t*)s.split_cptr, (const int32_t*)s.chunk_split,
+                            reinterpret_cast<typename Op::Acc*>(s.partial), s.lane_shift);
+    }
+    if (blocks > head) {
+      ProfScope ps(fam, st, bytes, true);
+      hipExtLaunchKernelGGL((k_rows<Op>), dim3((unsigned)(blocks - head)), dim3(kBlock), 0, st,
+                            ps.start(), ps.stop(), 0, op, rp, (const int32_t*)s.perm, ct, (int64_t)0,
+                            (const int32_t*)s.hub_rows, (int64_t)0, (const int32_t*)s.split_rows,
+                            (const int32_t*)s.split_cptr, (const int32_t*)s.chunk_split,
+                            reinterpret_cast<typename Op::Acc*>(s.partial), s.lane_shift);
+    }
+  } else {
     ProfScope ps(fam, st, bytes, true);
     hipExtLaunchKernelGGL((k_rows<Op>), dim3((unsigned)blocks), dim3(kBlock), 0, st, ps.start(),
                           ps.stop(), 0, op, rp, (const int32_t*)s.perm, ct, s.nhub,
@@ -721,10 +740,31 @@ int64_t run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_
     blk += c == kClasses - 1 ? rows : ceil_div(rows * L * M, kBlock);
   }
   ct.blk_start[kClasses] = (int32_t)blk;
-  const int64_t blocks =
-      round_up8(s.nchunk + s.nhub) + round_up8(std::min<int64_t>(blk, resident_grid(k_rows_col<Op>)));
+  const int64_t head = round_up8(s.nchunk + s.nhub);
+  const int64_t blocks = head + round_up8(std::min<int64_t>(blk, resident_grid(k_rows_col<Op>)));
   if (blocks == 0) return 0;
-  {
+  if (head > 0 && prof_wants("hubs")) {
+    // timing the hub and split rows: their workgroups as a launch of their
+    // own (family "hubs"), then the class rows; every row is reduced as in
+    // the single launch
+    {
+      ProfScope ps("hubs", st, 0.0, true);
+      hipExtLaunchKernelGGL((k_rows_col<Op>), dim3((unsigned)head), dim3(kBlock), 0, st, ps.start(),
+                            ps.stop(), 0, op, rp, (const int32_t*)s.perm, ct, s.nhub,
+                            (const int32_t*)s.hub_rows, s.nchunk, (const int32_t*)s.split_rows,
+                            (const int32_t*)s.split_cptr, (const int32_t*)s.chunk_split,
+                            reinterpret_cast<typename Op::Acc*>(s.partial), s.col_shift, dotp);
+    }
+    if (blocks > head) {
+      ProfScope ps(fam, st, bytes, true);
+      hipExtLaunchKernelGGL((k_rows_col<Op>), dim3((unsigned)(blocks - head)), dim3(kBlock), 0, st,
+                            ps.start(), ps.stop(), 0, op, rp, (const int32_t*)s.perm, ct, (int64_t)0,
+                            (const int32_t*)s.hub_rows, (int64_t)0, (const int32_t*)s.split_rows,
+                            (const int32_t*)s.split_cptr, (const int32_t*)s.chunk_split,
+                            reinterpret_cast<typename Op::Acc*>(s.partial), s.col_shift,
+                            dotp ? dotp + head * (int64_t)L * dot_width<Op>() : nullptr);
+    }
+  } else {
     ProfScope ps(fam, st, bytes, true);
     hipExtLaunchKernelGGL((k_rows_col<Op>), dim3((unsigned)blocks), dim3(kBlock), 0, st, ps.start(),
                           ps.stop(), 0, op, rp, (const int32_t*)s.perm, ct, s.nhub,

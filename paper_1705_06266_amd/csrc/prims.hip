@@ -169,6 +169,13 @@ hipEvent_t take_event(Prof& p) {
 
 bool prof_active() { return prof().enabled.load(std::memory_order_relaxed); }
 
+bool prof_wants(const char* family) {
+  Prof& p = prof();
+  if (!p.enabled.load(std::memory_order_relaxed)) return false;
+  std::lock_guard<std::mutex> g(p.mu);
+  return std::find(p.families.begin(), p.families.end(), family) != p.families.end();
+}
+
 ProfScope::ProfScope(const char* family, hipStream_t s, double b, bool att)
     : on(false), attached(att), st(s), bytes(b) {
   Prof& p = prof();
@@ -242,7 +249,7 @@ extern "C" lg_status lg_profile_read(int64_t* launches, double* total_ms, double
 
 extern "C" const char* lg_profile_names(void) {
   return "spmv,lanczos,spmm,resid64,cg_update,cheb0,cheb1,cheb,resid,spmm_inner,restrict,prolong,coarse,"
-         "jacobi_xsum,row_xsum,affinity,vote,elim_select,radix,galerkin_reduce";
+         "hubs,jacobi_xsum,row_xsum,affinity,vote,elim_select,radix,galerkin_reduce";
 }
 
 namespace lg {

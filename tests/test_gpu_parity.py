@@ -520,3 +520,25 @@ def test_solve_order_keeps_every_row_sum(built, name):
     for i in range(2):
         r = np.linalg.norm(laplacian_apply(g, V[:, i]) - lam[i] * V[:, i])
         assert r <= 1e-8 * lam[i] * 1.001
+
+
+@pytest.mark.parametrize("name", ["chunglu_30k_hubs", "star_40000_split_hub"])
+def test_hub_rows_timed_apart_give_the_same_bits(built, name):
+    """With the "hubs" profiler family enabled, hub and split rows run as a
+    launch of their own; every row is reduced as in the single launch, so a
+    solve (one column, and four columns with the fused p . q) is bit-identical."""
+    g = CASES[name]()
+    for k in (1, 4):
+        h = gpu_setup(g, max_rhs=k, row_shift=1)
+        B = to_dev(gg.rhs(g.n, k, 23))
+        X0, i0, st0 = lg.lg_solve(h, B)
+        lg.lg_profile_enable("hubs")
+        try:
+            X1, i1, st1 = lg.lg_solve(h, B)
+            n_launch, ms, _ = lg.lg_profile_read()
+        finally:
+            lg.lg_profile_enable(None)
+        say(f"  k={k}: {n_launch} hub launches, {ms:.3f} ms")
+        assert st0 == st1 == lg.LG_OK and n_launch > 0
+        assert [i["iters"] for i in i0] == [i["iters"] for i in i1]
+        assert np.array_equal(bits(X0.cpu().numpy()), bits(X1.cpu().numpy()))
