@@ -572,6 +572,9 @@ def main():
     ap.add_argument("--eigs", type=int, default=0, metavar="NEV",
                     help="also time lg_eigs for the NEV smallest nonzero eigenpairs (tol 1e-8) "
                          "on a hierarchy of the workload's graph")
+    ap.add_argument("--no-hub-rows", dest="hub_rows", action="store_false",
+                    help="skip the extra solve that times hub rows apart (counter and trace runs: "
+                         "its split launches would mix into the roofline kernel's dispatches)")
     ap.add_argument("--no-stream-roof", action="store_true",
                     help="skip the on-box copy / triad bandwidth measurement")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -736,7 +739,7 @@ def measure(args, lg, dev, g, b_host, rp, col, w, B, workload, family, latency_s
     # hub and split rows (a workgroup or more per row), timed as launches of
     # their own in one more solve; every row is reduced as in the timed steps
     hub = None
-    if any(s["n_hub"] for s in stats):
+    if args.hub_rows and any(s["n_hub"] for s in stats):
         lg.lg_profile_enable("hubs")
         torch.cuda.synchronize()
         a = time.perf_counter()
