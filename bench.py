@@ -24,6 +24,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -41,9 +42,11 @@ KERNEL_SOURCES = ["paper_1705_06266_amd/csrc/common.h", "paper_1705_06266_amd/cs
                   "paper_1705_06266_amd/csrc/prims.hip"]
 
 # family: the profiler families whose launches are the roofline kernel (the
-# kernel instance with the largest share of the step's GPU time in the
-# workload's rocprofv3 summary); kernel: that instance as rocprofv3 prints it;
-# companion: a second workload timed beside this one on the same inputs.
+# kernel with the largest share of the step's GPU time in the workload's
+# rocprofv3 summary); kernel: that kernel as rocprofv3 prints it, without the
+# column-split kernels' unroll argument (its instances at every unroll count
+# together, as the autotuner may pick another per level); companion: a second
+# workload timed beside this one on the same inputs.
 WORKLOADS = {
     "chunglu_4m": dict(cfg="chunglu_4m", precision="fp64", k=16,
                        label="chunglu_4m_g2.1_d16_fp64_16rhs", family="resid,resid64",
@@ -269,6 +272,17 @@ def _short(name):
     return name.split("(")[0].replace("void ", "").replace("lg::", "", 1).strip()
 
 
+_UNROLL_ARG = re.compile(r"^(k_rows_col<.*>), \d+>$")
+
+
+def _kernel_of(name):
+    """A short kernel name without the column-split kernels' unroll argument:
+    'k_rows_col<lg::LapColOp<double, 16, 1, 0>, 4>' -> 'k_rows_col<lg::LapColOp<double, 16, 1, 0> >'."""
+    short = _short(name)
+    m = _UNROLL_ARG.match(short)
+    return m.group(1) + " >" if m else short
+
+
 def pmc_summary(args):
     """Turns two rocprofv3 counter runs of this script (FETCH_SIZE, WRITE_SIZE,
     each with --calibration-copy) into HBM bytes per launch of the roofline
@@ -296,7 +310,7 @@ def pmc_summary(args):
         # the calibration copy moves 512 MiB each way: its largest dispatch
         cal = max(copy_kib)
         scale = (512 * 1024) / cal
-        vals = [v for n, v in rows if _short(n) == wl["kernel"]]
+        vals = [v for n, v in rows if _kernel_of(n) == wl["kernel"]]
         if not vals:
             raise SystemExit(f"{wl['kernel']} not found in {path}")
         out[counter] = dict(kib_per_launch_raw=float(np.mean(vals)), calibration_kib=cal,
@@ -353,13 +367,17 @@ def trace_summary(args):
         t = float(r["TotalDurationNs"])
         lines.append(f"{t / 1e6:10.3f} {100 * t / tot:5.1f}% {int(r['Calls']):7d} "
                      f"{float(r['AverageNs']) / 1e3:9.2f}  {name}")
-    for r in rows:
-        if _short(r["Name"]) == wl["kernel"]:
-            target = r
+    inst = [r for r in rows if _kernel_of(r["Name"]) == wl["kernel"]]
     lines.append("")
-    if target:
-        lines.append(f"roofline kernel {wl['kernel']}: {int(target['Calls'])} calls, "
-                     f"average {float(target['AverageNs']) / 1e3:.2f} us (rocprofv3)")
+    if inst:
+        calls = sum(int(r["Calls"]) for r in inst)
+        total = sum(float(r["TotalDurationNs"]) for r in inst)
+        lines.append(f"roofline kernel {wl['kernel']}: {calls} calls, "
+                     f"average {total / calls / 1e3:.2f} us (rocprofv3)")
+        if len(inst) > 1 or _short(inst[0]["Name"]) != wl["kernel"]:
+            lines.append("  instances: " + "; ".join(
+                f"{_short(r['Name'])} {int(r['Calls'])} calls, {float(r['AverageNs']) / 1e3:.2f} us"
+                for r in inst))
     logs = [("same run under the profiler", args.bench_log),
             ("default run without the profiler", args.plain_log)]
     for what, log in logs:
@@ -836,8 +854,8 @@ def measure(args, lg, dev, g, b_host, rp, col, w, B, workload, family, latency_s
         "spmv_fp64_by_level": by_level,
         "hub_rows": hub,
         "hierarchy_bytes": hier_bytes,
-        "levels": [(s["type"], s["n"], s["nnz"], s["lane_shift"], s["col_shift"], s["merge"])
-                   for s in stats],
+        "levels": [(s["type"], s["n"], s["nnz"], s["lane_shift"], s["col_shift"], s["merge"],
+                    s["col_unroll"]) for s in stats],
         "_X": Xh,
         "_opts": opts,
     }

@@ -61,6 +61,7 @@ extern "C" lg_status lg_default_opts(lg_setup_opts* o) {
   o->merge_path = 0;
   o->row_shift = -1;
   o->reorder = 1;
+  o->col_unroll = 0;
   return LG_OK;
 }
 
@@ -82,6 +83,8 @@ static const char* check_opts(const lg_setup_opts& o) {
   if (o.merge_path < 0 || o.merge_path > 2) return "merge_path must be 0, 1 or 2";
   if (o.row_shift < -1 || o.row_shift > 2) return "row_shift must be -1, 0, 1 or 2";
   if (o.reorder < 0 || o.reorder > 1) return "reorder must be 0 or 1";
+  if (o.col_unroll != 0 && o.col_unroll != 4 && o.col_unroll != 6)
+    return "col_unroll must be 0, 4 or 6";
   return nullptr;
 }
 
@@ -111,6 +114,8 @@ extern "C" lg_status lg_setup(const lg_graph* g, const lg_setup_opts* o, void* h
   lg::alloc_solve_workspace(h, st);
   if (opts.merge_path == 2)
     for (auto& L : h->lev) L.sched.merge = true;
+  if (opts.col_unroll > 0)
+    for (auto& L : h->lev) L.sched.col_unroll = opts.col_unroll;
   if (opts.row_shift >= 0) {
     for (auto& L : h->lev) L.sched.lane_shift = L.sched.col_shift = opts.row_shift;
   } else if (opts.autotune) {
@@ -211,6 +216,7 @@ extern "C" lg_status lg_hierarchy_stats(const lg_hierarchy* h, lg_level_stats* o
     out[l].col_shift = L.sched.col_shift;
     out[l].merge = L.sched.merge ? 1 : 0;
     out[l].reordered = L.perm ? 1 : 0;
+    out[l].col_unroll = L.sched.col_unroll;
   }
   return LG_OK;
 }

@@ -188,6 +188,16 @@ __device__ __forceinline__ T shfl_xor_any(const T& v, int mask) {
 // results do not depend on scheduling.
 constexpr int kClasses = 8;
 constexpr int kPartialBytes = 512;
+// Entries each lane group of a column-split row kernel loads per trip (all
+// issued together), 4 or 6.  Fewer in flight per wavefront take fewer
+// registers and allow more wavefronts.  Measured in whole solves, fp64
+// products of at most 16 columns (8 lanes per entry or fewer) ran faster at 4,
+// the others at 6, so a schedule's unroll of 0 takes that rule; a group adds
+// its entries in the same order at either value.
+template <class Op>
+constexpr int col_unroll_of() {
+  return Op::V == 2 && Op::kL <= 8 ? 4 : 6;
+}
 constexpr int kSplitDeg = LG_SPLIT_DEG;  // rows above this are split into kHubChunk-entry chunks
 
 struct ClassTable {
@@ -211,6 +221,7 @@ struct Sched {
   // lanes (one-column kernels) or lane groups (column-split kernels) of a
   // class-c row: 2^(c - shift), chosen per matrix by the autotuner
   int lane_shift = 1, col_shift = 1;
+  int col_unroll = 0;  // column-split kernels: entries per group per trip (0: col_unroll_of)
   // merge-path tiles for one-column Laplacian products (see k_merge_rows):
   // tile_row[t] = rows whose end marker precedes merged item t * kMergeTile
   int64_t ntile = 0;
@@ -444,19 +455,19 @@ __global__ __launch_bounds__(kBlock) void k_rows(Op op, const int32_t* __restric
 
 // Run Op over every row of the CSR described by (s, rp) on stream st: one launch.
 // Workgroups of kBlock threads that the whole chip holds at once for this
-// kernel (its occupancy times the compute units): the size of a persistent
-// row grid, so that no workgroup waits for a second round.  Computed once
-// per kernel.
-template <typename KernelT>
-inline int64_t resident_grid(KernelT kernel) {
+// kernel (its occupancy, at most max_per_cu, times the compute units): the
+// size of a persistent row grid, so that no workgroup waits for a second
+// round.  Computed once per kernel (a kernel takes one max_per_cu).
+template <auto Kernel>
+inline int64_t resident_grid(int max_per_cu = 1 << 30) {
   static std::atomic<int64_t> cached{0};  // threads that race compute the same value
   int64_t v = cached.load(std::memory_order_relaxed);
   if (v == 0) {
     int per_cu = 0, dev = 0, cus = 0;
     LG_HIP(hipGetDevice(&dev));
     LG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    LG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0));
-    v = std::max<int64_t>(1, (int64_t)per_cu * cus);
+    LG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, Kernel, kBlock, 0));
+    v = std::max<int64_t>(1, (int64_t)std::min(per_cu, max_per_cu) * cus);
     cached.store(v, std::memory_order_relaxed);
   }
   return v;
@@ -479,7 +490,7 @@ void run_rows(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st,
   }
   ct.blk_start[kClasses] = (int32_t)total;
   const int64_t head = round_up8(s.nchunk + s.nhub);
-  const int64_t blocks = head + round_up8(std::min<int64_t>(total, resident_grid(k_rows<Op>)));
+  const int64_t blocks = head + round_up8(std::min<int64_t>(total, resident_grid<k_rows<Op>>()));
   if (blocks == 0) return;
   if (head > 0 && prof_wants("hubs")) {
     // hub and split rows timed as a launch of their own (see run_rows_col)
@@ -558,8 +569,9 @@ __device__ __forceinline__ void dot_store(const double (&d)[dot_width<Op>()], do
 }
 
 // M groups of kL lanes per row for the rows perm[p0, p1): group g takes entries
-// beg + g, beg + g + M, ...; the groups' sums are combined by a butterfly.
-template <class Op, int M>
+// beg + g, beg + g + M, ... (U per trip); the groups' sums are combined by a
+// butterfly.
+template <class Op, int M, int U>
 __device__ __forceinline__ void col_rows(const Op& op, const int32_t* __restrict__ rp,
                                          const int32_t* __restrict__ perm, int64_t p0, int64_t p1,
                                          int64_t lb, double (&dacc)[dot_width<Op>()]) {
@@ -574,11 +586,12 @@ __device__ __forceinline__ void col_rows(const Op& op, const int32_t* __restrict
   typename Op::Acc acc = op.identity();
   if (op.active(row)) {
     const int end = rp[row + 1];
-    // eight entries per trip, all loads issued together: slots past the row's
-    // end re-read its last entry with weight zero
-    for (int e = rp[row] + grp; e < end; e += 8 * M) {
+    // U entries per trip, all loads issued together: slots past the row's end
+    // re-read its last entry with weight zero (adding +-0 to a sum that
+    // started at +0 leaves its bits unchanged)
+    for (int e = rp[row] + grp; e < end; e += U * M) {
 #pragma unroll
-      for (int u = 0; u < 8; u++) {
+      for (int u = 0; u < U; u++) {
         const int eu = e + u * M;
         op.accum(acc, row, eu < end ? eu : end - 1, part, eu < end);
       }
@@ -627,7 +640,7 @@ __device__ __forceinline__ typename Op::Acc col_block_reduce(const Op& op, int64
 
 // dotp (ops with kDot): each workgroup's column sums of the epilogue's dot
 // terms, kL * V per workgroup (zero for chunk and padding workgroups).
-template <class Op>
+template <class Op, int U>
 __global__ __launch_bounds__(kBlock) void k_rows_col(Op op, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ perm,
                                                      ClassTable ct, int64_t nhub,
@@ -676,12 +689,12 @@ __global__ __launch_bounds__(kBlock) void k_rows_col(Op op, const int32_t* __res
   for_class_blocks(ct, b, slots, [&](int c, int64_t lb) {
     const int64_t p0 = ct.cls_start[c], p1 = ct.cls_start[c + 1];
     switch (c >= kClasses - 1 ? 0 : min(class_lanes(c, shift), MM)) {
-      case 1: col_rows<Op, 1>(op, rp, perm, p0, p1, lb, dacc); break;
-      case 2: col_rows<Op, (2 < MM ? 2 : MM)>(op, rp, perm, p0, p1, lb, dacc); break;
-      case 4: col_rows<Op, (4 < MM ? 4 : MM)>(op, rp, perm, p0, p1, lb, dacc); break;
-      case 8: col_rows<Op, (8 < MM ? 8 : MM)>(op, rp, perm, p0, p1, lb, dacc); break;
-      case 16: col_rows<Op, (16 < MM ? 16 : MM)>(op, rp, perm, p0, p1, lb, dacc); break;
-      case 32: col_rows<Op, (32 < MM ? 32 : MM)>(op, rp, perm, p0, p1, lb, dacc); break;
+      case 1: col_rows<Op, 1, U>(op, rp, perm, p0, p1, lb, dacc); break;
+      case 2: col_rows<Op, (2 < MM ? 2 : MM), U>(op, rp, perm, p0, p1, lb, dacc); break;
+      case 4: col_rows<Op, (4 < MM ? 4 : MM), U>(op, rp, perm, p0, p1, lb, dacc); break;
+      case 8: col_rows<Op, (8 < MM ? 8 : MM), U>(op, rp, perm, p0, p1, lb, dacc); break;
+      case 16: col_rows<Op, (16 < MM ? 16 : MM), U>(op, rp, perm, p0, p1, lb, dacc); break;
+      case 32: col_rows<Op, (32 < MM ? 32 : MM), U>(op, rp, perm, p0, p1, lb, dacc); break;
       default: {  // one workgroup per row (class 7)
         const int64_t row = perm[p0 + lb];
         const typename Op::Acc t = col_block_reduce(op, row, rp[row], rp[row + 1]);
@@ -723,11 +736,22 @@ __global__ __launch_bounds__(64) void k_split_fix_col(Op op, const int32_t* __re
   }
 }
 
+// Persistent grid of a column-split kernel: at most kColMaxPerCu workgroups
+// (one wavefront per SIMD each) per compute unit.  With more rows in flight
+// the gathers ran slower (measured: the 4M-vertex power-law product at 16
+// fp64 columns, occupancy 8 against 7), as they evict x rows that other rows
+// reuse.
+constexpr int kColMaxPerCu = 7;
+template <class Op, int U>
+int64_t col_grid() {
+  return resident_grid<k_rows_col<Op, U>>(kColMaxPerCu);
+}
+
 // Returns the workgroups launched.  dotp (ops with kDot): their dot partials,
 // followed by those of the split rows (see dot_partials).
-template <class Op>
-int64_t run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st,
-                     const char* fam = "", double bytes = 0.0, double* dotp = nullptr) {
+template <class Op, int U>
+int64_t run_rows_col_u(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st,
+                       const char* fam, double bytes, double* dotp) {
   constexpr int L = Op::kL;
   static_assert(sizeof(typename Op::Acc) * L <= kPartialBytes, "partial slot too small");
   if (s.n == 0) return 0;
@@ -741,7 +765,7 @@ int64_t run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_
   }
   ct.blk_start[kClasses] = (int32_t)blk;
   const int64_t head = round_up8(s.nchunk + s.nhub);
-  const int64_t blocks = head + round_up8(std::min<int64_t>(blk, resident_grid(k_rows_col<Op>)));
+  const int64_t blocks = head + round_up8(std::min<int64_t>(blk, col_grid<Op, U>()));
   if (blocks == 0) return 0;
   if (head > 0 && prof_wants("hubs")) {
     // timing the hub and split rows: their workgroups as a launch of their
@@ -749,7 +773,7 @@ int64_t run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_
     // the single launch
     {
       ProfScope ps("hubs", st, 0.0, true);
-      hipExtLaunchKernelGGL((k_rows_col<Op>), dim3((unsigned)head), dim3(kBlock), 0, st, ps.start(),
+      hipExtLaunchKernelGGL((k_rows_col<Op, U>), dim3((unsigned)head), dim3(kBlock), 0, st, ps.start(),
                             ps.stop(), 0, op, rp, (const int32_t*)s.perm, ct, s.nhub,
                             (const int32_t*)s.hub_rows, s.nchunk, (const int32_t*)s.split_rows,
                             (const int32_t*)s.split_cptr, (const int32_t*)s.chunk_split,
@@ -757,7 +781,7 @@ int64_t run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_
     }
     if (blocks > head) {
       ProfScope ps(fam, st, bytes, true);
-      hipExtLaunchKernelGGL((k_rows_col<Op>), dim3((unsigned)(blocks - head)), dim3(kBlock), 0, st,
+      hipExtLaunchKernelGGL((k_rows_col<Op, U>), dim3((unsigned)(blocks - head)), dim3(kBlock), 0, st,
                             ps.start(), ps.stop(), 0, op, rp, (const int32_t*)s.perm, ct, (int64_t)0,
                             (const int32_t*)s.hub_rows, (int64_t)0, (const int32_t*)s.split_rows,
                             (const int32_t*)s.split_cptr, (const int32_t*)s.chunk_split,
@@ -766,7 +790,7 @@ int64_t run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_
     }
   } else {
     ProfScope ps(fam, st, bytes, true);
-    hipExtLaunchKernelGGL((k_rows_col<Op>), dim3((unsigned)blocks), dim3(kBlock), 0, st, ps.start(),
+    hipExtLaunchKernelGGL((k_rows_col<Op, U>), dim3((unsigned)blocks), dim3(kBlock), 0, st, ps.start(),
                           ps.stop(), 0, op, rp, (const int32_t*)s.perm, ct, s.nhub,
                           (const int32_t*)s.hub_rows, s.nchunk, (const int32_t*)s.split_rows,
                           (const int32_t*)s.split_cptr, (const int32_t*)s.chunk_split,
@@ -781,6 +805,21 @@ int64_t run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_
     LG_LAUNCH_CHECK();
   }
   return blocks;
+}
+
+// The column-split product of Op over schedule s, at the schedule's unroll.
+template <class Op>
+int64_t run_rows_col(const Sched& s, const int32_t* rp, const Op& op, hipStream_t st,
+                     const char* fam = "", double bytes = 0.0, double* dotp = nullptr) {
+  if ((s.col_unroll ? s.col_unroll : col_unroll_of<Op>()) == 4)
+    return run_rows_col_u<Op, 4>(s, rp, op, st, fam, bytes, dotp);
+  return run_rows_col_u<Op, 6>(s, rp, op, st, fam, bytes, dotp);
+}
+
+// Workgroups of Op's column-split kernel resident on the device at s's unroll.
+template <class Op>
+int64_t col_resident(const Sched& s) {
+  return (s.col_unroll ? s.col_unroll : col_unroll_of<Op>()) == 4 ? col_grid<Op, 4>() : col_grid<Op, 6>();
 }
 
 // Dot partials of one run_rows_col launch on schedule s: at most this many

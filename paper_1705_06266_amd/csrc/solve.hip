@@ -1041,7 +1041,7 @@ bool lap64_dot(lg_hierarchy* h, const double* p, double* q, double* out, hipStre
   if constexpr (use_col_split<double, K>()) {
     const Level& L = h->lev[0];
     using Op = LapColOp<double, K, LAP_SPMV, 2>;
-    if (dot_partials(L.sched, resident_grid(k_rows_col<Op>)) > h->dotp_rows) return false;
+    if (dot_partials(L.sched, col_resident<Op>(L.sched)) > h->dotp_rows) return false;
     const int64_t nb = run_rows_col(L.sched, L.rp,
                                     Op{L.col, L.w, L.d, L.dinv, p, q, nullptr, nullptr, 0.0, 0.0, 0.0},
                                     st, "spmv", spmm_bytes(L, K, 8, 2), h->dotp);
@@ -1582,17 +1582,21 @@ static void autotune_k(lg_hierarchy* h, hipStream_t st) {
     const bool col = agg ? use_col_split<T, K>() : use_col_split<double, K>();
     if (K == 1 && h->opts.merge_path == 2) continue;  // one-column products forced to the merge path
     int& shift = col ? L.sched.col_shift : L.sched.lane_shift;
-    // candidates: the class-binned kernels at shifts 0, 1, 2, and (one column) the merge path
+    // candidates: the class-binned kernels at shifts 0, 1, 2, and (one column)
+    // the merge path (cached as -1)
     const bool try_merge = K == 1 && h->opts.merge_path == 1;
+    auto apply = [&](int v) {
+      L.sched.merge = v < 0;
+      if (v >= 0) shift = v;
+    };
     const std::vector<int64_t> key{L.n, L.nnz, L.sched.min_deg, L.sched.max_deg, L.sched.nhub,
                                    L.sched.nsplit, agg ? (int64_t)sizeof(T) : 8, K, col ? 1 : 0,
-                                   h->opts.merge_path, L.perm ? 1 : 0};
+                                   h->opts.merge_path, L.perm ? 1 : 0, h->opts.col_unroll};
     {
       std::lock_guard<std::mutex> g(g_tune_mu);
       auto it = g_tune.find(key);
       if (it != g_tune.end()) {
-        L.sched.merge = it->second < 0;
-        if (it->second >= 0) shift = it->second;
+        apply((int)it->second);
         std::vector<int64_t> k2 = key;
         k2.push_back(-1);
         auto it2 = g_tune.find(k2);
@@ -1600,11 +1604,15 @@ static void autotune_k(lg_hierarchy* h, hipStream_t st) {
         continue;
       }
     }
+    // the level's dominant product: the cycle's residual form, or on an
+    // elimination level 0 the CG's product (with its fused p . q when the
+    // CG takes that form)
+    const bool cg_dot = h->opts.cycle != LG_CYCLE_K;
     auto product = [&]() {
       if (agg)
         eng.template lap<LAP_RESID>(L, (const T*)L.vx, (T*)L.vr, (const T*)L.vb, nullptr, T(0), T(0),
                                     T(0), "", 3);
-      else
+      else if (!cg_dot || !lap64_dot<K>(h, h->pp, h->pq, h->scal + S_PQ * K, st))
         lap64<K>(h, 0, h->pp, h->pq, nullptr, st, "");
     };
     const int64_t m = L.n * K;
@@ -1614,16 +1622,16 @@ static void autotune_k(lg_hierarchy* h, hipStream_t st) {
     } else {
       hipLaunchKernelGGL((k_fill<double>), dim3(nblk(m)), dim3(kBlock), 0, st, h->pp, m, 0.0);
     }
-    int best = shift;
+    std::vector<int> cands(std::begin(kTuneShifts), std::end(kTuneShifts));
+    if (try_merge) cands.push_back(-1);
+    int best = cands[0];
     float best_ms = 0.0f;
-    const int ncand = (int)(sizeof(kTuneShifts) / sizeof(int)) + (try_merge ? 1 : 0);
-    for (int ci = 0; ci < ncand; ci++) {
-      const int cand = ci < (int)(sizeof(kTuneShifts) / sizeof(int)) ? kTuneShifts[ci] : -1;
-      L.sched.merge = cand < 0;
-      if (cand >= 0) shift = cand;
-      product();  // warm-up at this shift
+    for (size_t ci = 0; ci < cands.size(); ci++) {
+      const int cand = cands[ci];
+      apply(cand);
+      product();  // warm-up at this candidate
       LG_HIP(hipEventRecord(e0, st));
-      for (int r = 0; r < 3; r++) product();
+      for (int r = 0; r < 5; r++) product();
       LG_HIP(hipEventRecord(e1, st));
       LG_HIP(hipEventSynchronize(e1));
       float ms = 0.0f;
@@ -1633,8 +1641,7 @@ static void autotune_k(lg_hierarchy* h, hipStream_t st) {
         best = cand;
       }
     }
-    L.sched.merge = best < 0;
-    if (best >= 0) shift = best;
+    apply(best);
     {
       std::lock_guard<std::mutex> g(g_tune_mu);
       g_tune[key] = best;

@@ -48,14 +48,15 @@ class lg_setup_opts(C.Structure):
         ("seed", C.c_uint64), ("precision", C.c_int32), ("max_rhs", C.c_int32),
         ("keep_setup_data", C.c_int32), ("validate", C.c_int32), ("graphs", C.c_int32),
         ("autotune", C.c_int32), ("elim_passes", C.c_int32), ("merge_path", C.c_int32),
-        ("row_shift", C.c_int32), ("reorder", C.c_int32),
+        ("row_shift", C.c_int32), ("reorder", C.c_int32), ("col_unroll", C.c_int32),
     ]
 
 
 class lg_level_stats(C.Structure):
     _fields_ = [("type", C.c_int32), ("n", C.c_int64), ("nnz", C.c_int64), ("nc", C.c_int64),
                 ("lmax", C.c_double), ("n_hub", C.c_int64), ("lane_shift", C.c_int32),
-                ("col_shift", C.c_int32), ("merge", C.c_int32), ("reordered", C.c_int32)]
+                ("col_shift", C.c_int32), ("merge", C.c_int32), ("reordered", C.c_int32),
+                ("col_unroll", C.c_int32)]
 
 
 class lg_rhs_info(C.Structure):
@@ -285,7 +286,7 @@ def lg_hierarchy_stats(h):
     _check(load().lg_hierarchy_stats(h.handle, arr, nl.value, C.byref(nl)), "lg_hierarchy_stats")
     return [dict(type=s.type, n=s.n, nnz=s.nnz, nc=s.nc, lmax=s.lmax, n_hub=s.n_hub,
                  lane_shift=s.lane_shift, col_shift=s.col_shift, merge=s.merge,
-                 reordered=s.reordered) for s in arr]
+                 reordered=s.reordered, col_unroll=s.col_unroll) for s in arr]
 
 
 def lg_export_level(h, level):

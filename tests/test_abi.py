@@ -38,10 +38,12 @@ def test_struct_layouts_match_the_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "lgmg.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(lg_setup_opts),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(lg_setup_opts),"
         " offsetof(lg_setup_opts, seed), offsetof(lg_setup_opts, merge_path),"
-        " offsetof(lg_setup_opts, row_shift), offsetof(lg_setup_opts, reorder), sizeof(lg_graph),"
-        " sizeof(lg_level_stats), offsetof(lg_level_stats, reordered), sizeof(lg_rhs_info),"
+        " offsetof(lg_setup_opts, row_shift), offsetof(lg_setup_opts, reorder),"
+        " offsetof(lg_setup_opts, col_unroll), sizeof(lg_graph),"
+        " sizeof(lg_level_stats), offsetof(lg_level_stats, reordered),"
+        " offsetof(lg_level_stats, col_unroll), sizeof(lg_rhs_info),"
         " sizeof(lg_server_opts),"
         " offsetof(lg_server_opts, setup), sizeof(lg_server_stats),"
         " offsetof(lg_server_stats, resident_graphs), offsetof(lg_server_stats, refills));"
@@ -51,8 +53,9 @@ def test_struct_layouts_match_the_header(tmp_path):
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(lg.lg_setup_opts), lg.lg_setup_opts.seed.offset,
             lg.lg_setup_opts.merge_path.offset, lg.lg_setup_opts.row_shift.offset,
-            lg.lg_setup_opts.reorder.offset, C.sizeof(lg.lg_graph), C.sizeof(lg.lg_level_stats),
-            lg.lg_level_stats.reordered.offset, C.sizeof(lg.lg_rhs_info), C.sizeof(lg.lg_server_opts), lg.lg_server_opts.setup.offset,
+            lg.lg_setup_opts.reorder.offset, lg.lg_setup_opts.col_unroll.offset,
+            C.sizeof(lg.lg_graph), C.sizeof(lg.lg_level_stats),
+            lg.lg_level_stats.reordered.offset, lg.lg_level_stats.col_unroll.offset, C.sizeof(lg.lg_rhs_info), C.sizeof(lg.lg_server_opts), lg.lg_server_opts.setup.offset,
             C.sizeof(lg.lg_server_stats), lg.lg_server_stats.resident_graphs.offset,
             lg.lg_server_stats.refills.offset]
     assert got == want
@@ -80,6 +83,10 @@ def test_argument_errors_need_no_device():
     g.row_ptr = C.cast(rp2, C.c_void_p)
     assert lib.lg_setup(C.byref(g), C.byref(o), None, C.byref(h)) == lg.LG_E_ARG
     assert "max_rhs" in lg.lg_last_error()
+    o = lg.lg_default_opts(col_unroll=5)
+    assert lib.lg_setup(C.byref(g), C.byref(o), None, C.byref(h)) == lg.LG_E_ARG
+    assert "col_unroll" in lg.lg_last_error()
+    assert lg.lg_default_opts().col_unroll == 0
     assert lib.lg_solve(None, None, None, 1, 1e-8, 10, None, None) == lg.LG_E_ARG
     assert lg.status_str(lg.LG_E_DISCONNECTED) == "graph not connected"
     lib.lg_free(None)

@@ -547,3 +547,53 @@ def test_hub_rows_timed_apart_give_the_same_bits(built, name):
         assert st0 == st1 == lg.LG_OK and n_launch > 0
         assert [i["iters"] for i in i0] == [i["iters"] for i in i1]
         assert np.array_equal(bits(X0.cpu().numpy()), bits(X1.cpu().numpy()))
+
+
+@pytest.mark.parametrize("name", ["chunglu_30k_hubs", "star_40000_split_hub", "grid3d_12_loguniform",
+                                  "rmat_s12"])
+def test_unroll_keeps_every_row_sum(built, name):
+    """The column-split products load 4 or 6 entries per lane group and trip
+    (col_unroll; by default 4 for fp64 products of at most 16 columns, 6 for
+    the others); a group adds its entries in the same order at either value
+    and the padding slots add +-0 to sums that start at +0.  So every level's
+    product and a V-cycle (fp64 and mixed) are bit-identical at 4, 6 and the
+    default, and solves, whose fused p . q sums over a workgroup count that
+    follows the kernel's occupancy, agree at the FP64 bar."""
+    import torch
+
+    g = CASES[name]()
+    say(f"[case] {name}: n={g.n} nnz={g.nnz}")
+    B = to_dev(gg.rhs(g.n, 16, 9))
+    for prec in (lg.LG_FP64, lg.LG_MIXED):
+        h4 = gpu_setup(g, col_unroll=4, row_shift=1, max_rhs=16, precision=prec)
+        h6 = gpu_setup(g, col_unroll=6, row_shift=1, max_rhs=16, precision=prec)
+        h0 = gpu_setup(g, row_shift=1, max_rhs=16, precision=prec)
+        s4, s6, s0 = (lg.lg_hierarchy_stats(h) for h in (h4, h6, h0))
+        assert {s["col_unroll"] for s in s4} == {4} and {s["col_unroll"] for s in s6} == {6}
+        assert {s["col_unroll"] for s in s0} == {0}
+        rng = np.random.default_rng(2)
+        for l, s in enumerate(s4):
+            for k in (4, 8, 16, 32):
+                X = to_dev(rng.standard_normal((s["n"], k)))
+                Y4, Y6, Y0 = torch.empty_like(X), torch.empty_like(X), torch.empty_like(X)
+                lg.lg_spmv(h4, l, X, Y4)
+                lg.lg_spmv(h6, l, X, Y6)
+                lg.lg_spmv(h0, l, X, Y0)
+                torch.cuda.synchronize()
+                assert np.array_equal(bits(Y4.cpu().numpy()), bits(Y6.cpu().numpy())), (l, k)
+                assert np.array_equal(bits(Y0.cpu().numpy()), bits(Y6.cpu().numpy())), (l, k)
+        for _ in range(2):  # eager, then the captured graph's replay
+            C4, C6, C0 = lg.lg_cycle(h4, B), lg.lg_cycle(h6, B), lg.lg_cycle(h0, B)
+            assert np.array_equal(bits(C4.cpu().numpy()), bits(C6.cpu().numpy()))
+            assert np.array_equal(bits(C0.cpu().numpy()), bits(C6.cpu().numpy()))
+        X4, i4, st4 = lg.lg_solve(h4, B)
+        X6, i6, st6 = lg.lg_solve(h6, B)
+        assert st4 == lg.LG_OK and st6 == lg.LG_OK
+        b = B.cpu().numpy()
+        for c in (0, 7, 15):
+            x4, x6 = X4.cpu().numpy()[:, c], X6.cpu().numpy()[:, c]
+            bp = b[:, c] - b[:, c].mean()
+            rel = np.linalg.norm(bp - laplacian_apply(g, x4)) / np.linalg.norm(bp)
+            diff = dense_laplacian_norm(g, x4 - x6) / dense_laplacian_norm(g, x6)
+            assert rel <= 1e-8 * 1.001 and abs(i4[c]["iters"] - i6[c]["iters"]) <= 1
+            assert diff <= (1e-6 if prec == lg.LG_FP64 else 1e-5)
