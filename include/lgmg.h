@@ -95,8 +95,8 @@ typedef struct {
                                0, 1, 2: every level's row products use 2^(class - row_shift)
                                lanes and the autotuner is not run.  The shift fixes the
                                summation order inside a row, so a solve is bit-reproducible
-                               given the shifts in lg_level_stats, and a tuned run can differ
-                               from another process's in the last bits */
+                               given the shifts in lg_level_stats (and col_unroll), and a tuned
+                               run can differ from another process's in the last bits */
   int32_t reorder;          /* 1: after setup, aggregation levels (and an elimination level 0
                                when max_rhs >= 4) of at least 2^14 vertices whose largest
                                degree is at least 8x their mean, and whose mean degree is at
