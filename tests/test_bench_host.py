@@ -61,3 +61,15 @@ def test_cpu_baseline_times_setup_and_solves_apart():
     # a solve longer than the sample cap is timed for that many iterations and scaled
     part = bench.cpu_baseline(g, B, k=2, iters=40, max_sample_iters=5)
     assert "5 CG iterations" in part["sample"] and part["iters"] == 40
+
+
+def test_roofline_kernels_are_matched_at_every_unroll():
+    """rocprofv3 names a column-split kernel with its unroll argument; the
+    roofline kernel counts its instances at every unroll together."""
+    col = "void lg::k_rows_col<lg::LapColOp<double, 16, 1, 0>, 4>(lg::LapColOp<double, 16, 1, 0>, int const*)"
+    assert bench._kernel_of(col) == "k_rows_col<lg::LapColOp<double, 16, 1, 0> >"
+    assert bench._kernel_of(col.replace(", 4>(", ", 6>(")) == bench._kernel_of(col)
+    one = "void lg::k_rows<lg::LapOp<double, 1, 1, 0> >(lg::LapOp<double, 1, 1, 0>, int const*)"
+    assert bench._kernel_of(one) == "k_rows<lg::LapOp<double, 1, 1, 0> >"
+    names = {w["kernel"] for w in bench.WORKLOADS.values()}
+    assert all(not bench._UNROLL_ARG.match(n) for n in names)
