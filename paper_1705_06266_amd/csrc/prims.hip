@@ -20,12 +20,14 @@ const char* last_error_cstr() { return g_last_error.c_str(); }
 [[noreturn]] void fail(lg_status code, const std::string& msg) { throw Error{code, msg}; }
 
 // ------------------------------------------------------------------ arena
-// Device chunks of released arenas are kept, up to kChunkCacheBytes per
-// process, and handed to later arenas on the same device: hipMalloc and
-// hipFree of tens of megabytes cost tens to hundreds of microseconds each,
-// which a setup that follows a release (a serving loop, a benchmark) would
-// otherwise pay every time.  A cached chunk serves a request of at least 4/5
-// of its size.
+// Device chunks of released arenas are kept, up to chunk_cache_cap() bytes
+// per process (a sixteenth of the device's memory, at least 4 GB), and
+// handed to later arenas on the same device: hipMalloc and hipFree of tens of
+// megabytes cost tens to hundreds of microseconds each, which a setup that
+// follows a release (a serving loop, a benchmark) would otherwise pay every
+// time.  A cached chunk serves a request of at least 4/5 of its size.  When
+// hipMalloc fails, the device's cached chunks are freed and it is tried once
+// more.
 namespace {
 struct CachedChunk {
   char* p;
@@ -35,7 +37,37 @@ struct CachedChunk {
 std::mutex g_chunk_mu;
 std::vector<CachedChunk> g_chunk_cache;
 size_t g_chunk_cache_bytes = 0;
-constexpr size_t kChunkCacheBytes = (size_t)4 << 30;
+
+size_t chunk_cache_cap() {
+  static std::atomic<size_t> cap{0};  // threads that race compute the same value
+  size_t v = cap.load(std::memory_order_relaxed);
+  if (v == 0) {
+    int dev = 0;
+    size_t total = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceTotalMem(&total, dev) != hipSuccess) total = 0;
+    v = std::max((size_t)4 << 30, total / 16);
+    cap.store(v, std::memory_order_relaxed);
+  }
+  return v;
+}
+
+// Frees the cached chunks of device dev (no queued work uses them: a chunk
+// enters the cache after a device synchronisation); false if there were none.
+bool chunk_flush(int dev) {
+  std::lock_guard<std::mutex> g(g_chunk_mu);
+  bool any = false;
+  for (size_t k = 0; k < g_chunk_cache.size();) {
+    if (g_chunk_cache[k].dev == dev) {
+      (void)hipFree(g_chunk_cache[k].p);
+      g_chunk_cache_bytes -= g_chunk_cache[k].size;
+      g_chunk_cache.erase(g_chunk_cache.begin() + k);
+      any = true;
+    } else {
+      k++;
+    }
+  }
+  return any;
+}
 
 char* chunk_take(size_t want, int dev, size_t* got) {
   std::lock_guard<std::mutex> g(g_chunk_mu);
@@ -78,6 +110,10 @@ void* Arena::alloc(size_t bytes) {
     hipError_t e = hipMalloc((void**)&p, sz);
     if (e != hipSuccess) {
       (void)hipGetLastError();
+      if (chunk_flush(dev)) e = hipMalloc((void**)&p, sz);
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
       fail(LG_E_NOMEM, "device allocation of " + std::to_string(sz) + " bytes failed");
     }
   }
@@ -99,7 +135,7 @@ void Arena::release() {
     bool keep = false;
     if (c.dev == dev) {
       std::lock_guard<std::mutex> g(g_chunk_mu);
-      keep = g_chunk_cache_bytes + c.size <= kChunkCacheBytes;
+      keep = g_chunk_cache_bytes + c.size <= chunk_cache_cap();
       if (keep) g_chunk_cache_bytes += c.size;  // reserved; the chunk is added below
     }
     if (!keep) {
