@@ -108,8 +108,8 @@ typedef struct {
                                the setup's numbering.  0: the setup's numbering throughout */
   int32_t col_unroll;       /* column-split products (k columns of at least 32 bytes per row):
                                entries each lane group loads per trip, 4 or 6 on every level's
-                               Laplacian products; 0 (default): by kernel, 4 for fp64 products
-                               of at most 16 columns and 6 for the others.  A row's entries
+                               Laplacian products; 0 (default): by width, 4 for products of
+                               at most 16 columns and 6 for 32.  A row's entries
                                are added in the same order at either value, so products and
                                cycles keep their bits; the CG product's fused p . q sums per
                                workgroup, and the workgroup count follows the kernel's
@@ -128,7 +128,7 @@ typedef struct {
   int32_t lane_shift, col_shift; /* row lanes 2^(class - shift) in use (set by the autotuner) */
   int32_t merge;                 /* 1: one-column products use the merge-path traversal */
   int32_t reordered;             /* 1: stored in the solve-time vertex order (reorder option) */
-  int32_t col_unroll;            /* col_unroll in use on the level's Laplacian products (0: by kernel) */
+  int32_t col_unroll;            /* col_unroll in use on the level's Laplacian products (0: by width) */
 } lg_level_stats;
 
 typedef struct {

@@ -190,13 +190,13 @@ constexpr int kClasses = 8;
 constexpr int kPartialBytes = 512;
 // Entries each lane group of a column-split row kernel loads per trip (all
 // issued together), 4 or 6.  Fewer in flight per wavefront take fewer
-// registers and allow more wavefronts.  Measured in whole solves, fp64
-// products of at most 16 columns (8 lanes per entry or fewer) ran faster at 4,
-// the others at 6, so a schedule's unroll of 0 takes that rule; a group adds
-// its entries in the same order at either value.
+// registers and allow more wavefronts.  Measured in whole solves, products of
+// at most 16 columns (fp64 and fp32) ran faster at 4 and those of 32 columns
+// at 6, so a schedule's unroll of 0 takes that rule; a group adds its entries
+// in the same order at either value.
 template <class Op>
 constexpr int col_unroll_of() {
-  return Op::V == 2 && Op::kL <= 8 ? 4 : 6;
+  return Op::kL * Op::V <= 16 ? 4 : 6;
 }
 constexpr int kSplitDeg = LG_SPLIT_DEG;  // rows above this are split into kHubChunk-entry chunks
 

@@ -553,8 +553,8 @@ def test_hub_rows_timed_apart_give_the_same_bits(built, name):
                                   "rmat_s12"])
 def test_unroll_keeps_every_row_sum(built, name):
     """The column-split products load 4 or 6 entries per lane group and trip
-    (col_unroll; by default 4 for fp64 products of at most 16 columns, 6 for
-    the others); a group adds its entries in the same order at either value
+    (col_unroll; by default 4 for products of at most 16 columns, 6 for 32);
+    a group adds its entries in the same order at either value
     and the padding slots add +-0 to sums that start at +0.  So every level's
     product and a V-cycle (fp64 and mixed) are bit-identical at 4, 6 and the
     default, and solves, whose fused p . q sums over a workgroup count that
